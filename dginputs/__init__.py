@@ -1,0 +1,312 @@
+"""Seeded synthetic inputs for the tetrahedral DG wave solver.
+
+This module is shared by the FP64 oracle and the GPU product path.  It holds
+none of the discontinuous Galerkin arithmetic: only the synthetic workload
+(Kuhn-split box meshes with optional vertex jitter, per-element material
+coefficients, analytic initial-data functions of the physical coordinates and
+a time-step recipe from raw vertex geometry), so that both sides are fed the
+same inputs.
+
+Mesh format (the product's set-up call takes the same arrays):
+
+* ``elem_xyz``  float64 [K, 4, 3]  vertex coordinates of every tetrahedron
+  (positively oriented: det[x2-x1, x3-x1, x4-x1] > 0);
+* ``elem_topo`` int64   [K, 4]     topological vertex ids; two elements share
+  a face iff they share the three ids of that face (periodic boxes identify
+  opposite vertices through these ids, while ``elem_xyz`` keeps the unwrapped
+  coordinates);
+* ``period``    float64 [3] or None, the box lengths of a periodic mesh.
+
+Faces that have no partner are boundary faces (reflecting walls).
+"""
+
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# Meshes
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class TetMesh:
+    elem_xyz: np.ndarray
+    elem_topo: np.ndarray
+    period: np.ndarray | None
+    dims: tuple
+    lengths: tuple
+
+    @property
+    def K(self) -> int:
+        return int(self.elem_xyz.shape[0])
+
+
+_PERMS = list(itertools.permutations(range(3)))
+
+
+def kuhn_box(
+    nx: int,
+    ny: int | None = None,
+    nz: int | None = None,
+    lengths=(1.0, 1.0, 1.0),
+    jitter: float = 0.0,
+    seed: int = 0,
+    periodic: bool = False,
+) -> TetMesh:
+    """Box of nx*ny*nz subcubes, each split into 6 Kuhn tetrahedra.
+
+    Each subcube is cut along its (0,0,0)-(1,1,1) diagonal into the six
+    tetrahedra v0 -> v0+e_a -> v0+e_a+e_b -> v0+e_a+e_b+e_c, one per
+    permutation (a, b, c) of the axes; the split is conforming across subcubes
+    and compatible with periodic identification.  Elements are ordered
+    subcube by subcube (x fastest), six consecutive elements per subcube.
+
+    ``jitter`` moves vertices by U[-jitter*h, jitter*h] per coordinate (h the
+    subcube edge along that axis): interior vertices only for a wall-bounded
+    box, every vertex (consistently through its topological id) for a periodic
+    one.  The draw is repeated with the next seed offset until every element
+    is positively oriented.
+    """
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    L = np.asarray(lengths, dtype=float)
+    h = L / np.array([nx, ny, nz], dtype=float)
+    gi, gj, gk = np.meshgrid(
+        np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij"
+    )
+    grid = np.stack([gi, gj, gk], axis=-1).reshape(-1, 3)  # index order x slowest here
+
+    K = 6 * nx * ny * nz
+    ck, cj, ci = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cell = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=-1)  # x fastest
+    corners = np.zeros((cell.shape[0], 6, 4, 3), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        path = [cell.copy()]
+        c = cell.copy()
+        for ax in perm:
+            c = c.copy()
+            c[:, ax] += 1
+            path.append(c)
+        if np.linalg.det(np.eye(3)[list(perm)]) < 0:  # odd permutation
+            path[2], path[3] = path[3], path[2]
+        corners[:, p] = np.stack(path, axis=1)
+    corners = corners.reshape(K, 4, 3)
+    topo = _vectorised_ids(corners, nx, ny, nz, periodic)
+
+    base = corners.astype(float) * h  # unwrapped coordinates
+    attempt = 0
+    while True:
+        xyz = base.copy()
+        if jitter > 0.0:
+            rng = np.random.Generator(np.random.PCG64(seed + 7919 * attempt))
+            if periodic:
+                nv = nx * ny * nz
+                d = rng.uniform(-jitter, jitter, size=(nv, 3)) * h
+                xyz += d[topo]
+            else:
+                nv = (nx + 1) * (ny + 1) * (nz + 1)
+                d = rng.uniform(-jitter, jitter, size=(nv, 3)) * h
+                interior = (
+                    (grid[:, 0] > 0) & (grid[:, 0] < nx)
+                    & (grid[:, 1] > 0) & (grid[:, 1] < ny)
+                    & (grid[:, 2] > 0) & (grid[:, 2] < nz)
+                )
+                d[~interior] = 0.0
+                gid = (corners[..., 0] * (ny + 1) + corners[..., 1]) * (nz + 1) + corners[..., 2]
+                xyz += d[gid]
+        dets = np.linalg.det(
+            np.stack([xyz[:, 1] - xyz[:, 0], xyz[:, 2] - xyz[:, 0], xyz[:, 3] - xyz[:, 0]], axis=-1)
+        )
+        if np.all(dets > 0.0):
+            break
+        attempt += 1
+        if attempt > 50:
+            raise RuntimeError("could not draw a valid jittered mesh")
+    period = L.copy() if periodic else None
+    return TetMesh(
+        elem_xyz=np.ascontiguousarray(xyz),
+        elem_topo=np.ascontiguousarray(topo),
+        period=period,
+        dims=(nx, ny, nz),
+        lengths=tuple(float(x) for x in L),
+    )
+
+
+def _vectorised_ids(corners, nx, ny, nz, periodic):
+    i, j, k = corners[..., 0], corners[..., 1], corners[..., 2]
+    if periodic:
+        return ((i % nx) * ny + (j % ny)) * nz + (k % nz)
+    return (i * (ny + 1) + j) * (nz + 1) + k
+
+
+def element_centroids(mesh: TetMesh) -> np.ndarray:
+    return mesh.elem_xyz.mean(axis=1)
+
+
+def inradius(mesh: TetMesh) -> np.ndarray:
+    """Inradius 3V / (sum of face areas) of every element, from its vertices."""
+    x = mesh.elem_xyz
+    vol = np.abs(
+        np.linalg.det(np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]], -1))
+    ) / 6.0
+    area = np.zeros(len(x))
+    for a, b, c in ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)):
+        area += 0.5 * np.linalg.norm(np.cross(x[:, b] - x[:, a], x[:, c] - x[:, a]), axis=1)
+    return 3.0 * vol / area
+
+
+# ----------------------------------------------------------------------------
+# Material coefficients
+# ----------------------------------------------------------------------------
+
+
+def acoustic_constant(mesh: TetMesh, rho: float = 1.0, c: float = 1.0) -> np.ndarray:
+    """[K, 2] (rho, c) constant over the mesh."""
+    out = np.empty((mesh.K, 2))
+    out[:, 0] = rho
+    out[:, 1] = c
+    return out
+
+
+def acoustic_two_layer(mesh: TetMesh, z_split: float = 0.5) -> np.ndarray:
+    """[K, 2] (rho, c): (1, 1) below the plane z = z_split, (2, 1.5) above,
+    chosen by element centroid."""
+    zc = element_centroids(mesh)[:, 2]
+    out = np.empty((mesh.K, 2))
+    low = zc < z_split
+    out[low] = (1.0, 1.0)
+    out[~low] = (2.0, 1.5)
+    return out
+
+
+def acoustic_loguniform(mesh: TetMesh, seed: int, lo: float = 0.5, hi: float = 2.0) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size=(mesh.K, 2)))
+
+
+def elastic_constant(mesh: TetMesh, rho=1.0, lam=1.0, mu=1.0) -> np.ndarray:
+    out = np.empty((mesh.K, 3))
+    out[:] = (rho, lam, mu)
+    return out
+
+
+def elastic_loguniform(mesh: TetMesh, seed: int, lo: float = 0.5, hi: float = 2.0) -> np.ndarray:
+    """[K, 3] (rho, lambda, mu), each exp(U[ln lo, ln hi]) independently."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size=(mesh.K, 3)))
+
+
+def max_wave_speed(coef: np.ndarray, physics: str) -> float:
+    if physics == "acoustic":
+        return float(np.max(coef[:, 1]))
+    rho, lam, mu = coef[:, 0], coef[:, 1], coef[:, 2]
+    return float(np.max(np.sqrt((lam + 2.0 * mu) / rho)))
+
+
+# ----------------------------------------------------------------------------
+# Initial data (analytic functions of the physical coordinates)
+# ----------------------------------------------------------------------------
+
+ACOUSTIC_FIELDS = ("p", "u", "v", "w")
+ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "syz", "sxz", "sxy")
+
+
+def gaussian(x: np.ndarray, center=(0.5, 0.5, 0.5), sigma: float = 0.1) -> np.ndarray:
+    d = x - np.asarray(center, dtype=float)
+    return np.exp(-np.sum(d * d, axis=-1) / (2.0 * sigma * sigma))
+
+
+def acoustic_gaussian(x: np.ndarray, center=(0.5, 0.5, 0.5), sigma=0.1) -> np.ndarray:
+    """Fields [4, ...]: p = Gaussian pulse, v = 0.  x has shape [..., 3]."""
+    out = np.zeros((4,) + x.shape[:-1])
+    out[0] = gaussian(x, center, sigma)
+    return out
+
+
+def elastic_gaussian(x: np.ndarray, center=(0.5, 0.5, 0.5), sigma=0.1) -> np.ndarray:
+    """Fields [9, ...]: v = Gaussian * (1,1,1)/sqrt(3), sigma = 0."""
+    out = np.zeros((9,) + x.shape[:-1])
+    g = gaussian(x, center, sigma) / math.sqrt(3.0)
+    out[0] = out[1] = out[2] = g
+    return out
+
+
+def acoustic_plane_wave(x, m, rho=1.0, c=1.0, t=0.0) -> np.ndarray:
+    """Travelling acoustic plane wave p = cos(2 pi m.x - omega t), omega =
+    2 pi |m| c, v = mhat p / (rho c): an exact solution of the pressure-velocity
+    system in a homogeneous medium (periodic for integer m on a unit box)."""
+    m = np.asarray(m, dtype=float)
+    km = np.linalg.norm(m)
+    mh = m / km
+    ph = 2.0 * math.pi * (x @ m) - 2.0 * math.pi * km * c * t
+    f = np.cos(ph)
+    out = np.zeros((4,) + x.shape[:-1])
+    out[0] = f
+    for i in range(3):
+        out[1 + i] = mh[i] * f / (rho * c)
+    return out
+
+
+def _sym_to_voigt(S):
+    """Symmetric 3x3 (leading dims) -> (xx, yy, zz, yz, xz, xy)."""
+    return np.stack([S[0, 0], S[1, 1], S[2, 2], S[1, 2], S[0, 2], S[0, 1]])
+
+
+def elastic_plane_wave(x, m, kind="P", rho=1.0, lam=1.0, mu=1.0, t=0.0, d=None) -> np.ndarray:
+    """Elastic plane waves in a homogeneous isotropic medium.
+
+    P: v = mhat f, sigma = -(lam I + 2 mu mhat mhat^T) f / c_p;
+    S: v = d f (d unit, d . mhat = 0), sigma = -(mu/c_s)(mhat d^T + d mhat^T) f;
+    f = cos(2 pi m.x - omega t) with omega = 2 pi |m| c_p (resp. c_s).
+    """
+    m = np.asarray(m, dtype=float)
+    km = np.linalg.norm(m)
+    mh = m / km
+    cp = math.sqrt((lam + 2.0 * mu) / rho)
+    cs = math.sqrt(mu / rho)
+    out = np.zeros((9,) + x.shape[:-1])
+    if kind == "P":
+        f = np.cos(2.0 * math.pi * (x @ m) - 2.0 * math.pi * km * cp * t)
+        for i in range(3):
+            out[i] = mh[i] * f
+        S = -(lam * np.eye(3) + 2.0 * mu * np.outer(mh, mh)) / cp
+    else:
+        if d is None:
+            trial = np.array([1.0, 0.0, 0.0]) if abs(mh[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+            d = trial - (trial @ mh) * mh
+        d = np.asarray(d, float)
+        d = d / np.linalg.norm(d)
+        f = np.cos(2.0 * math.pi * (x @ m) - 2.0 * math.pi * km * cs * t)
+        for i in range(3):
+            out[i] = d[i] * f
+        S = -(mu / cs) * (np.outer(mh, d) + np.outer(d, mh))
+    V = _sym_to_voigt(S)
+    for a in range(6):
+        out[3 + a] = V[a] * f
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Time step recipe and the paper-scale workloads
+# ----------------------------------------------------------------------------
+
+CFL_DEFAULT = 0.5
+
+
+def time_step(mesh: TetMesh, N: int, cmax: float, cfl: float = CFL_DEFAULT) -> float:
+    """dt = cfl * min inradius / (cmax * (N+1)^2), from raw vertex geometry."""
+    return float(cfl * inradius(mesh).min() / (cmax * (N + 1) ** 2))
+
+
+def n_nodes(N: int) -> int:
+    return (N + 1) * (N + 2) * (N + 3) // 6
+
+
+def paper_scale_n(N: int, target_nodes: float = 2.0e6) -> int:
+    """Subcubes per edge so that 6 n^3 N_p is closest to ~2M nodes."""
+    return int(round((target_nodes / (6.0 * n_nodes(N))) ** (1.0 / 3.0)))

@@ -1,0 +1,335 @@
+"""Right-hand sides, Adams-Bashforth update and energy (FP64 oracle).
+
+Test infrastructure only.  Everything is the plain definition, vectorised over
+elements with NumPy; no blocking, fusion or reordering beyond the formulas.
+
+Acoustic system (Sec. 2.1; eqs. (5)-(6)), fields (p, v1, v2, v3):
+  r^p   = -rho c^2 sum_j D_j [sum_i g_ij v_i] - L (Fscale p_p)
+  r^v_i = -(1/rho) sum_j g_ij D_j p            - L (Fscale p_v n_i)
+  p_p = -(rho c^2)^- k_c alpha,  p_v = c^- k_c alpha,
+  alpha = [[p]] - (rho c)^+ [[v_n]],  k_c = 1/{rho c},
+  [[p]] = (p^+ - p^-)/2,  [[v_n]] = (v^+ - v^-).n/2,  {a} = (a^- + a^+)/2.
+
+Isotropic elastic system (Sec. 2.1 and the elastic right-hand side of
+Sec. 3.2), fields (v1, v2, v3, s11, s22, s33, s23, s13, s12):
+  r^v_i    = (1/rho) sum_n D_n [sum_m g_mn s_im] + L (Fscale p_v)_i
+  r^s_ij   = delta_ij lambda div v + mu (d v_i/d x_j + d v_j/d x_i)
+             + L (Fscale P_s)_ij
+  The paper prints the mu term with garbled indices; the reading used is
+  mu sum_n (g_jn D_n v_i + g_in D_n v_j), i.e. 2 mu sym(grad v) as in the PDE.
+  P_s = k_p a_p lambda^- I + 2 (k_p a_p - k_s a_s) mu^- n n^T
+        + k_s mu^- (n a_s^T + a_s n^T)
+  p_v = (k_p a_p c_p^- - k_s a_s c_s^-) n + k_s c_s^- a_s(vector),
+  a_p = [[s_nn]] + (rho c_p)^+ [[v_n]],  a_s = [[s_nn]] + (rho c_s)^+ [[v_n]],
+  a_s(vector) = [[s n]] + (rho c_s)^+ [[v]],  k_p = 1/{rho c_p},
+  k_s = 1/{rho c_s}, jumps halved as above, n the outward normal of the
+  element ("-" side).
+
+Walls (unpaired faces; the paper is silent): mirror ghost state with the
+element's own coefficients -- acoustic p^+ = p^-, v_n^+ = -v_n^- (rigid wall);
+elastic v^+ = v^-, (s n)^+ = -(s n)^- (traction-free).
+
+Time stepping (eq. (4)): q^{m+1} = q^m + dt (a1 r^m + a2 r^{m-1} + a3 r^{m-2}),
+a = (23, -16, 5)/12.  The paper is silent on the start: step 0 uses forward
+Euler, step 1 the two-step formula (3/2, -1/2), unless the history is given.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .mesh import MeshGeometry
+
+# Voigt order of the stress components and the full-tensor lookup
+VOIGT = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+TENSOR_INDEX = np.array([[0, 5, 4], [5, 1, 3], [4, 3, 2]])
+
+
+def ab3_coefficients(m: int):
+    """Adams-Bashforth weights for step m with the start-up reading."""
+    if m == 0:
+        return (1.0, 0.0, 0.0)
+    if m == 1:
+        return (1.5, -0.5, 0.0)
+    return (23.0 / 12.0, -16.0 / 12.0, 5.0 / 12.0)
+
+
+class _Base:
+    nfields = 0
+
+    def __init__(self, mesh: MeshGeometry, coef: np.ndarray):
+        self.mesh = mesh
+        self.ref = mesh.ref
+        self.coef = np.asarray(coef, dtype=float)
+        if self.coef.shape != (mesh.K, self.ncoef):
+            raise ValueError("coefficient array has the wrong shape")
+        self.K = mesh.K
+        # neighbour lookups for every face node (walls point to themselves)
+        K, Nfp = mesh.K, self.ref.Nfp
+        kk = np.repeat(np.arange(K)[:, None], 4, axis=1)
+        ff = np.repeat(np.arange(4)[None, :], K, axis=0)
+        self.nb_elem = np.where(mesh.wall, kk, mesh.EToE)
+        nb_face = np.where(mesh.wall, ff, mesh.EToF)
+        nb_node = np.where(mesh.wall[..., None], np.arange(Nfp)[None, None, :], mesh.nbr_node)
+        # volume node index on the neighbour for each own face node
+        self.nb_vol = self.ref.Fmask[nb_face[..., None], nb_node]  # (K, 4, Nfp)
+        self.nb_el3 = np.broadcast_to(self.nb_elem[..., None], (K, 4, Nfp))
+
+    # helpers ---------------------------------------------------------------
+    def ref_derivs(self, u: np.ndarray) -> np.ndarray:
+        """u (..., Np) -> (..., 3, Np) with [..., j, :] = D_j u."""
+        return np.stack([u @ self.ref.D[j].T for j in range(3)], axis=-2)
+
+    def lift(self, flux: np.ndarray) -> np.ndarray:
+        """flux (K, ..., 4, Nfp) -> (K, ..., Np) = LIFT @ flux."""
+        sh = flux.shape
+        return flux.reshape(sh[:-2] + (4 * sh[-1],)) @ self.ref.LIFT.T
+
+    def own_face(self, u: np.ndarray) -> np.ndarray:
+        """u (K, Np) -> (K, 4, Nfp)."""
+        return u[:, self.ref.Fmask]
+
+    def nbr_face(self, u: np.ndarray) -> np.ndarray:
+        """u (K, Np) -> neighbour values at each own face node (K, 4, Nfp)."""
+        return u[self.nb_el3, self.nb_vol]
+
+    def mass_norm2(self, u: np.ndarray) -> np.ndarray:
+        """Per element J_k u^T M u for u (K, Np)."""
+        return self.mesh.J * np.einsum("kn,nm,km->k", u, self.ref.M, u)
+
+    def rel_l2(self, q: np.ndarray, q_ref: np.ndarray):
+        """Mass-weighted relative L2 error (overall, per field) of q vs q_ref."""
+        e = q - q_ref
+        num = np.array([self.mass_norm2(e[:, c]).sum() for c in range(self.nfields)])
+        den = np.array([self.mass_norm2(q_ref[:, c]).sum() for c in range(self.nfields)])
+        overall = float(np.sqrt(num.sum() / den.sum()))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            per = np.sqrt(num / np.where(den > 0, den, np.nan))
+        return overall, per
+
+
+class AcousticOracle(_Base):
+    nfields = 4
+    ncoef = 2  # (rho, c)
+
+    def __init__(self, mesh, coef):
+        super().__init__(mesh, coef)
+        rho, c = self.coef[:, 0], self.coef[:, 1]
+        self.rho, self.c = rho, c
+        self.Z = rho * c
+        self.Znb = np.where(self.mesh.wall, self.Z[:, None], self.Z[self.nb_elem])
+
+    def rhs(self, q: np.ndarray) -> np.ndarray:
+        mesh = self.mesh
+        G = mesh.G
+        p, v = q[:, 0], q[:, 1:4]
+        rho, c = self.rho, self.c
+        # volume terms
+        Dp = self.ref_derivs(p)  # (K, 3, Np)
+        grad_p = np.einsum("kij,kjn->kin", G, Dp)
+        Dv = self.ref_derivs(v)  # (K, 3(i), 3(j), Np)
+        div_v = np.einsum("kij,kijn->kn", G, Dv)
+        r = np.empty_like(q)
+        r[:, 0] = -(rho * c * c)[:, None] * div_v
+        r[:, 1:4] = -(1.0 / rho)[:, None, None] * grad_p
+        # surface terms
+        n = mesh.normals  # (K, 4, 3)
+        pM = self.own_face(p)
+        vnM = np.einsum("kfi,kifj->kfj", n, v[:, :, mesh.ref.Fmask])
+        pP = self.nbr_face(p)
+        vP = np.stack([self.nbr_face(v[:, i]) for i in range(3)], axis=1)
+        vnP = np.einsum("kfi,kifj->kfj", n, vP)
+        wall = mesh.wall[..., None]
+        pP = np.where(wall, pM, pP)
+        vnP = np.where(wall, -vnM, vnP)
+        Zm = self.Z[:, None, None]
+        Zp = self.Znb[..., None]
+        jp = 0.5 * (pP - pM)
+        jv = 0.5 * (vnP - vnM)
+        kc = 2.0 / (Zm + Zp)
+        alpha = jp - Zp * jv
+        Fs = mesh.Fscale[..., None]
+        flux_p = Fs * (rho * c * c)[:, None, None] * kc * alpha
+        r[:, 0] += self.lift(flux_p)
+        base = -Fs * c[:, None, None] * kc * alpha  # (K, 4, Nfp)
+        for i in range(3):
+            r[:, 1 + i] += self.lift(base * n[:, :, i][..., None])
+        return r
+
+    def energy_density(self, q: np.ndarray) -> np.ndarray:
+        """Per element 1/2 J_k (p^T M p/(rho c^2) + rho sum v_i^T M v_i)."""
+        e = self.mass_norm2(q[:, 0]) / (self.rho * self.c**2)
+        for i in range(3):
+            e = e + self.rho * self.mass_norm2(q[:, 1 + i])
+        return 0.5 * e
+
+    def energy(self, q: np.ndarray) -> float:
+        return float(self.energy_density(q).sum())
+
+    def energy_rate(self, q: np.ndarray) -> float:
+        """dE/dt = sum_k J_k (p^T M r_p/(rho c^2) + rho sum v_i^T M r_vi)."""
+        r = self.rhs(q)
+        M, J = self.ref.M, self.mesh.J
+        w = np.concatenate([(1.0 / (self.rho * self.c**2))[:, None], np.repeat(self.rho[:, None], 3, 1)], 1)
+        return float(np.einsum("k,kc,kcn,nm,kcm->", J, w, q, M, r))
+
+
+class ElasticOracle(_Base):
+    nfields = 9
+    ncoef = 3  # (rho, lambda, mu)
+
+    def __init__(self, mesh, coef):
+        super().__init__(mesh, coef)
+        rho, lam, mu = self.coef[:, 0], self.coef[:, 1], self.coef[:, 2]
+        if np.any(mu <= 0.0):
+            raise ValueError("the elastic flux needs mu > 0")
+        self.rho, self.lam, self.mu = rho, lam, mu
+        self.cp = np.sqrt((lam + 2.0 * mu) / rho)
+        self.cs = np.sqrt(mu / rho)
+        self.Zp = rho * self.cp
+        self.Zs = rho * self.cs
+        w = self.mesh.wall
+        self.Zp_nb = np.where(w, self.Zp[:, None], self.Zp[self.nb_elem])
+        self.Zs_nb = np.where(w, self.Zs[:, None], self.Zs[self.nb_elem])
+
+    @staticmethod
+    def tensor(s: np.ndarray) -> np.ndarray:
+        """Voigt (K, 6, ...) -> full (K, 3, 3, ...)."""
+        return s[:, TENSOR_INDEX]
+
+    def rhs(self, q: np.ndarray) -> np.ndarray:
+        mesh = self.mesh
+        G = mesh.G
+        v = q[:, 0:3]
+        S = self.tensor(q[:, 3:9])  # (K, 3, 3, Np)
+        rho, lam, mu = self.rho, self.lam, self.mu
+        # volume terms
+        Dv = self.ref_derivs(v)  # (K, 3 i, 3 l, Np): D_l v_i
+        grad_v = np.einsum("kjl,kiln->kijn", G, Dv)  # d v_i / d x_j
+        div_v = np.einsum("kiin->kn", grad_v)
+        DS = self.ref_derivs(q[:, 3:9])  # (K, 6, 3 l, Np)
+        DS = DS[:, TENSOR_INDEX]  # (K, 3 i, 3 j, 3 l, Np)
+        div_s = np.einsum("kjl,kijln->kin", G, DS, optimize=True)  # sum_j d s_ij / d x_j
+        r = np.empty_like(q)
+        r[:, 0:3] = (1.0 / rho)[:, None, None] * div_s
+        for a, (i, j) in enumerate(VOIGT):
+            val = mu[:, None] * (grad_v[:, i, j] + grad_v[:, j, i])
+            if i == j:
+                val = val + lam[:, None] * div_v
+            r[:, 3 + a] = val
+        # surface terms
+        n = mesh.normals  # (K, 4, 3)
+        Fm = mesh.ref.Fmask
+        vM = v[:, :, Fm]  # (K, 3, 4, Nfp)
+        SM = S[:, :, :, Fm]  # (K, 3, 3, 4, Nfp)
+        vP = np.stack([self.nbr_face(v[:, i]) for i in range(3)], axis=1)
+        sP = np.stack([self.nbr_face(q[:, 3 + a]) for a in range(6)], axis=1)
+        SP = self.tensor(sP)
+        tM = np.einsum("kijfx,kfj->kifx", SM, n)  # (s^- n)_i
+        tP = np.einsum("kijfx,kfj->kifx", SP, n)  # (s^+ n)_i, own normal
+        wall = mesh.wall[None, :, :, None].transpose(1, 0, 2, 3)  # (K,1,4,1)
+        vP = np.where(wall, vM, vP)
+        tP = np.where(wall, -tM, tP)
+        jv = 0.5 * (vP - vM)  # (K, 3, 4, Nfp)
+        jt = 0.5 * (tP - tM)
+        jvn = np.einsum("kifx,kfi->kfx", jv, n)
+        jsnn = np.einsum("kifx,kfi->kfx", jt, n)
+        Zpm, Zsm = self.Zp[:, None, None], self.Zs[:, None, None]
+        Zpp, Zsp = self.Zp_nb[..., None], self.Zs_nb[..., None]
+        kp = 2.0 / (Zpm + Zpp)
+        ks = 2.0 / (Zsm + Zsp)
+        ap = jsnn + Zpp * jvn
+        as_ = jsnn + Zsp * jvn
+        asv = jt + Zsp[:, None] * jv  # (K, 3, 4, Nfp)
+        lam3, mu3 = lam[:, None, None], mu[:, None, None]
+        cp3, cs3 = self.cp[:, None, None], self.cs[:, None, None]
+        Fs = mesh.Fscale[..., None]
+        nn = n.transpose(0, 2, 1)[..., None]  # (K, 3, 4, 1)
+        # velocity penalty
+        pv = (kp * ap * cp3 - ks * as_ * cs3)[:, None] * nn + (ks * cs3)[:, None] * asv
+        r[:, 0:3] += self.lift(Fs[:, None] * pv)
+        # stress penalty
+        A = kp * ap * lam3
+        B = 2.0 * (kp * ap - ks * as_) * mu3
+        C = ks * mu3
+        for a, (i, j) in enumerate(VOIGT):
+            Ps = B * nn[:, i] * nn[:, j] + C * (nn[:, i] * asv[:, j] + asv[:, i] * nn[:, j])
+            if i == j:
+                Ps = Ps + A
+            r[:, 3 + a] += self.lift(Fs * Ps)
+        return r
+
+    def energy_density(self, q: np.ndarray) -> np.ndarray:
+        """Per element 1/2 J_k [rho |v|^2 + (1/(2mu))(s:s - lam/(3lam+2mu) tr(s)^2)]
+        integrated with the mass matrix (off-diagonal stresses count twice)."""
+        rho, lam, mu = self.rho, self.lam, self.mu
+        e = np.zeros(self.K)
+        for i in range(3):
+            e += rho * self.mass_norm2(q[:, i])
+        ss = np.zeros(self.K)
+        for a, (i, j) in enumerate(VOIGT):
+            ss += (1.0 if i == j else 2.0) * self.mass_norm2(q[:, 3 + a])
+        tr = q[:, 3] + q[:, 4] + q[:, 5]
+        e += (ss - lam / (3.0 * lam + 2.0 * mu) * self.mass_norm2(tr)) / (2.0 * mu)
+        return 0.5 * e
+
+    def energy(self, q: np.ndarray) -> float:
+        return float(self.energy_density(q).sum())
+
+    def energy_rate(self, q: np.ndarray) -> float:
+        """Semi-discrete dE/dt = <q, r>_E (the energy inner product of q and r)."""
+        r = self.rhs(q)
+        rho, lam, mu = self.rho, self.lam, self.mu
+        J, M = self.mesh.J, self.ref.M
+
+        def ip(a, b):
+            return J * np.einsum("kn,nm,km->k", a, M, b)
+
+        e = np.zeros(self.K)
+        for i in range(3):
+            e += rho * ip(q[:, i], r[:, i])
+        ss = np.zeros(self.K)
+        for a, (i, j) in enumerate(VOIGT):
+            ss += (1.0 if i == j else 2.0) * ip(q[:, 3 + a], r[:, 3 + a])
+        trq = q[:, 3] + q[:, 4] + q[:, 5]
+        trr = r[:, 3] + r[:, 4] + r[:, 5]
+        e += (ss - lam / (3.0 * lam + 2.0 * mu) * ip(trq, trr)) / (2.0 * mu)
+        return float(e.sum())
+
+
+def make_oracle(physics: str, mesh: MeshGeometry, coef: np.ndarray):
+    if physics == "acoustic":
+        return AcousticOracle(mesh, coef)
+    if physics == "elastic":
+        return ElasticOracle(mesh, coef)
+    raise ValueError(physics)
+
+
+class AB3Stepper:
+    """Third-order Adams-Bashforth time loop (eq. (4)) over an oracle's RHS.
+
+    ``source(m, t)`` optionally returns an additive forcing for r^m.
+    """
+
+    def __init__(self, oracle, q0: np.ndarray, history=None, step_index: int = 0):
+        self.oracle = oracle
+        self.q = np.array(q0, copy=True)
+        if not np.issubdtype(self.q.dtype, np.inexact):
+            self.q = self.q.astype(float)
+        self.r1 = None if history is None else np.array(history[0], dtype=float)
+        self.r2 = None if history is None else np.array(history[1], dtype=float)
+        self.m = step_index
+
+    def step(self, nsteps: int, dt: float):
+        for _ in range(nsteps):
+            r0 = self.oracle.rhs(self.q)
+            a1, a2, a3 = ab3_coefficients(self.m)
+            upd = a1 * r0
+            if a2 != 0.0:
+                upd = upd + a2 * self.r1
+            if a3 != 0.0:
+                upd = upd + a3 * self.r2
+            self.q = self.q + dt * upd
+            self.r2, self.r1 = self.r1, r0
+            self.m += 1
+        return self.q
