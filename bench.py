@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Throughput of the nodal DG wave step on one MI355X.
+
+Default workload (the paper-scale acoustic sweep): for every degree N = 1..8 a
+Kuhn-split unit cube with ~2M nodes (n^3 subcubes x 6 tetrahedra, n chosen so
+that 6 n^3 N_p ~ 2e6), interior vertices jittered by up to 10% of h (seed 0),
+two-layer (rho, c) = (1, 1) / (2, 1.5) by element centroid, Gaussian pressure
+pulse.  One benchmark step = one AB3 step (the fused volume + flux + LIFT +
+update kernel) on each of the eight meshes; value = total node updates / s.
+``--config elastic`` runs the elastic sweep (log-uniform rho, lambda, mu in
+[0.5, 2], seed 1, Gaussian velocity pulse).
+
+Prints one JSON line with the throughput, a roofline object for the kernel
+that takes the largest share of the time (algorithmic bytes and flops per
+element from the model below, divided by its average launch duration from HIP
+events recorded on the launch stream), per-degree details, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import dginputs as di  # noqa: E402
+
+METRIC = "DG node-updates/s and % roofline, acoustic+elastic N=1..8: FP32 vs mixed/batched"
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+FP32_PEAK = 157.3e12  # flop/s, MI355X FP32 vector / matrix
+
+
+def algorithmic_model(physics: str, N: int):
+    """Algorithmic (bytes, flops) per element per step of the fused FP32 step.
+
+    bytes = 4 * [5 NF Np (q read+write, r^{m-1}, r^{m-2} read, r^m write)
+                 + 2 * 4 NT Nfp (neighbour traces read, own traces written)
+                 + 9 (inverse Jacobian) + c (own + neighbour coefficients)
+                 + 4 (packed face connectivity)],  c = 6 acoustic, 11 elastic
+    flops: acoustic 12 Np^2 + 32 Np Nfp + 64 Nfp + 58 Np,
+           elastic  36 Np^2 + 72 Np Nfp + 240 Nfp + 174 Np.
+    """
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    if physics == "acoustic":
+        NF, NT, c = 4, 2, 6
+        flops = 12 * Np * Np + 32 * Np * Nfp + 16 * 4 * Nfp + 24 * Np + 34 * Np
+    else:
+        NF, NT, c = 9, 6, 11
+        flops = 36 * Np * Np + 72 * Np * Nfp + 60 * 4 * Nfp + 54 * Np + 120 * Np
+    nbytes = 4 * (5 * NF * Np + 2 * 4 * NT * Nfp + 9 + c + 4)
+    return nbytes, flops
+
+
+def workload(physics: str, N: int, scale: float = 1.0):
+    n = di.paper_scale_n(N)
+    if scale != 1.0:
+        n = max(2, int(math.ceil(n * scale)))
+    mesh = di.kuhn_box(n, jitter=0.1, seed=0)
+    if physics == "acoustic":
+        coef = di.acoustic_two_layer(mesh)
+    else:
+        coef = di.elastic_loguniform(mesh, 1)
+    coef = coef.astype(np.float32).astype(np.float64)
+    return n, mesh, coef
+
+
+def init_fields(physics, xyz):
+    f = di.acoustic_gaussian(xyz) if physics == "acoustic" else di.elastic_gaussian(xyz)
+    return np.ascontiguousarray(np.moveaxis(f, 0, 1)).astype(np.float32)
+
+
+def run_gpu(physics, degrees, steps, warmup, log):
+    import torch
+
+    from paper_1602_07997_amd import DGSolver
+
+    stream = torch.cuda.current_stream()
+    cases = []
+    for N in degrees:
+        n, mesh, coef = workload(physics, N)
+        s = DGSolver(physics, N, mesh.elem_xyz, mesh.elem_topo, stream=stream)
+        s.set_coefficients(torch.tensor(coef, dtype=torch.float32, device="cuda"))
+        s.set_fields(torch.tensor(init_fields(physics, s.node_coordinates()), device="cuda"))
+        dt = di.time_step(mesh, N, di.max_wave_speed(coef, physics))
+        s.step(2, dt)  # Euler and two-step start-up
+        cases.append({"N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt})
+        log(f"  set up {physics} N={N}: n={n} K={mesh.K} nodes={mesh.K * s.Np}")
+    for c in cases:
+        c["solver"].step(warmup, c["dt"])
+    torch.cuda.synchronize()
+    ev = {c["N"]: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)] for c in cases}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        for c in cases:
+            a, b = ev[c["N"]][k]
+            a.record(stream)
+            c["solver"].step(1, c["dt"])
+            b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for c in cases:
+        times = [a.elapsed_time(b) * 1e-3 for a, b in ev[c["N"]]]
+        c["kernel_s"] = float(np.mean(times))
+        c["kernel_s_min"] = float(np.min(times))
+        e = c["solver"].energy()
+        if not math.isfinite(e):
+            raise RuntimeError(f"non-finite energy at N={c['N']}")
+        c["energy"] = e
+    for c in cases:
+        c["solver"].close()
+        del c["solver"]
+    return cases, wall
+
+
+def run_cpu_baseline(physics, degrees, steps, log):
+    """The FP64 oracle on half-edge samples of each degree's mesh (1/8 of the
+    elements), timed over `steps` AB3 steps after one untimed step."""
+    from threadpoolctl import threadpool_info
+
+    from oracle.dg import AB3Stepper, make_oracle
+    from oracle.mesh import build_mesh
+
+    total_nodes = 0
+    total_time = 0.0
+    cpu_time = 0.0
+    parts = []
+    for N in degrees:
+        n, mesh, coef = workload(physics, N, scale=0.5)
+        geo = build_mesh(N, mesh.elem_xyz, mesh.elem_topo, None)
+        o = make_oracle(physics, geo, coef)
+        q0 = init_fields(physics, geo.xyz).astype(np.float64)
+        dt = di.time_step(mesh, N, di.max_wave_speed(coef, physics))
+        st = AB3Stepper(o, q0)
+        st.step(1, dt)
+        c0, t0 = time.process_time(), time.perf_counter()
+        st.step(steps, dt)
+        t = time.perf_counter() - t0
+        cpu_time += time.process_time() - c0
+        total_time += t
+        total_nodes += geo.K * geo.ref.Np * steps
+        parts.append(f"N={N}:n={n},K={geo.K}")
+        log(f"  cpu oracle {physics} N={N}: {geo.K * geo.ref.Np * steps / t:.3e} node-updates/s")
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    return {
+        "value": total_nodes / total_time,
+        "unit": "node-updates/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{physics} N={degrees[0]}..{degrees[-1]}, meshes with half the subcubes per edge "
+        f"({', '.join(parts)}), {steps} AB3 steps each after one untimed step; "
+        f"{total_time:.1f} s wall, {cpu_time / max(total_time, 1e-9):.1f} cores busy on average",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", choices=["acoustic", "elastic"], default="acoustic")
+    ap.add_argument("--degrees", type=str, default="1-8")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    if args.gpus != 1:
+        print(
+            f"bench.py: --gpus {args.gpus} is not supported: this build measures one GPU only "
+            "(the multi-GPU halo exchange is a design, not an implementation)",
+            file=sys.stderr,
+        )
+        return 2
+    if "-" in args.degrees:
+        lo, hi = (int(x) for x in args.degrees.split("-"))
+        degrees = list(range(lo, hi + 1))
+    else:
+        degrees = [int(x) for x in args.degrees.split(",")]
+    physics = args.config
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    log(f"bench: {physics} sweep N={degrees}, {args.steps} timed steps, {args.warmup} warm-up")
+    cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log)
+
+    per = []
+    for c in cases:
+        nbytes, flops = algorithmic_model(physics, c["N"])
+        t = c["kernel_s"]
+        bw = nbytes * c["K"] / t
+        fl = flops * c["K"] / t
+        t_hbm = nbytes * c["K"] / HBM_PEAK
+        t_alu = flops * c["K"] / FP32_PEAK
+        bound = "hbm" if t_hbm >= t_alu else "alu"
+        frac = (t_hbm if bound == "hbm" else t_alu) / t
+        per.append(
+            {
+                "N": c["N"], "n": c["n"], "K": c["K"], "nodes": c["K"] * c["Np"],
+                "kernel_us": round(t * 1e6, 2), "kernel_us_min": round(c["kernel_s_min"] * 1e6, 2),
+                "node_updates_per_s": c["K"] * c["Np"] / t,
+                "alg_bytes_per_elem": nbytes, "alg_flops_per_elem": flops,
+                "achieved_GBps": bw / 1e9, "achieved_TFLOPs": fl / 1e12,
+                "bound": bound, "frac": frac,
+            }
+        )
+        log(
+            f"  N={c['N']}: {t * 1e6:8.1f} us/step  {c['K'] * c['Np'] / t:.3e} node-upd/s  "
+            f"{bw / 1e9:7.1f} GB/s  {fl / 1e12:6.2f} TFLOP/s  {bound} frac {frac:.3f}"
+        )
+    total_nodes = sum(c["K"] * c["Np"] for c in cases)
+    ms_per_step = wall / args.steps * 1e3
+    value = total_nodes / (wall / args.steps)
+    dom = max(per, key=lambda p: p["kernel_us"])
+    nb, nf = dom["alg_bytes_per_elem"] * dom["K"], dom["alg_flops_per_elem"] * dom["K"]
+    t = dom["kernel_us"] * 1e-6
+    if dom["bound"] == "hbm":
+        roof = {"bound": "hbm", "achieved": nb / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": nf / t / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"dg_step_kernel<N={dom['N']},{physics}>"
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)")
+        cpu = run_cpu_baseline(physics, degrees, args.cpu_steps, log)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{physics} sweep N={degrees[0]}..{degrees[-1]}, one ~2M-node jittered Kuhn cube per degree, "
+            "one AB3 step on every mesh per benchmark step",
+            "physics": physics,
+            "degrees": degrees,
+            "total_nodes": total_nodes,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "per_degree": per,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

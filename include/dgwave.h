@@ -1,0 +1,200 @@
+/*
+ * dgwave.h -- C ABI of the MI355X (gfx950) nodal discontinuous Galerkin wave
+ * step library.
+ *
+ * The library advances the semi-discrete nodal DG systems of Sec. 2 of
+ * Modave, St-Cyr & Warburton, "GPU performance analysis of a nodal
+ * discontinuous Galerkin method for acoustic and elastic models"
+ * (arXiv:1602.07997):
+ *   - acoustic pressure-velocity system with the upwind penalty of Sec. 2.1,
+ *     right-hand side in the form of eqs. (5)-(6);
+ *   - isotropic elastic velocity-stress system with the exact-Riemann upwind
+ *     flux of Sec. 2.1 and the elastic right-hand side of Sec. 3.2 (the mu
+ *     term read as 2 mu sym(grad v), as the PDE of Sec. 2.1 states);
+ *   - third-order Adams-Bashforth time stepping, eq. (4), started with one
+ *     forward-Euler and one two-step Adams-Bashforth step.
+ * The per-step work (volume term, face traces and upwind flux, merged LIFT,
+ * AB3 update) runs in hand-written HIP kernels on one GPU.
+ *
+ * Conventions
+ *   physics   DG_ACOUSTIC (fields p, v1, v2, v3) or DG_ELASTIC (fields v1,
+ *             v2, v3, s11, s22, s33, s23, s13, s12).
+ *   order     polynomial degree N, 1 <= N <= 8; Np = (N+1)(N+2)(N+3)/6 nodes
+ *             per element, Nfp = (N+1)(N+2)/2 nodes per face.
+ *   nodes     warp-and-blend nodes on the reference tetrahedron
+ *             v1=(-1,-1,-1), v2=(1,-1,-1), v3=(-1,1,-1), v4=(-1,-1,1); node n
+ *             is the lattice point with integer barycentrics (l1,l2,l3,l4),
+ *             sum N, enumerated with l4 outermost, then l3, then l2.
+ *   faces     f0=(v1,v2,v3), f1=(v1,v2,v4), f2=(v2,v3,v4), f3=(v1,v3,v4);
+ *             face node j <-> (a,b) = barycentrics of the 2nd and 3rd face
+ *             vertex, b outermost.
+ *   fields    element-major float32 [K][Nfields][Np] (element k's block is
+ *             contiguous; field c of element k starts at (k*Nfields + c)*Np).
+ *   meshes    elem_xyz float64 [K][4][3] vertex coordinates, positively
+ *             oriented; elem_topo int64 [K][4] topological vertex ids.  Two
+ *             faces are neighbours iff they carry the same three ids; faces
+ *             without a partner are reflecting walls (mirror ghost state:
+ *             rigid wall for acoustics, traction-free for elasticity).
+ *             Periodic boxes identify vertices through elem_topo while
+ *             elem_xyz keeps unwrapped coordinates.
+ *
+ * Pointers named "device" must point to GPU memory of the device current when
+ * the solver was created; they are used stream-ordered on the solver's
+ * stream, and the library keeps no reference to them after the call's work
+ * has executed.  Pointers named "host" are read or written before the call
+ * returns.  No call throws; every call returns a dg_status and on failure
+ * dg_last_error() describes the cause (thread-local, valid until the next
+ * failing call on the same thread).
+ */
+#ifndef DGWAVE_H
+#define DGWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int dg_status;
+#define DG_OK 0
+#define DG_E_ARG (-1)         /* bad scalar argument or null pointer          */
+#define DG_E_SHAPE (-2)       /* sizes inconsistent with the solver           */
+#define DG_E_MESH (-3)        /* invalid mesh (orientation, connectivity)     */
+#define DG_E_STATE (-4)       /* call out of order (e.g. step before fields)  */
+#define DG_E_HIP (-5)         /* HIP runtime error                            */
+#define DG_E_UNSUPPORTED (-6) /* degree or physics not built                  */
+#define DG_E_UNSTABLE (-7)    /* non-finite energy detected                   */
+
+#define DG_ACOUSTIC 0
+#define DG_ELASTIC 1
+
+typedef struct dg_solver dg_solver;
+
+/* Version of this ABI (bumped on any incompatible change). */
+int dg_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* dg_last_error(void);
+
+/* Number of fields for a physics (4 acoustic, 9 elastic), or -1. */
+int dg_num_fields(int physics);
+
+/* ------------------------------------------------------------------------ */
+/* Host-only set-up queries (no GPU needed).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Np and Nfp for degree `order` (1..8).  Np/Nfp are host int*. */
+dg_status dg_ref_sizes(int order, int* Np, int* Nfp);
+
+/* Reference element of degree `order` (Sec. 2.2: nodal expansion eq. (1),
+ * differentiation matrices D_j and merged lift matrix L of eqs. (3), (5)-(6)),
+ * all host arrays owned by the caller, row-major, any of them may be NULL:
+ *   nodes [Np][3]          (r,s,t) of the warp-and-blend nodes
+ *   D     [3][Np][Np]      D[j][n][m] = d ell_m / d r_j at node n
+ *   mass  [Np][Np]         reference mass matrix (volume 4/3)
+ *   lift  [Np][4*Nfp]      merged LIFT = M^{-1}[E_0..E_3], face blocks in
+ *                          face order, face mass in the parameter triangle
+ *                          (-1,-1),(1,-1),(-1,1) through the face's vertices
+ *   fmask [4][Nfp]         volume node of face node j of face f            */
+dg_status dg_reference_operators(int order, double* nodes, double* D, double* mass,
+                                 double* lift, int32_t* fmask);
+
+/* Face-node permutation for the six relative orientations of two faces that
+ * share three vertices (the per-face-node neighbour map of Sec. 3.2, stored
+ * per face instead of per node).  perm is host int32 [6][Nfp]: own face node j
+ * meets neighbour face node perm[o][j], where o indexes the permutation pi of
+ * the face's vertices (own vertex p is neighbour vertex pi(p)) in the order
+ * (0,1,2),(0,2,1),(1,0,2),(1,2,0),(2,0,1),(2,1,0).                         */
+dg_status dg_face_permutations(int order, int32_t* perm);
+
+/* Face connectivity of a mesh from its topological ids (host arrays):
+ *   e2e [K][4] neighbour element or -1 (wall); e2f [K][4] neighbour face or
+ *   -1; orient [K][4] orientation index (see dg_face_permutations) or -1.
+ * Fails with DG_E_MESH if a face is shared by more than two elements or an
+ * element repeats a vertex id.                                              */
+dg_status dg_mesh_connectivity(int64_t K, const int64_t* elem_topo, int64_t* e2e, int32_t* e2f,
+                               int32_t* orient);
+
+/* ------------------------------------------------------------------------ */
+/* Solver (needs a GPU).                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Create a solver for `K` elements of degree `order`.  elem_xyz (host
+ * float64 [K][4][3]) and elem_topo (host int64 [K][4]) are copied; the
+ * geometry (per-element inverse Jacobian G[i][j] = d r_j / d x_i, the volume
+ * factor of eq. (3); face normals and Fscale = sJ/J, the surface factor) and
+ * connectivity are built on the host in float64 and uploaded.  `stream` is a
+ * hipStream_t (NULL = default stream) used by every later call.  Device
+ * memory is allocated here and freed by dg_destroy.  Errors: DG_E_ARG,
+ * DG_E_UNSUPPORTED, DG_E_MESH (J <= 0, inconsistent face pairing), DG_E_HIP. */
+dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz,
+                    const int64_t* elem_topo, void* stream, dg_solver** out);
+
+/* Release the solver and its device memory (synchronises its stream). */
+void dg_destroy(dg_solver* s);
+
+/* Replace the stream used by later calls (hipStream_t, NULL = default). */
+dg_status dg_set_stream(dg_solver* s, void* stream);
+
+/* Wait for all work queued by the solver. */
+dg_status dg_synchronize(dg_solver* s);
+
+/* Physical coordinates of every node, host float64 [K][Np][3]. */
+dg_status dg_node_coordinates(dg_solver* s, double* xyz);
+
+/* Material coefficients per element, device float32: acoustic [K][2]
+ * (rho, c); elastic [K][3] (rho, lambda, mu), all > 0 (mu > 0 is required by
+ * the elastic flux).  Derived per-face impedances of the neighbours are
+ * computed on the device.  Must precede dg_step/dg_rhs.                     */
+dg_status dg_set_coefficients(dg_solver* s, const float* coef);
+
+/* Set the fields (device float32 [K][Nfields][Np]); resets the step counter
+ * to 0 so that the next steps use the Euler / two-step start-up.            */
+dg_status dg_set_fields(dg_solver* s, const float* q);
+
+/* Copy the current fields to device float32 [K][Nfields][Np]. */
+dg_status dg_get_fields(dg_solver* s, float* q);
+
+/* Full AB3 state for checkpoint / resume: q^m, r^{m-1}, r^{m-2} (device
+ * float32, each [K][Nfields][Np]; r1/r2 ignored when step_index < 1 / < 2)
+ * and the step index m.                                                     */
+dg_status dg_set_state(dg_solver* s, const float* q, const float* r1, const float* r2,
+                       int64_t step_index);
+dg_status dg_get_state(dg_solver* s, float* q, float* r1, float* r2, int64_t* step_index);
+
+/* Current step index m (host int64*). */
+dg_status dg_step_index(dg_solver* s, int64_t* m);
+
+/* Advance `nsteps` steps of size dt (eq. (4)); one fused kernel per step,
+ * asynchronous on the solver's stream.                                      */
+dg_status dg_step(dg_solver* s, int nsteps, double dt);
+
+/* One evaluation of the right-hand side r(q) of eqs. (2)-(3): q and r are
+ * device float32 [K][Nfields][Np]; does not touch the solver's state.       */
+dg_status dg_rhs(dg_solver* s, const float* q, float* r);
+
+/* Discrete energy of the current fields, accumulated in float64 on the GPU:
+ * acoustic 1/2 sum_k J_k [p^T M p/(rho c^2) + rho sum_i v_i^T M v_i];
+ * elastic 1/2 sum_k J_k [rho sum_i v_i^T M v_i + (s:s - lambda/(3 lambda +
+ * 2 mu) tr(s)^2)/(2 mu)] with the mass matrix (off-diagonal stresses twice).
+ * Synchronises; *e is host float64.  Returns DG_E_UNSTABLE (with *e set) if
+ * the energy is not finite.                                                  */
+dg_status dg_energy(dg_solver* s, double* e);
+
+/* Diagnostics: copy one internal device buffer of the solver into caller
+ * memory (host), for layout and data checks in tests.  `name` is one of
+ * "geo" (float32 [K][9]), "cf" (float32 [K][CB]), "conn" (int32 [K][4]),
+ * "fmask" (int32 [4][Nfp]), "perm" (int32 [6][Nfp]), "DT" (float32
+ * [3][Np][Np], DT[j][m][n] = D_j[n][m]), "LT" (float32 [4Nfp][Np]),
+ * "traces" (float32 [K][4][NT][Nfp], the traces of the current fields) or
+ * "traces_rhs" (traces of the last dg_rhs input).  *bytes is the buffer
+ * size on return; nothing is copied when dst is NULL or *bytes is too small
+ * on entry (DG_E_SHAPE).  Synchronises the solver's stream.               */
+dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGWAVE_H */

@@ -1,0 +1,701 @@
+// HIP kernels of the nodal DG wave step for gfx950.
+//
+// One fused kernel per time step (Sec. 3.2's volume, surface and update
+// kernels merged): a workgroup owns a tile of KT consecutive elements and
+//   P0  stages the tile's fields, inverse Jacobians, coefficients and face
+//       connectivity in LDS (contiguous, coalesced loads);
+//   P1  forms the per-node geometric combinations of the volume term
+//       (acoustic U_j = sum_i g_ij v_i, eq. (5); elastic S_il = sum_j g_jl s_ij)
+//       and, at every face node, gathers the neighbour's traces from the
+//       previous step's trace buffer and evaluates the upwind penalty times
+//       Fscale (Sec. 2.1);
+//   P2  node per thread: the six (acoustic) or eighteen (elastic) Np x Np
+//       matrix-vector products with D_j, the merged LIFT product, the
+//       coefficient combinations of eqs. (5)-(6) / the elastic right-hand
+//       side, and the AB3 update of eq. (4); writes q^{m+1} and r^m;
+//   P3  writes the updated fields' own traces (acoustic p and n.v, elastic v
+//       and s n) to the other trace buffer.
+// Traces are double-buffered, so no element reads a trace written in the
+// same launch; every element's fields are read and written only by its own
+// workgroup.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace dgw {
+
+namespace {
+
+template <int N>
+struct Deg {
+  static constexpr int NP = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int NFP = (N + 1) * (N + 2) / 2;
+};
+
+template <int PHYS>
+struct Phys;
+template <>
+struct Phys<0> {  // acoustic: p, v1, v2, v3
+  static constexpr int NF = 4, NT = 2, NAUX = 3, CB = 8;
+};
+template <>
+struct Phys<1> {  // elastic: v1, v2, v3, s11, s22, s33, s23, s13, s12
+  static constexpr int NF = 9, NT = 6, NAUX = 9, CB = 16;
+};
+
+// Elements per workgroup, chosen so that KT*NP fills ~256 threads.
+template <int N, int PHYS>
+struct Tile {
+  static constexpr int NP = Deg<N>::NP;
+  static constexpr int raw = 256 / NP;
+  static constexpr int KT =
+      (N == 8 && PHYS == 0) ? 3 : (PHYS == 1 && N <= 2 ? (N == 1 ? 32 : 16) : (raw < 1 ? 1 : raw));
+};
+
+constexpr int kThreads = 256;
+
+// Voigt index of the symmetric stress component (i, j).
+__device__ __forceinline__ constexpr int voigt(int i, int j) {
+  return (i == j) ? i : (3 + (3 - i - j));  // (1,2)->3, (0,2)->4, (0,1)->5
+}
+
+// Outward unit normal and Fscale of reference face f from G (row-major 3x3):
+// n ~ G nref_f with nref = (0,0,-1), (0,-1,0), (1,1,1), (-1,0,0) for f = 0..3,
+// Fscale = |G nref_f|.  The reference normal is formed with 0/1 weights rather
+// than a chain of selects: hipcc (ROCm 7.2) turned such a chain into branches
+// that left face 3 with the face-1 value.
+__device__ __forceinline__ void face_normal(const float* G, int f, float n[3], float& fs) {
+  const float is0 = static_cast<float>(f == 0), is1 = static_cast<float>(f == 1);
+  const float is2 = static_cast<float>(f == 2), is3 = static_cast<float>(f == 3);
+  const float w0 = is2 - is3, w1 = is2 - is1, w2 = is2 - is0;
+  float v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = G[3 * i + 0] * w0 + G[3 * i + 1] * w1 + G[3 * i + 2] * w2;
+  fs = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const float inv = 1.0f / fs;
+  n[0] = v[0] * inv;
+  n[1] = v[1] * inv;
+  n[2] = v[2] * inv;
+}
+
+__device__ __forceinline__ int64_t tile_of_block(int xcd_remap) {
+  const int64_t b = blockIdx.x;
+  if (!xcd_remap) return b;
+  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+  // contiguous range of tiles so that neighbours share an L2.
+  const int64_t per = gridDim.x / 8;  // grid is a multiple of 8 when remapping
+  return (b % 8) * per + b / 8;
+}
+
+template <int N, int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_step_kernel(StepArgs a) {
+  constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP, NFN = 4 * NFP;
+  constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT, NAUX = Phys<PHYS>::NAUX;
+  constexpr int CB = Phys<PHYS>::CB;
+  constexpr int KT = Tile<N, PHYS>::KT;
+
+  __shared__ float s_q[KT * NF * NP];
+  __shared__ float s_qn[KT * NF * NP];
+  __shared__ float s_aux[KT * NAUX * NP];
+  __shared__ float s_flux[KT * NF * NFN];
+  __shared__ float s_g[KT * 9];
+  __shared__ float s_cf[KT * CB];
+  __shared__ int s_conn[KT * 4];
+
+  const int64_t tile = tile_of_block(a.xcd_remap);
+  const int64_t e0 = tile * KT;
+  if (e0 >= a.K) return;  // whole workgroup exits together
+  const int ne = static_cast<int>((a.K - e0) < KT ? (a.K - e0) : KT);
+  const int tid = threadIdx.x;
+
+  // ---- P0: stage the tile ------------------------------------------------
+  {
+    const float* src = a.q_in + e0 * NF * NP;
+    for (int i = tid; i < ne * NF * NP; i += kThreads) s_q[i] = src[i];
+    for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
+    for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
+    for (int i = tid; i < ne * 4; i += kThreads) s_conn[i] = a.conn[e0 * 4 + i];
+  }
+  __syncthreads();
+
+  // ---- P1a: geometric combinations for the volume term ------------------
+  for (int i = tid; i < ne * NP; i += kThreads) {
+    const int e = i / NP, n = i - e * NP;
+    const float* G = s_g + 9 * e;
+    const float* qe = s_q + e * NF * NP;
+    float* ax = s_aux + e * NAUX * NP;
+    if constexpr (PHYS == 0) {
+      const float v0 = qe[1 * NP + n], v1 = qe[2 * NP + n], v2 = qe[3 * NP + n];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) ax[j * NP + n] = G[0 * 3 + j] * v0 + G[1 * 3 + j] * v1 + G[2 * 3 + j] * v2;
+    } else {
+      // S_il = sum_j g_jl s_ij  (stress divergence in reference directions)
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        const float si0 = qe[(3 + voigt(ii, 0)) * NP + n];
+        const float si1 = qe[(3 + voigt(ii, 1)) * NP + n];
+        const float si2 = qe[(3 + voigt(ii, 2)) * NP + n];
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+          ax[(ii * 3 + l) * NP + n] = G[0 * 3 + l] * si0 + G[1 * 3 + l] * si1 + G[2 * 3 + l] * si2;
+      }
+    }
+  }
+
+  // ---- P1b: traces, upwind penalty, times Fscale -------------------------
+  for (int i = tid; i < ne * NFN; i += kThreads) {
+    const int e = i / NFN, fn = i - e * NFN;
+    const int f = fn / NFP, j = fn - f * NFP;
+    float nrm[3], fs;
+    face_normal(s_g + 9 * e, f, nrm, fs);
+    const int vn = a.fmask[f * NFP + j];
+    const float* qe = s_q + e * NF * NP;
+    const float* cf = s_cf + e * CB;
+    const int word = s_conn[e * 4 + f];
+    const int orient = word & 7;
+    float* fl = s_flux + e * NF * NFN;
+    if constexpr (PHYS == 0) {
+      const float pM = qe[vn];
+      const float vnM = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
+      const float rc2 = cf[0], c = cf[3], ZM = cf[2];
+      float pP, vnP, ZP;
+      if (orient == 7) {  // rigid wall: mirror state
+        pP = pM;
+        vnP = -vnM;
+        ZP = ZM;
+      } else {
+        const int64_t kn = static_cast<int64_t>(word >> 5);
+        const int fnb = (word >> 3) & 3;
+        const int jn = a.perm[orient * NFP + j];
+        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP;
+        pP = tr[jn];
+        vnP = -tr[NFP + jn];  // neighbour stored v.n with its own normal
+        ZP = cf[4 + f];
+      }
+      const float jp = 0.5f * (pP - pM);
+      const float jv = 0.5f * (vnP - vnM);
+      const float kc = 2.0f / (ZM + ZP);
+      const float alpha = jp - ZP * jv;
+      const float fp = fs * rc2 * kc * alpha;
+      const float fv = -fs * c * kc * alpha;
+      fl[0 * NFN + fn] = fp;
+      fl[1 * NFN + fn] = fv * nrm[0];
+      fl[2 * NFN + fn] = fv * nrm[1];
+      fl[3 * NFN + fn] = fv * nrm[2];
+    } else {
+      const float lam = cf[0], mu = cf[1];
+      const float ZpM = cf[3], ZsM = cf[4], cp = cf[5], cs = cf[6];
+      float vM[3], tM[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) vM[ii] = qe[ii * NP + vn];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+        tM[ii] = qe[(3 + voigt(ii, 0)) * NP + vn] * nrm[0] + qe[(3 + voigt(ii, 1)) * NP + vn] * nrm[1] +
+                 qe[(3 + voigt(ii, 2)) * NP + vn] * nrm[2];
+      float vP[3], tP[3], ZpP, ZsP;
+      if (orient == 7) {  // traction-free wall: mirror state
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          vP[ii] = vM[ii];
+          tP[ii] = -tM[ii];
+        }
+        ZpP = ZpM;
+        ZsP = ZsM;
+      } else {
+        const int64_t kn = static_cast<int64_t>(word >> 5);
+        const int fnb = (word >> 3) & 3;
+        const int jn = a.perm[orient * NFP + j];
+        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP;
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          vP[ii] = tr[ii * NFP + jn];
+          tP[ii] = -tr[(3 + ii) * NFP + jn];  // neighbour stored s n with its own normal
+        }
+        ZpP = cf[8 + f];
+        ZsP = cf[12 + f];
+      }
+      float jv[3], jt[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        jv[ii] = 0.5f * (vP[ii] - vM[ii]);
+        jt[ii] = 0.5f * (tP[ii] - tM[ii]);
+      }
+      const float jvn = jv[0] * nrm[0] + jv[1] * nrm[1] + jv[2] * nrm[2];
+      const float jsnn = jt[0] * nrm[0] + jt[1] * nrm[1] + jt[2] * nrm[2];
+      const float kp = 2.0f / (ZpM + ZpP);
+      const float ks = 2.0f / (ZsM + ZsP);
+      const float ap = jsnn + ZpP * jvn;
+      const float as = jsnn + ZsP * jvn;
+      float asv[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) asv[ii] = jt[ii] + ZsP * jv[ii];
+      const float pvn = kp * ap * cp - ks * as * cs;
+      const float pvs = ks * cs;
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) fl[ii * NFN + fn] = fs * (pvn * nrm[ii] + pvs * asv[ii]);
+      const float A = kp * ap * lam;
+      const float B = 2.0f * (kp * ap - ks * as) * mu;
+      const float C = ks * mu;
+      // Voigt order (00, 11, 22, 12, 02, 01)
+      const int vi[6] = {0, 1, 2, 1, 0, 0};
+      const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        const int ii = vi[v], jj = vj[v];
+        float ps = B * nrm[ii] * nrm[jj] + C * (nrm[ii] * asv[jj] + asv[ii] * nrm[jj]);
+        if (ii == jj) ps += A;
+        fl[(3 + v) * NFN + fn] = fs * ps;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- P2: node per thread: D_j products, LIFT, combinations, AB3 --------
+  const bool step = (a.mode == kStepMode);
+  for (int i = tid; i < ne * NP; i += kThreads) {
+    const int e = i / NP, n = i - e * NP;
+    const float* G = s_g + 9 * e;
+    const float* qe = s_q + e * NF * NP;
+    const float* ax = s_aux + e * NAUX * NP;
+    const float* fl = s_flux + e * NF * NFN;
+    const float* cf = s_cf + e * CB;
+    float r[NF];
+    // merged LIFT of all penalty components
+    float lift[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) lift[c] = 0.0f;
+#pragma unroll 4
+    for (int fm = 0; fm < NFN; ++fm) {
+      const float l = a.LT[fm * NP + n];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) lift[c] += l * fl[c * NFN + fm];
+    }
+    if constexpr (PHYS == 0) {
+      float T0 = 0.f, T1 = 0.f, T2 = 0.f, dv = 0.f;
+#pragma unroll 4
+      for (int m = 0; m < NP; ++m) {
+        const float d0 = a.DT[(0 * NP + m) * NP + n];
+        const float d1 = a.DT[(1 * NP + m) * NP + n];
+        const float d2 = a.DT[(2 * NP + m) * NP + n];
+        const float pm = qe[m];
+        T0 += d0 * pm;
+        T1 += d1 * pm;
+        T2 += d2 * pm;
+        dv += d0 * ax[m] + d1 * ax[NP + m] + d2 * ax[2 * NP + m];
+      }
+      const float rc2 = cf[0], irho = cf[1];
+      r[0] = -rc2 * dv + lift[0];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+        r[1 + ii] = -irho * (G[3 * ii + 0] * T0 + G[3 * ii + 1] * T1 + G[3 * ii + 2] * T2) + lift[1 + ii];
+    } else {
+      float Dv[3][3], dS[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        dS[ii] = 0.f;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) Dv[ii][l] = 0.f;
+      }
+#pragma unroll 2
+      for (int m = 0; m < NP; ++m) {
+        float d[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) d[l] = a.DT[(l * NP + m) * NP + n];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          const float vm = qe[ii * NP + m];
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            Dv[ii][l] += d[l] * vm;
+            dS[ii] += d[l] * ax[(ii * 3 + l) * NP + m];
+          }
+        }
+      }
+      const float lam = cf[0], mu = cf[1], irho = cf[2];
+      float gv[3][3];  // d v_i / d x_j = sum_l g_jl D_l v_i
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          gv[ii][jj] = G[3 * jj + 0] * Dv[ii][0] + G[3 * jj + 1] * Dv[ii][1] + G[3 * jj + 2] * Dv[ii][2];
+      const float divv = gv[0][0] + gv[1][1] + gv[2][2];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) r[ii] = irho * dS[ii] + lift[ii];
+      const int vi[6] = {0, 1, 2, 1, 0, 0};
+      const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        const int ii = vi[v], jj = vj[v];
+        float val = mu * (gv[ii][jj] + gv[jj][ii]);
+        if (ii == jj) val += lam * divv;
+        r[3 + v] = val + lift[3 + v];
+      }
+    }
+    const int64_t base = (e0 + e) * NF * NP + n;
+    if (step) {
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        const int64_t idx = base + c * NP;
+        float upd = a.c0 * r[c];
+        if (a.c1 != 0.0f) upd += a.c1 * a.r1[idx];
+        if (a.c2 != 0.0f) upd += a.c2 * a.r2[idx];
+        const float qn = qe[c * NP + n] + upd;
+        a.q_out[idx] = qn;
+        a.r_out[idx] = r[c];
+        s_qn[(e * NF + c) * NP + n] = qn;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NF; ++c) a.r_out[base + c * NP] = r[c];
+    }
+  }
+  if (!step) return;
+  __syncthreads();
+
+  // ---- P3: own traces of the updated fields -------------------------------
+  for (int i = tid; i < ne * NFN; i += kThreads) {
+    const int e = i / NFN, fn = i - e * NFN;
+    const int f = fn / NFP, j = fn - f * NFP;
+    float nrm[3], fs;
+    face_normal(s_g + 9 * e, f, nrm, fs);
+    const int vn = a.fmask[f * NFP + j];
+    const float* qe = s_qn + e * NF * NP;
+    float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP;
+    if constexpr (PHYS == 0) {
+      tr[j] = qe[vn];
+      tr[NFP + j] = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
+    } else {
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) tr[ii * NFP + j] = qe[ii * NP + vn];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+        tr[(3 + ii) * NFP + j] = qe[(3 + voigt(ii, 0)) * NP + vn] * nrm[0] +
+                                 qe[(3 + voigt(ii, 1)) * NP + vn] * nrm[1] +
+                                 qe[(3 + voigt(ii, 2)) * NP + vn] * nrm[2];
+    }
+  }
+}
+
+// Own traces of a field array (initial state, right-hand-side evaluation).
+template <int N, int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_trace_kernel(int64_t K, const float* __restrict__ q, const float* __restrict__ geo,
+                const int32_t* __restrict__ fmask, float* __restrict__ qf) {
+  constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP, NFN = 4 * NFP;
+  constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= K * NFN) return;
+  const int64_t k = i / NFN;
+  const int fn = static_cast<int>(i - k * NFN);
+  const int f = fn / NFP, j = fn - f * NFP;
+  float G[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) G[t] = geo[k * 9 + t];
+  float nrm[3], fs;
+  face_normal(G, f, nrm, fs);
+  const int vn = fmask[f * NFP + j];
+  const float* qe = q + k * NF * NP;
+  float* tr = qf + (k * 4 + f) * NT * NFP;
+  if constexpr (PHYS == 0) {
+    tr[j] = qe[vn];
+    tr[NFP + j] = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
+  } else {
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) tr[ii * NFP + j] = qe[ii * NP + vn];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+      tr[(3 + ii) * NFP + j] = qe[(3 + voigt(ii, 0)) * NP + vn] * nrm[0] +
+                               qe[(3 + voigt(ii, 1)) * NP + vn] * nrm[1] +
+                               qe[(3 + voigt(ii, 2)) * NP + vn] * nrm[2];
+  }
+}
+
+// Derived coefficients per element, including the neighbours' impedances on
+// each face (own values on walls).
+//   acoustic cf = [rho c^2, 1/rho, Z, c, Z+_0..3]
+//   elastic  cf = [lambda, mu, 1/rho, Zp, Zs, cp, cs, 0, Zp+_0..3, Zs+_0..3]
+template <int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_coef_kernel(int64_t K, const float* __restrict__ coef, const int32_t* __restrict__ conn,
+               float* __restrict__ cf) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (k >= K) return;
+  if constexpr (PHYS == 0) {
+    const float rho = coef[2 * k], c = coef[2 * k + 1];
+    float* o = cf + 8 * k;
+    o[0] = rho * c * c;
+    o[1] = 1.0f / rho;
+    o[2] = rho * c;
+    o[3] = c;
+    for (int f = 0; f < 4; ++f) {
+      const int w = conn[4 * k + f];
+      int64_t kn = ((w & 7) == 7) ? k : static_cast<int64_t>(w >> 5);
+      o[4 + f] = coef[2 * kn] * coef[2 * kn + 1];
+    }
+  } else {
+    const float rho = coef[3 * k], lam = coef[3 * k + 1], mu = coef[3 * k + 2];
+    const float cp = sqrtf((lam + 2.0f * mu) / rho), cs = sqrtf(mu / rho);
+    float* o = cf + 16 * k;
+    o[0] = lam;
+    o[1] = mu;
+    o[2] = 1.0f / rho;
+    o[3] = rho * cp;
+    o[4] = rho * cs;
+    o[5] = cp;
+    o[6] = cs;
+    o[7] = 0.0f;
+    for (int f = 0; f < 4; ++f) {
+      const int w = conn[4 * k + f];
+      int64_t kn = ((w & 7) == 7) ? k : static_cast<int64_t>(w >> 5);
+      const float rn = coef[3 * kn], ln = coef[3 * kn + 1], mn = coef[3 * kn + 2];
+      o[8 + f] = rn * sqrtf((ln + 2.0f * mn) / rn);
+      o[12 + f] = rn * sqrtf(mn / rn);
+    }
+  }
+}
+
+// FP64 discrete energy: one workgroup per tile of elements, partial sums.
+template <int N, int PHYS>
+struct ETile {
+  static constexpr int NP = Deg<N>::NP;
+  static constexpr int KT = (256 / NP) < 1 ? 1 : (256 / NP);
+};
+
+template <int N, int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_energy_kernel(int64_t K, const float* __restrict__ q, const float* __restrict__ coef,
+                 const double* __restrict__ J, const double* __restrict__ M,
+                 double* __restrict__ partial) {
+  constexpr int NP = Deg<N>::NP;
+  constexpr int NF = Phys<PHYS>::NF;
+  constexpr int KT = ETile<N, PHYS>::KT;
+  __shared__ float s_q[KT * NF * NP];
+  __shared__ double s_red[kThreads];
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * KT;
+  const int ne = static_cast<int>((K - e0) < KT ? (K - e0) : KT);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ne * NF * NP; i += kThreads) s_q[i] = q[e0 * NF * NP + i];
+  __syncthreads();
+  double acc = 0.0;
+  for (int i = tid; i < ne * NP; i += kThreads) {
+    const int e = i / NP, n = i - e * NP;
+    const float* qe = s_q + e * NF * NP;
+    double Mq[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) Mq[c] = 0.0;
+    for (int m = 0; m < NP; ++m) {
+      const double mm = M[n * NP + m];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) Mq[c] += mm * static_cast<double>(qe[c * NP + m]);
+    }
+    const int64_t k = e0 + e;
+    double en;
+    if constexpr (PHYS == 0) {
+      const double rho = coef[2 * k], c = coef[2 * k + 1];
+      en = Mq[0] * qe[n] / (rho * c * c);
+#pragma unroll
+      for (int ii = 1; ii < 4; ++ii) en += rho * Mq[ii] * qe[ii * NP + n];
+    } else {
+      const double rho = coef[3 * k], lam = coef[3 * k + 1], mu = coef[3 * k + 2];
+      double kin = 0.0, ss = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) kin += Mq[ii] * qe[ii * NP + n];
+#pragma unroll
+      for (int v = 0; v < 6; ++v) ss += (v < 3 ? 1.0 : 2.0) * Mq[3 + v] * qe[(3 + v) * NP + n];
+      const double tr = static_cast<double>(qe[3 * NP + n]) + qe[4 * NP + n] + qe[5 * NP + n];
+      const double Mtr = Mq[3] + Mq[4] + Mq[5];
+      en = rho * kin + (ss - lam / (3.0 * lam + 2.0 * mu) * tr * Mtr) / (2.0 * mu);
+    }
+    acc += 0.5 * J[k] * en;
+  }
+  s_red[tid] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) s_red[tid] += s_red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) partial[blockIdx.x] = s_red[0];
+}
+
+__global__ void __launch_bounds__(kThreads)
+dg_sum_kernel(int64_t n, const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double s_red[kThreads];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) acc += partial[i];
+  s_red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s_red[0];
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over (physics, degree)
+// ---------------------------------------------------------------------------
+template <int N, int PHYS>
+hipError_t step_impl(const StepArgs& a, hipStream_t s) {
+  constexpr int KT = Tile<N, PHYS>::KT;
+  int64_t tiles = (a.K + KT - 1) / KT;
+  if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_step_kernel<N, PHYS>), dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <int N, int PHYS>
+hipError_t trace_impl(int64_t K, const float* q, const float* geo, const int32_t* fmask, float* qf,
+                      hipStream_t s) {
+  const int64_t items = K * 4 * Deg<N>::NFP;
+  const int64_t blocks = (items + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL((dg_trace_kernel<N, PHYS>), dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
+                     s, K, q, geo, fmask, qf);
+  return hipGetLastError();
+}
+
+template <int N, int PHYS>
+hipError_t energy_impl(int64_t K, const float* q, const float* coef, const double* J, const double* M,
+                       double* partial, double* out, hipStream_t s) {
+  constexpr int KT = ETile<N, PHYS>::KT;
+  const int64_t blocks = (K + KT - 1) / KT;
+  hipLaunchKernelGGL((dg_energy_kernel<N, PHYS>), dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
+                     s, K, q, coef, J, M, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(dg_sum_kernel, dim3(1), dim3(kThreads), 0, s, blocks, partial, out);
+  return hipGetLastError();
+}
+
+template <int PHYS>
+int64_t energy_blocks_impl(int N, int64_t K) {
+  int KT = 1;
+  switch (N) {
+    case 1: KT = ETile<1, PHYS>::KT; break;
+    case 2: KT = ETile<2, PHYS>::KT; break;
+    case 3: KT = ETile<3, PHYS>::KT; break;
+    case 4: KT = ETile<4, PHYS>::KT; break;
+    case 5: KT = ETile<5, PHYS>::KT; break;
+    case 6: KT = ETile<6, PHYS>::KT; break;
+    case 7: KT = ETile<7, PHYS>::KT; break;
+    case 8: KT = ETile<8, PHYS>::KT; break;
+    default: return -1;
+  }
+  return (K + KT - 1) / KT;
+}
+
+}  // namespace
+
+int coef_block(int physics) { return physics == 0 ? Phys<0>::CB : Phys<1>::CB; }
+int num_traces(int physics) { return physics == 0 ? Phys<0>::NT : Phys<1>::NT; }
+
+hipError_t launch_step(int physics, int N, const StepArgs& a, hipStream_t s) {
+#define CALL(n, p) step_impl<n, p>(a, s)
+  if (physics == 0) {
+    switch (N) {
+      case 1: return CALL(1, 0);
+      case 2: return CALL(2, 0);
+      case 3: return CALL(3, 0);
+      case 4: return CALL(4, 0);
+      case 5: return CALL(5, 0);
+      case 6: return CALL(6, 0);
+      case 7: return CALL(7, 0);
+      case 8: return CALL(8, 0);
+    }
+  } else {
+    switch (N) {
+      case 1: return CALL(1, 1);
+      case 2: return CALL(2, 1);
+      case 3: return CALL(3, 1);
+      case 4: return CALL(4, 1);
+      case 5: return CALL(5, 1);
+      case 6: return CALL(6, 1);
+      case 7: return CALL(7, 1);
+      case 8: return CALL(8, 1);
+    }
+  }
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const float* geo,
+                         const int32_t* fmask, float* qf, hipStream_t s) {
+#define CALL(n, p) trace_impl<n, p>(K, q, geo, fmask, qf, s)
+  if (physics == 0) {
+    switch (N) {
+      case 1: return CALL(1, 0);
+      case 2: return CALL(2, 0);
+      case 3: return CALL(3, 0);
+      case 4: return CALL(4, 0);
+      case 5: return CALL(5, 0);
+      case 6: return CALL(6, 0);
+      case 7: return CALL(7, 0);
+      case 8: return CALL(8, 0);
+    }
+  } else {
+    switch (N) {
+      case 1: return CALL(1, 1);
+      case 2: return CALL(2, 1);
+      case 3: return CALL(3, 1);
+      case 4: return CALL(4, 1);
+      case 5: return CALL(5, 1);
+      case 6: return CALL(6, 1);
+      case 7: return CALL(7, 1);
+      case 8: return CALL(8, 1);
+    }
+  }
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int32_t* conn, float* cf,
+                            hipStream_t s) {
+  const int64_t blocks = (K + kThreads - 1) / kThreads;
+  if (physics == 0)
+    hipLaunchKernelGGL(dg_coef_kernel<0>, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, K,
+                       coef, conn, cf);
+  else
+    hipLaunchKernelGGL(dg_coef_kernel<1>, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, K,
+                       coef, conn, cf);
+  return hipGetLastError();
+}
+
+int64_t energy_blocks(int physics, int N, int64_t K) {
+  return physics == 0 ? energy_blocks_impl<0>(N, K) : energy_blocks_impl<1>(N, K);
+}
+
+hipError_t launch_energy(int physics, int N, int64_t K, const float* q, const float* coef, const double* J,
+                         const double* mass, double* partial, double* out, hipStream_t s) {
+#define CALL(n, p) energy_impl<n, p>(K, q, coef, J, mass, partial, out, s)
+  if (physics == 0) {
+    switch (N) {
+      case 1: return CALL(1, 0);
+      case 2: return CALL(2, 0);
+      case 3: return CALL(3, 0);
+      case 4: return CALL(4, 0);
+      case 5: return CALL(5, 0);
+      case 6: return CALL(6, 0);
+      case 7: return CALL(7, 0);
+      case 8: return CALL(8, 0);
+    }
+  } else {
+    switch (N) {
+      case 1: return CALL(1, 1);
+      case 2: return CALL(2, 1);
+      case 3: return CALL(3, 1);
+      case 4: return CALL(4, 1);
+      case 5: return CALL(5, 1);
+      case 6: return CALL(6, 1);
+      case 7: return CALL(7, 1);
+      case 8: return CALL(8, 1);
+    }
+  }
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dgw

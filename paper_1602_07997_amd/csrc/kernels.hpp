@@ -1,0 +1,52 @@
+// Launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace dgw {
+
+// Per-step kernel arguments.  All pointers are device pointers.
+struct StepArgs {
+  int64_t K;
+  const float* q_in;     // fields read this step [K][NF][NP]
+  float* q_out;          // fields written (step mode; may equal q_in)
+  const float* r1;       // r^{m-1} (read when c1 != 0)
+  const float* r2;       // r^{m-2} (read when c2 != 0)
+  float* r_out;          // r^m
+  const float* qf_in;    // neighbour traces [K][4][NT][NFP]
+  float* qf_out;         // own traces of the updated fields (step mode)
+  const float* geo;      // [K][9] G[i][j] = d r_j / d x_i
+  const float* cf;       // [K][CB] derived coefficients (see coef_prep)
+  const int32_t* conn;   // [K][4] packed (neighbour<<5 | face<<3 | orient), orient 7 = wall
+  const float* DT;       // [3][NP][NP] DT[j][m][n] = D_j[n][m]
+  const float* LT;       // [4*NFP][NP] LT[fm][n] = L[n][fm]
+  const int32_t* fmask;  // [4][NFP]
+  const int32_t* perm;   // [6][NFP]
+  float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
+  int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))
+  int xcd_remap;         // map consecutive tiles onto one XCD
+};
+
+constexpr int kStepMode = 0;
+constexpr int kRhsMode = 1;
+
+// Number of coefficient words per element in `cf`.
+int coef_block(int physics);
+// Number of traces per face node (2 acoustic, 6 elastic).
+int num_traces(int physics);
+
+hipError_t launch_step(int physics, int N, const StepArgs& a, hipStream_t s);
+hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const float* geo,
+                         const int32_t* fmask, float* qf, hipStream_t s);
+hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int32_t* conn,
+                            float* cf, hipStream_t s);
+// Energy: partial sums per block into `partial` (size energy_blocks), then
+// the total into out[0].
+int64_t energy_blocks(int physics, int N, int64_t K);
+hipError_t launch_energy(int physics, int N, int64_t K, const float* q, const float* coef,
+                         const double* J, const double* mass, double* partial, double* out,
+                         hipStream_t s);
+
+}  // namespace dgw

@@ -1,0 +1,213 @@
+"""Python front end of the dgwave C ABI.
+
+Marshals numpy / torch arrays into the C calls; every step of the hot path
+runs in the library's HIP kernels.  Torch supplies device memory and the
+stream only.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as nat
+from ._native import check, lib
+
+PHYSICS = {"acoustic": nat.DG_ACOUSTIC, "elastic": nat.DG_ELASTIC}
+
+
+def ref_sizes(order: int):
+    Np, Nfp = C.c_int(), C.c_int()
+    check(lib.dg_ref_sizes(order, C.byref(Np), C.byref(Nfp)), "dg_ref_sizes")
+    return Np.value, Nfp.value
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i32ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _i64ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def reference_operators(order: int) -> dict:
+    """Host-side reference element of the product (no GPU needed)."""
+    Np, Nfp = ref_sizes(order)
+    nodes = np.zeros((Np, 3))
+    D = np.zeros((3, Np, Np))
+    mass = np.zeros((Np, Np))
+    lift = np.zeros((Np, 4 * Nfp))
+    fmask = np.zeros((4, Nfp), dtype=np.int32)
+    check(
+        lib.dg_reference_operators(order, _dptr(nodes), _dptr(D), _dptr(mass), _dptr(lift), _i32ptr(fmask)),
+        "dg_reference_operators",
+    )
+    perm = np.zeros((6, Nfp), dtype=np.int32)
+    check(lib.dg_face_permutations(order, _i32ptr(perm)), "dg_face_permutations")
+    return {"nodes": nodes, "D": D, "mass": mass, "lift": lift, "fmask": fmask, "perm": perm}
+
+
+def mesh_connectivity(elem_topo: np.ndarray):
+    topo = np.ascontiguousarray(elem_topo, dtype=np.int64)
+    K = topo.shape[0]
+    e2e = np.zeros((K, 4), dtype=np.int64)
+    e2f = np.zeros((K, 4), dtype=np.int32)
+    orient = np.zeros((K, 4), dtype=np.int32)
+    check(lib.dg_mesh_connectivity(K, _i64ptr(topo), _i64ptr(e2e), _i32ptr(e2f), _i32ptr(orient)), "dg_mesh_connectivity")
+    return e2e, e2f, orient
+
+
+def _require_torch_device_tensor(t, shape, name):
+    """Validates a device float32 tensor of the given shape; returns its pointer."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class DGSolver:
+    """One mesh, one degree, one physics on the current GPU.
+
+    ``elem_xyz`` float64 [K,4,3] and ``elem_topo`` int64 [K,4] (host numpy).
+    Field tensors are torch float32 [K, Nfields, Np] on the GPU.
+    """
+
+    def __init__(self, physics: str, order: int, elem_xyz, elem_topo, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("DGSolver needs a GPU")
+        self.physics = physics
+        self.order = order
+        self.xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
+        self.topo = np.ascontiguousarray(elem_topo, dtype=np.int64)
+        self.K = int(self.xyz.shape[0])
+        self.Np, self.Nfp = ref_sizes(order)
+        self.nfields = lib.dg_num_fields(PHYSICS[physics])
+        self.ncoef = 2 if physics == "acoustic" else 3
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = C.c_void_p()
+        check(
+            lib.dg_create(
+                PHYSICS[physics], order, self.K, _dptr(self.xyz), _i64ptr(self.topo),
+                C.c_void_p(stream.cuda_stream), C.byref(h),
+            ),
+            "dg_create",
+        )
+        self._h = h
+
+    # lifecycle ---------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes ------------------------------------------------------------------
+    @property
+    def field_shape(self):
+        return (self.K, self.nfields, self.Np)
+
+    def empty_fields(self):
+        import torch
+
+        return torch.empty(self.field_shape, dtype=torch.float32, device="cuda")
+
+    # calls -------------------------------------------------------------------
+    def node_coordinates(self) -> np.ndarray:
+        out = np.zeros((self.K, self.Np, 3))
+        check(lib.dg_node_coordinates(self._h, _dptr(out)), "dg_node_coordinates")
+        return out
+
+    def set_coefficients(self, coef):
+        p = _require_torch_device_tensor(coef, (self.K, self.ncoef), "coef")
+        check(lib.dg_set_coefficients(self._h, p), "dg_set_coefficients")
+
+    def set_fields(self, q):
+        check(lib.dg_set_fields(self._h, _require_torch_device_tensor(q, self.field_shape, "q")), "dg_set_fields")
+
+    def get_fields(self, out=None):
+        out = self.empty_fields() if out is None else out
+        check(lib.dg_get_fields(self._h, _require_torch_device_tensor(out, self.field_shape, "out")), "dg_get_fields")
+        return out
+
+    def set_state(self, q, r1, r2, step_index: int):
+        z = C.c_void_p(0)
+        p1 = _require_torch_device_tensor(r1, self.field_shape, "r1") if r1 is not None else z
+        p2 = _require_torch_device_tensor(r2, self.field_shape, "r2") if r2 is not None else z
+        check(
+            lib.dg_set_state(self._h, _require_torch_device_tensor(q, self.field_shape, "q"), p1, p2, int(step_index)),
+            "dg_set_state",
+        )
+
+    def get_state(self):
+        q, r1, r2 = self.empty_fields(), self.empty_fields(), self.empty_fields()
+        m = C.c_int64()
+        check(
+            lib.dg_get_state(
+                self._h,
+                C.c_void_p(q.data_ptr()), C.c_void_p(r1.data_ptr()), C.c_void_p(r2.data_ptr()), C.byref(m),
+            ),
+            "dg_get_state",
+        )
+        return q, (r1 if m.value >= 1 else None), (r2 if m.value >= 2 else None), m.value
+
+    @property
+    def step_index(self) -> int:
+        m = C.c_int64()
+        check(lib.dg_step_index(self._h, C.byref(m)), "dg_step_index")
+        return m.value
+
+    def step(self, nsteps: int, dt: float):
+        check(lib.dg_step(self._h, int(nsteps), float(dt)), "dg_step")
+
+    def rhs(self, q, out=None):
+        out = self.empty_fields() if out is None else out
+        check(
+            lib.dg_rhs(
+                self._h,
+                _require_torch_device_tensor(q, self.field_shape, "q"),
+                _require_torch_device_tensor(out, self.field_shape, "out"),
+            ),
+            "dg_rhs",
+        )
+        return out
+
+    def energy(self) -> float:
+        e = C.c_double()
+        check(lib.dg_energy(self._h, C.byref(e)), "dg_energy")
+        return e.value
+
+    def debug_buffer(self, name: str) -> np.ndarray:
+        """Copy of an internal device buffer (see dg_debug_buffer)."""
+        nbytes = C.c_size_t(0)
+        check(lib.dg_debug_buffer(self._h, name.encode(), None, C.byref(nbytes)), "dg_debug_buffer")
+        dtype = np.int32 if name in ("conn", "fmask", "perm") else np.float32
+        out = np.zeros(nbytes.value // 4, dtype=dtype)
+        check(
+            lib.dg_debug_buffer(self._h, name.encode(), out.ctypes.data_as(C.c_void_p), C.byref(nbytes)),
+            "dg_debug_buffer",
+        )
+        return out
+
+    def synchronize(self):
+        check(lib.dg_synchronize(self._h), "dg_synchronize")

@@ -1,0 +1,132 @@
+"""C-ABI checks that run without a GPU.
+
+* the shared library loads and exports every function declared in
+  include/dgwave.h, and the binding declares each one;
+* host-side set-up (reference operators, face permutations, connectivity)
+  matches the oracle's independently built counterparts;
+* argument and mesh validation that happens before any device work.
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dginputs as di
+from oracle.mesh import build_mesh
+from oracle.refelem import reference_element
+from paper_1602_07997_amd import _native as nat
+from paper_1602_07997_amd.solver import mesh_connectivity, reference_operators
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dgwave.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(nat.lib, name), name
+        assert name in nat.SIGNATURES, name
+    assert set(nat.SIGNATURES) == set(names)
+    assert nat.lib.dg_abi_version() == 1
+    assert nat.lib.dg_num_fields(0) == 4 and nat.lib.dg_num_fields(1) == 9
+    assert nat.lib.dg_num_fields(7) == -1
+
+
+@pytest.mark.parametrize("N", range(1, 9))
+def test_reference_operators_match_oracle(N):
+    ops = reference_operators(N)
+    ref = reference_element(N)
+    np.testing.assert_allclose(ops["nodes"], ref.r, atol=1e-13)
+    np.testing.assert_allclose(ops["D"], ref.D, atol=1e-11)
+    np.testing.assert_allclose(ops["mass"], ref.M, atol=1e-13)
+    np.testing.assert_allclose(ops["lift"], ref.LIFT, atol=1e-11)
+    assert np.array_equal(ops["fmask"], ref.Fmask)
+
+
+@pytest.mark.parametrize("N", [1, 4, 8])
+def test_product_operators_differentiate_monomials(N):
+    ops = reference_operators(N)
+    r, s, t = ops["nodes"].T
+    for a in range(N + 1):
+        for b in range(N + 1 - a):
+            c = N - a - b
+            u = r**a * s**b * t**c
+            du = a * r ** max(a - 1, 0) * s**b * t**c
+            np.testing.assert_allclose(ops["D"][0] @ u, du, atol=1e-11)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_connectivity_and_face_permutations_match_oracle(periodic):
+    m = di.kuhn_box(3, 4, 3, jitter=0.1, seed=7, periodic=periodic)
+    for N in (2, 5):
+        geo = build_mesh(N, m.elem_xyz, m.elem_topo, m.period)
+        e2e, e2f, orient = mesh_connectivity(m.elem_topo)
+        assert np.array_equal(e2e, geo.EToE)
+        assert np.array_equal(e2f, geo.EToF)
+        perm = reference_operators(N)["perm"]
+        k, f = np.nonzero(~geo.wall)
+        assert np.all(orient[k, f] >= 0)
+        assert np.array_equal(perm[orient[k, f]], geo.nbr_node[k, f])
+        assert np.all(orient[geo.wall] == -1)
+
+
+def test_permutations_are_permutations():
+    for N in range(1, 9):
+        perm = reference_operators(N)["perm"]
+        Nfp = (N + 1) * (N + 2) // 2
+        for o in range(6):
+            assert sorted(perm[o]) == list(range(Nfp))
+        assert np.array_equal(perm[0], np.arange(Nfp))
+
+
+def test_host_validation_errors():
+    bad = C.c_int()
+    assert nat.lib.dg_ref_sizes(0, C.byref(bad), C.byref(bad)) == nat.DG_E_UNSUPPORTED
+    assert nat.lib.dg_ref_sizes(9, C.byref(bad), C.byref(bad)) == nat.DG_E_UNSUPPORTED
+    assert "order" in nat.lib.dg_last_error().decode()
+    # a face shared by three elements
+    topo = np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]], dtype=np.int64)
+    with pytest.raises(nat.DGError) as ei:
+        mesh_connectivity(topo)
+    assert ei.value.status == nat.DG_E_MESH
+    topo = np.array([[0, 1, 1, 3]], dtype=np.int64)
+    with pytest.raises(nat.DGError):
+        mesh_connectivity(topo)
+
+
+def _create(physics, order, xyz, topo):
+    h = C.c_void_p()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    topo = np.ascontiguousarray(topo, dtype=np.int64)
+    st = nat.lib.dg_create(
+        physics, order, xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)),
+        topo.ctypes.data_as(C.POINTER(C.c_int64)), None, C.byref(h),
+    )
+    return st, h
+
+
+def test_create_rejects_bad_meshes_before_device_work():
+    m = di.kuhn_box(2)
+    st, h = _create(5, 2, m.elem_xyz, m.elem_topo)
+    assert st == nat.DG_E_ARG and not h.value
+    st, h = _create(0, 9, m.elem_xyz, m.elem_topo)
+    assert st == nat.DG_E_UNSUPPORTED
+    xyz = m.elem_xyz.copy()
+    xyz[5, [2, 3]] = xyz[5, [3, 2]]  # invert one element
+    st, h = _create(0, 2, xyz, m.elem_topo)
+    assert st == nat.DG_E_MESH and "Jacobian" in nat.lib.dg_last_error().decode()
+    # ids say the faces match but the coordinates do not
+    xyz = m.elem_xyz.copy()
+    topo = m.elem_topo.copy()
+    xyz[0] += 0.01 * np.array([[0, 0, 0], [0, 0, 0], [0, 0, 0], [0, 0, 1.0]])
+    st, h = _create(0, 2, xyz, topo)
+    assert st == nat.DG_E_MESH
