@@ -61,6 +61,26 @@ def algorithmic_model(physics: str, N: int):
     return nbytes, flops
 
 
+def measured_traffic(physics: str, N: int):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary (profiles/dg_step_<physics>_sweep_traffic.md), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    src = os.path.join(ROOT, "paper_1602_07997_amd", "csrc", "kernels.hip")
+    path = os.path.join(ROOT, "profiles", f"dg_step_{physics}_sweep_traffic.md")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    pat = re.compile(rf"^traffic {physics} N={N} bytes_per_launch=(\d+) kernel_sha1=([0-9a-f]+)$")
+    for line in open(path):
+        m = pat.match(line.strip())
+        if m and m.group(2) == sha:
+            return int(m.group(1))
+    return None
+
+
 def workload(physics: str, N: int, scale: float = 1.0):
     n = di.paper_scale_n(N)
     if scale != 1.0:
@@ -124,8 +144,8 @@ def run_gpu(physics, degrees, steps, warmup, log):
 
 
 def run_cpu_baseline(physics, degrees, steps, log):
-    """The FP64 oracle on half-edge samples of each degree's mesh (1/8 of the
-    elements), timed over `steps` AB3 steps after one untimed step."""
+    """The FP64 oracle on the same ~2M-node meshes, timed over `steps` AB3
+    steps after one untimed step (a bounded sample of the GPU run's steps)."""
     from threadpoolctl import threadpool_info
 
     from oracle.dg import AB3Stepper, make_oracle
@@ -136,7 +156,7 @@ def run_cpu_baseline(physics, degrees, steps, log):
     cpu_time = 0.0
     parts = []
     for N in degrees:
-        n, mesh, coef = workload(physics, N, scale=0.5)
+        n, mesh, coef = workload(physics, N)
         geo = build_mesh(N, mesh.elem_xyz, mesh.elem_topo, None)
         o = make_oracle(physics, geo, coef)
         q0 = init_fields(physics, geo.xyz).astype(np.float64)
@@ -157,7 +177,7 @@ def run_cpu_baseline(physics, degrees, steps, log):
         "unit": "node-updates/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"{physics} N={degrees[0]}..{degrees[-1]}, meshes with half the subcubes per edge "
+        "sample": f"{physics} N={degrees[0]}..{degrees[-1]} on the benchmark's own meshes "
         f"({', '.join(parts)}), {steps} AB3 steps each after one untimed step; "
         f"{total_time:.1f} s wall, {cpu_time / max(total_time, 1e-9):.1f} cores busy on average",
     }
@@ -170,9 +190,14 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", choices=["acoustic", "elastic"], default="acoustic")
     ap.add_argument("--degrees", type=str, default="1-8")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument(
+        "--copy-calibration-mib", type=int, default=0,
+        help="before the timed loop, copy a buffer of this many MiB device-to-device (a kernel of "
+        "known traffic against which hardware byte counters are scaled)",
+    )
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -198,6 +223,15 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 device copies of {args.copy_calibration_mib} MiB")
+        del src, dst
     log(f"bench: {physics} sweep N={degrees}, {args.steps} timed steps, {args.warmup} warm-up")
     cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log)
 
@@ -219,6 +253,7 @@ def main(argv=None):
                 "alg_bytes_per_elem": nbytes, "alg_flops_per_elem": flops,
                 "achieved_GBps": bw / 1e9, "achieved_TFLOPs": fl / 1e12,
                 "bound": bound, "frac": frac,
+                "traffic_bytes": measured_traffic(physics, c["N"]),
             }
         )
         log(
@@ -236,7 +271,7 @@ def main(argv=None):
     else:
         roof = {"bound": "alu", "achieved": nf / t / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(physics, dom["N"])
     roof["kernel"] = f"dg_step_kernel<N={dom['N']},{physics}>"
 
     cpu = None
