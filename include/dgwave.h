@@ -185,7 +185,8 @@ dg_status dg_energy(dg_solver* s, double* e);
 /* Diagnostics: copy one internal device buffer of the solver into caller
  * memory (host), for layout and data checks in tests.  `name` is one of
  * "geo" (float32 [K][9]), "cf" (float32 [K][CB]), "conn" (int32 [K][4]),
- * "fmask" (int32 [4][Nfp]), "perm" (int32 [6][Nfp]), "DT" (float32
+ * "fmask" (int32 [4][Nfp]), "perm" (int32 [6][Nfp]), "nodeface" (int32
+ * [Np][3], the face slots f*Nfp+j of each node, -1 padded), "DT" (float32
  * [3][Np][Np], DT[j][m][n] = D_j[n][m]), "LT" (float32 [4Nfp][Np]),
  * "traces" (float32 [K][4][NT][Nfp], the traces of the current fields) or
  * "traces_rhs" (traces of the last dg_rhs input).  *bytes is the buffer

@@ -42,6 +42,7 @@ struct dg_solver {
   int32_t* conn = nullptr;
   int32_t* fmask = nullptr;
   int32_t* perm = nullptr;
+  int32_t* nodeface = nullptr;
   double* J = nullptr;
   double* mass = nullptr;
   double* partial = nullptr;
@@ -82,7 +83,7 @@ dg_status check_solver(const dg_solver* s) {
 
 void free_all(dg_solver* s) {
   void* ptrs[] = {s->q,  s->r[0], s->r[1], s->r[2], s->qf[0], s->qf[1], s->qf_tmp, s->geo,
-                  s->cf, s->coef, s->DT,   s->LT,   s->conn,  s->fmask, s->perm,   s->J,
+                  s->cf, s->coef, s->DT,   s->LT,   s->conn,  s->fmask, s->perm,   s->nodeface, s->J,
                   s->mass, s->partial, s->e_out, s->flag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -308,6 +309,7 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
   if ((err = dev_alloc(&s->conn, conn.size())) != hipSuccess) return fail(err, "alloc conn");
   if ((err = dev_alloc(&s->fmask, ref->fmask.size())) != hipSuccess) return fail(err, "alloc fmask");
   if ((err = dev_alloc(&s->perm, ref->perm.size())) != hipSuccess) return fail(err, "alloc perm");
+  if ((err = dev_alloc(&s->nodeface, ref->nodeface.size())) != hipSuccess) return fail(err, "alloc nodeface");
   if ((err = dev_alloc(&s->J, J.size())) != hipSuccess) return fail(err, "alloc J");
   if ((err = dev_alloc(&s->mass, ref->mass.size())) != hipSuccess) return fail(err, "alloc mass");
   const int64_t eb = dgw::energy_blocks(physics, order, K);
@@ -326,6 +328,7 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
       {s->conn, conn.data(), conn.size() * sizeof(int32_t)},
       {s->fmask, ref->fmask.data(), ref->fmask.size() * sizeof(int32_t)},
       {s->perm, ref->perm.data(), ref->perm.size() * sizeof(int32_t)},
+      {s->nodeface, ref->nodeface.data(), ref->nodeface.size() * sizeof(int32_t)},
       {s->J, J.data(), J.size() * sizeof(double)},
       {s->mass, ref->mass.data(), ref->mass.size() * sizeof(double)},
   };
@@ -484,6 +487,7 @@ static dgw::StepArgs base_args(dg_solver* s) {
   a.LT = s->LT;
   a.fmask = s->fmask;
   a.perm = s->perm;
+  a.nodeface = s->nodeface;
   a.xcd_remap = s->xcd_remap;
   return a;
 }
@@ -583,6 +587,7 @@ dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* byt
   else if (key == "conn") { src = s->conn; n = K * 4 * sizeof(int32_t); }
   else if (key == "fmask") { src = s->fmask; n = 4 * static_cast<size_t>(s->Nfp) * sizeof(int32_t); }
   else if (key == "perm") { src = s->perm; n = 6 * static_cast<size_t>(s->Nfp) * sizeof(int32_t); }
+  else if (key == "nodeface") { src = s->nodeface; n = 3 * static_cast<size_t>(s->Np) * sizeof(int32_t); }
   else if (key == "DT") { src = s->DT; n = 3 * static_cast<size_t>(s->Np) * s->Np * sizeof(float); }
   else if (key == "LT") { src = s->LT; n = 4 * static_cast<size_t>(s->Nfp) * s->Np * sizeof(float); }
   else if (key == "traces") { src = s->qf[s->cur]; n = trace_count(s) * sizeof(float); }

@@ -26,6 +26,7 @@ struct RefElement {
   std::vector<double> lift;    // [Np][4*Nfp]
   std::vector<int32_t> fmask;  // [4][Nfp]
   std::vector<int32_t> perm;   // [6][Nfp]
+  std::vector<int32_t> nodeface;  // [Np][3] face slots f*Nfp+j holding node n, -1 padded
 };
 
 // Builds (and caches) the reference element; returns nullptr for bad N.

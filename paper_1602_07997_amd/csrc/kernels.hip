@@ -2,19 +2,19 @@
 //
 // One fused kernel per time step (Sec. 3.2's volume, surface and update
 // kernels merged): a workgroup owns a tile of KT consecutive elements and
-//   P0  stages the tile's fields, inverse Jacobians, coefficients and face
-//       connectivity in LDS (contiguous, coalesced loads);
-//   P1  forms the per-node geometric combinations of the volume term
-//       (acoustic U_j = sum_i g_ij v_i, eq. (5); elastic S_il = sum_j g_jl s_ij)
-//       and, at every face node, gathers the neighbour's traces from the
-//       previous step's trace buffer and evaluates the upwind penalty times
-//       Fscale (Sec. 2.1);
-//   P2  node per thread: the six (acoustic) or eighteen (elastic) Np x Np
-//       matrix-vector products with D_j, the merged LIFT product, the
-//       coefficient combinations of eqs. (5)-(6) / the elastic right-hand
-//       side, and the AB3 update of eq. (4); writes q^{m+1} and r^m;
-//   P3  writes the updated fields' own traces (acoustic p and n.v, elastic v
-//       and s n) to the other trace buffer.
+//   A  issues every global load at once: the neighbour traces of its
+//      face-node items (gathered through the packed connectivity word and the
+//      face-node permutation), the AB3 history of its node items, and the
+//      tile's fields, inverse Jacobians and coefficients (into LDS);
+//   B  forms the per-node geometric combinations of the volume term
+//      (acoustic U_j = sum_i g_ij v_i, eq. (5); elastic S_il = sum_j g_jl s_ij)
+//      and, at every face node, the upwind penalty of Sec. 2.1 times Fscale;
+//   C  node per thread: the six (acoustic) or eighteen (elastic) Np x Np
+//      matrix-vector products with D_j, the merged LIFT product, the
+//      coefficient combinations of eqs. (5)-(6) / the elastic right-hand
+//      side, and the AB3 update of eq. (4); writes q^{m+1}, r^m and the own
+//      traces (acoustic p and n.v, elastic v and s n) of the faces the node
+//      lies on into the other trace buffer.
 // Traces are double-buffered, so no element reads a trace written in the
 // same launch; every element's fields are read and written only by its own
 // workgroup.
@@ -89,39 +89,107 @@ __device__ __forceinline__ int64_t tile_of_block(int xcd_remap) {
   return (b % 8) * per + b / 8;
 }
 
+// Number of lifted scalars per face node: acoustic (Fscale*penalty for p,
+// scalar velocity penalty along n), elastic (k_p a_p, k_s a_s, vector a_s),
+// each times Fscale.  The normal and the per-face constants are applied after
+// the lift, so the merged LIFT product runs on 2 (acoustic) / 5 (elastic)
+// columns per element instead of 4 / 9.
+template <int PHYS>
+struct LiftCols;
+template <>
+struct LiftCols<0> {
+  static constexpr int NL = 2;
+};
+template <>
+struct LiftCols<1> {
+  static constexpr int NL = 5;
+};
+
 template <int N, int PHYS>
 __global__ void __launch_bounds__(kThreads)
 dg_step_kernel(StepArgs a) {
   constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP, NFN = 4 * NFP;
   constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT, NAUX = Phys<PHYS>::NAUX;
   constexpr int CB = Phys<PHYS>::CB;
+  constexpr int NL = LiftCols<PHYS>::NL;
   constexpr int KT = Tile<N, PHYS>::KT;
+  constexpr int NIT = (KT * NP + kThreads - 1) / kThreads;   // node items per thread
+  constexpr int FIT = (KT * NFN + kThreads - 1) / kThreads;  // face-node items per thread
 
   __shared__ float s_q[KT * NF * NP];
-  __shared__ float s_qn[KT * NF * NP];
   __shared__ float s_aux[KT * NAUX * NP];
-  __shared__ float s_flux[KT * NF * NFN];
+  __shared__ float s_lift[KT * NL * NFN];
   __shared__ float s_g[KT * 9];
   __shared__ float s_cf[KT * CB];
-  __shared__ int s_conn[KT * 4];
+  __shared__ float s_nrm[KT * 4 * 3];
 
   const int64_t tile = tile_of_block(a.xcd_remap);
   const int64_t e0 = tile * KT;
   if (e0 >= a.K) return;  // whole workgroup exits together
   const int ne = static_cast<int>((a.K - e0) < KT ? (a.K - e0) : KT);
   const int tid = threadIdx.x;
+  const bool step = (a.mode == kStepMode);
 
-  // ---- P0: stage the tile ------------------------------------------------
+  // ---- phase A: issue every global load before the first barrier ----------
+  // neighbour traces of this thread's face-node items, straight from the
+  // connectivity word (no LDS round trip)
+  int word[FIT];
+  float nbt[FIT][NT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    word[t] = 7;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) nbt[t][c] = 0.0f;
+    if (i < ne * NFN) {
+      const int e = i / NFN, fn = i - e * NFN;
+      const int f = fn / NFP, j = fn - f * NFP;
+      const int w = a.conn[(e0 + e) * 4 + f];
+      word[t] = w;
+      if ((w & 7) != 7) {
+        const int64_t kn = static_cast<int64_t>(w >> 5);
+        const int fnb = (w >> 3) & 3;
+        const int jn = a.perm[(w & 7) * NFP + j];
+        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) nbt[t][c] = tr[c * NFP];
+      }
+    }
+  }
+  // AB3 history of this thread's node items
+  float h1[NIT][NF], h2[NIT][NF];
+  const bool use1 = step && (a.c1 != 0.0f), use2 = step && (a.c2 != 0.0f);
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i < ne * NP) {
+      const int e = i / NP, n = i - e * NP;
+      const int64_t base = (e0 + e) * NF * NP + n;
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        h1[t][c] = use1 ? a.r1[base + c * NP] : 0.0f;
+        h2[t][c] = use2 ? a.r2[base + c * NP] : 0.0f;
+      }
+    }
+  }
+  // the tile's fields, inverse Jacobians and coefficients into LDS
   {
     const float* src = a.q_in + e0 * NF * NP;
-    for (int i = tid; i < ne * NF * NP; i += kThreads) s_q[i] = src[i];
+    const int cnt = ne * NF * NP;
+    if (((e0 * NF * NP) & 3) == 0) {
+      const float4* src4 = reinterpret_cast<const float4*>(src);
+      float4* dst4 = reinterpret_cast<float4*>(s_q);
+      for (int i = tid; i < cnt / 4; i += kThreads) dst4[i] = src4[i];
+      for (int i = (cnt / 4) * 4 + tid; i < cnt; i += kThreads) s_q[i] = src[i];
+    } else {
+      for (int i = tid; i < cnt; i += kThreads) s_q[i] = src[i];
+    }
     for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
     for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
-    for (int i = tid; i < ne * 4; i += kThreads) s_conn[i] = a.conn[e0 * 4 + i];
   }
   __syncthreads();
 
-  // ---- P1a: geometric combinations for the volume term ------------------
+  // ---- phase B: volume combinations and upwind penalties -----------------
   for (int i = tid; i < ne * NP; i += kThreads) {
     const int e = i / NP, n = i - e * NP;
     const float* G = s_g + 9 * e;
@@ -132,7 +200,6 @@ dg_step_kernel(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) ax[j * NP + n] = G[0 * 3 + j] * v0 + G[1 * 3 + j] * v1 + G[2 * 3 + j] * v2;
     } else {
-      // S_il = sum_j g_jl s_ij  (stress divergence in reference directions)
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
         const float si0 = qe[(3 + voigt(ii, 0)) * NP + n];
@@ -144,79 +211,52 @@ dg_step_kernel(StepArgs a) {
       }
     }
   }
-
-  // ---- P1b: traces, upwind penalty, times Fscale -------------------------
-  for (int i = tid; i < ne * NFN; i += kThreads) {
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i >= ne * NFN) continue;
     const int e = i / NFN, fn = i - e * NFN;
     const int f = fn / NFP, j = fn - f * NFP;
     float nrm[3], fs;
     face_normal(s_g + 9 * e, f, nrm, fs);
+    if (j == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s_nrm[(e * 4 + f) * 3 + d] = nrm[d];
+    }
     const int vn = a.fmask[f * NFP + j];
     const float* qe = s_q + e * NF * NP;
     const float* cf = s_cf + e * CB;
-    const int word = s_conn[e * 4 + f];
-    const int orient = word & 7;
-    float* fl = s_flux + e * NF * NFN;
+    const bool wall = (word[t] & 7) == 7;
+    float* lf = s_lift + e * NL * NFN + fn;
     if constexpr (PHYS == 0) {
       const float pM = qe[vn];
       const float vnM = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
-      const float rc2 = cf[0], c = cf[3], ZM = cf[2];
-      float pP, vnP, ZP;
-      if (orient == 7) {  // rigid wall: mirror state
-        pP = pM;
-        vnP = -vnM;
-        ZP = ZM;
-      } else {
-        const int64_t kn = static_cast<int64_t>(word >> 5);
-        const int fnb = (word >> 3) & 3;
-        const int jn = a.perm[orient * NFP + j];
-        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP;
-        pP = tr[jn];
-        vnP = -tr[NFP + jn];  // neighbour stored v.n with its own normal
-        ZP = cf[4 + f];
-      }
-      const float jp = 0.5f * (pP - pM);
-      const float jv = 0.5f * (vnP - vnM);
+      const float ZM = cf[2];
+      // rigid wall: mirror state p+ = p-, v.n+ = -v.n-
+      const float pP = wall ? pM : nbt[t][0];
+      const float vnP = wall ? -vnM : -nbt[t][1];  // neighbour stored v.n with its own normal
+      const float ZP = wall ? ZM : cf[4 + f];
       const float kc = 2.0f / (ZM + ZP);
-      const float alpha = jp - ZP * jv;
-      const float fp = fs * rc2 * kc * alpha;
-      const float fv = -fs * c * kc * alpha;
-      fl[0 * NFN + fn] = fp;
-      fl[1 * NFN + fn] = fv * nrm[0];
-      fl[2 * NFN + fn] = fv * nrm[1];
-      fl[3 * NFN + fn] = fv * nrm[2];
+      const float alpha = 0.5f * (pP - pM) - ZP * 0.5f * (vnP - vnM);
+      lf[0] = fs * cf[0] * kc * alpha;   // lifted into r^p
+      lf[NFN] = -fs * cf[3] * kc * alpha;  // lifted, then times n, into r^v
     } else {
-      const float lam = cf[0], mu = cf[1];
-      const float ZpM = cf[3], ZsM = cf[4], cp = cf[5], cs = cf[6];
-      float vM[3], tM[3];
+      float vM[3], tM[3], vP[3], tP[3];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) vM[ii] = qe[ii * NP + vn];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
         tM[ii] = qe[(3 + voigt(ii, 0)) * NP + vn] * nrm[0] + qe[(3 + voigt(ii, 1)) * NP + vn] * nrm[1] +
                  qe[(3 + voigt(ii, 2)) * NP + vn] * nrm[2];
-      float vP[3], tP[3], ZpP, ZsP;
-      if (orient == 7) {  // traction-free wall: mirror state
+      // traction-free wall: mirror state v+ = v-, (s n)+ = -(s n)-
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          vP[ii] = vM[ii];
-          tP[ii] = -tM[ii];
-        }
-        ZpP = ZpM;
-        ZsP = ZsM;
-      } else {
-        const int64_t kn = static_cast<int64_t>(word >> 5);
-        const int fnb = (word >> 3) & 3;
-        const int jn = a.perm[orient * NFP + j];
-        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP;
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          vP[ii] = tr[ii * NFP + jn];
-          tP[ii] = -tr[(3 + ii) * NFP + jn];  // neighbour stored s n with its own normal
-        }
-        ZpP = cf[8 + f];
-        ZsP = cf[12 + f];
+      for (int ii = 0; ii < 3; ++ii) {
+        vP[ii] = wall ? vM[ii] : nbt[t][ii];
+        tP[ii] = wall ? -tM[ii] : -nbt[t][3 + ii];  // neighbour stored s n with its own normal
       }
+      const float ZpM = cf[3], ZsM = cf[4];
+      const float ZpP = wall ? ZpM : cf[8 + f];
+      const float ZsP = wall ? ZsM : cf[12 + f];
       float jv[3], jt[3];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
@@ -227,51 +267,40 @@ dg_step_kernel(StepArgs a) {
       const float jsnn = jt[0] * nrm[0] + jt[1] * nrm[1] + jt[2] * nrm[2];
       const float kp = 2.0f / (ZpM + ZpP);
       const float ks = 2.0f / (ZsM + ZsP);
-      const float ap = jsnn + ZpP * jvn;
-      const float as = jsnn + ZsP * jvn;
-      float asv[3];
+      lf[0] = fs * kp * (jsnn + ZpP * jvn);  // k_p alpha_p
+      lf[NFN] = fs * ks * (jsnn + ZsP * jvn);  // k_s alpha_s
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) asv[ii] = jt[ii] + ZsP * jv[ii];
-      const float pvn = kp * ap * cp - ks * as * cs;
-      const float pvs = ks * cs;
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) fl[ii * NFN + fn] = fs * (pvn * nrm[ii] + pvs * asv[ii]);
-      const float A = kp * ap * lam;
-      const float B = 2.0f * (kp * ap - ks * as) * mu;
-      const float C = ks * mu;
-      // Voigt order (00, 11, 22, 12, 02, 01)
-      const int vi[6] = {0, 1, 2, 1, 0, 0};
-      const int vj[6] = {0, 1, 2, 2, 2, 1};
-#pragma unroll
-      for (int v = 0; v < 6; ++v) {
-        const int ii = vi[v], jj = vj[v];
-        float ps = B * nrm[ii] * nrm[jj] + C * (nrm[ii] * asv[jj] + asv[ii] * nrm[jj]);
-        if (ii == jj) ps += A;
-        fl[(3 + v) * NFN + fn] = fs * ps;
-      }
+      for (int ii = 0; ii < 3; ++ii) lf[(2 + ii) * NFN] = fs * (jt[ii] + ZsP * jv[ii]);  // vector alpha_s
     }
   }
   __syncthreads();
 
-  // ---- P2: node per thread: D_j products, LIFT, combinations, AB3 --------
-  const bool step = (a.mode == kStepMode);
-  for (int i = tid; i < ne * NP; i += kThreads) {
+  // ---- phase C: node per thread: D_j products, LIFT, combinations, AB3 ----
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i >= ne * NP) continue;
     const int e = i / NP, n = i - e * NP;
     const float* G = s_g + 9 * e;
     const float* qe = s_q + e * NF * NP;
     const float* ax = s_aux + e * NAUX * NP;
-    const float* fl = s_flux + e * NF * NFN;
+    const float* lf = s_lift + e * NL * NFN;
     const float* cf = s_cf + e * CB;
+    const float* nr = s_nrm + e * 12;
     float r[NF];
-    // merged LIFT of all penalty components
-    float lift[NF];
+    // per-face lifts of the penalty scalars
+    float L[4][NL];
 #pragma unroll
-    for (int c = 0; c < NF; ++c) lift[c] = 0.0f;
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+      for (int c = 0; c < NL; ++c) L[f][c] = 0.0f;
 #pragma unroll 4
-    for (int fm = 0; fm < NFN; ++fm) {
-      const float l = a.LT[fm * NP + n];
+      for (int j = 0; j < NFP; ++j) {
+        const int fm = f * NFP + j;
+        const float l = a.LT[fm * NP + n];
 #pragma unroll
-      for (int c = 0; c < NF; ++c) lift[c] += l * fl[c * NFN + fm];
+        for (int c = 0; c < NL; ++c) L[f][c] += l * lf[c * NFN + fm];
+      }
     }
     if constexpr (PHYS == 0) {
       float T0 = 0.f, T1 = 0.f, T2 = 0.f, dv = 0.f;
@@ -287,10 +316,12 @@ dg_step_kernel(StepArgs a) {
         dv += d0 * ax[m] + d1 * ax[NP + m] + d2 * ax[2 * NP + m];
       }
       const float rc2 = cf[0], irho = cf[1];
-      r[0] = -rc2 * dv + lift[0];
+      r[0] = -rc2 * dv + (L[0][0] + L[1][0] + L[2][0] + L[3][0]);
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
-        r[1 + ii] = -irho * (G[3 * ii + 0] * T0 + G[3 * ii + 1] * T1 + G[3 * ii + 2] * T2) + lift[1 + ii];
+        r[1 + ii] = -irho * (G[3 * ii + 0] * T0 + G[3 * ii + 1] * T1 + G[3 * ii + 2] * T2) +
+                    (nr[0 * 3 + ii] * L[0][1] + nr[1 * 3 + ii] * L[1][1] + nr[2 * 3 + ii] * L[2][1] +
+                     nr[3 * 3 + ii] * L[3][1]);
     } else {
       float Dv[3][3], dS[3];
 #pragma unroll
@@ -314,7 +345,7 @@ dg_step_kernel(StepArgs a) {
           }
         }
       }
-      const float lam = cf[0], mu = cf[1], irho = cf[2];
+      const float lam = cf[0], mu = cf[1], irho = cf[2], cp = cf[5], cs = cf[6];
       float gv[3][3];  // d v_i / d x_j = sum_l g_jl D_l v_i
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
@@ -322,59 +353,75 @@ dg_step_kernel(StepArgs a) {
         for (int jj = 0; jj < 3; ++jj)
           gv[ii][jj] = G[3 * jj + 0] * Dv[ii][0] + G[3 * jj + 1] * Dv[ii][1] + G[3 * jj + 2] * Dv[ii][2];
       const float divv = gv[0][0] + gv[1][1] + gv[2][2];
+      // surface: velocity  sum_f [n (cp L1 - cs L2) + ks cs L3]
+      //          stress    sum_f [lam L1 I + 2 mu n n^T (L1 - L2) + mu ks (n L3^T + L3 n^T)]
+      float sv[3] = {0.f, 0.f, 0.f};
+      float ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float l1sum = 0.f;
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) r[ii] = irho * dS[ii] + lift[ii];
+      for (int f = 0; f < 4; ++f) {
+        const float ks = 2.0f / (cf[4] + cf[12 + f]);
+        const float n0 = nr[f * 3 + 0], n1 = nr[f * 3 + 1], n2 = nr[f * 3 + 2];
+        const float nf[3] = {n0, n1, n2};
+        const float a1 = cp * L[f][0] - cs * L[f][1];
+        const float b2 = 2.0f * mu * (L[f][0] - L[f][1]);
+        const float c3 = mu * ks;
+        l1sum += L[f][0];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) sv[ii] += nf[ii] * a1 + ks * cs * L[f][2 + ii];
+        const int vi[6] = {0, 1, 2, 1, 0, 0};
+        const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+          const int ii = vi[v], jj = vj[v];
+          ss[v] += b2 * nf[ii] * nf[jj] + c3 * (nf[ii] * L[f][2 + jj] + L[f][2 + ii] * nf[jj]);
+        }
+      }
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) r[ii] = irho * dS[ii] + sv[ii];
       const int vi[6] = {0, 1, 2, 1, 0, 0};
       const int vj[6] = {0, 1, 2, 2, 2, 1};
 #pragma unroll
       for (int v = 0; v < 6; ++v) {
         const int ii = vi[v], jj = vj[v];
-        float val = mu * (gv[ii][jj] + gv[jj][ii]);
-        if (ii == jj) val += lam * divv;
-        r[3 + v] = val + lift[3 + v];
+        float val = mu * (gv[ii][jj] + gv[jj][ii]) + ss[v];
+        if (ii == jj) val += lam * (divv + l1sum);
+        r[3 + v] = val;
       }
     }
     const int64_t base = (e0 + e) * NF * NP + n;
-    if (step) {
-#pragma unroll
-      for (int c = 0; c < NF; ++c) {
-        const int64_t idx = base + c * NP;
-        float upd = a.c0 * r[c];
-        if (a.c1 != 0.0f) upd += a.c1 * a.r1[idx];
-        if (a.c2 != 0.0f) upd += a.c2 * a.r2[idx];
-        const float qn = qe[c * NP + n] + upd;
-        a.q_out[idx] = qn;
-        a.r_out[idx] = r[c];
-        s_qn[(e * NF + c) * NP + n] = qn;
-      }
-    } else {
+    if (!step) {
 #pragma unroll
       for (int c = 0; c < NF; ++c) a.r_out[base + c * NP] = r[c];
+      continue;
     }
-  }
-  if (!step) return;
-  __syncthreads();
-
-  // ---- P3: own traces of the updated fields -------------------------------
-  for (int i = tid; i < ne * NFN; i += kThreads) {
-    const int e = i / NFN, fn = i - e * NFN;
-    const int f = fn / NFP, j = fn - f * NFP;
-    float nrm[3], fs;
-    face_normal(s_g + 9 * e, f, nrm, fs);
-    const int vn = a.fmask[f * NFP + j];
-    const float* qe = s_qn + e * NF * NP;
-    float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP;
-    if constexpr (PHYS == 0) {
-      tr[j] = qe[vn];
-      tr[NFP + j] = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
-    } else {
+    float qn[NF];
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) tr[ii * NFP + j] = qe[ii * NP + vn];
+    for (int c = 0; c < NF; ++c) {
+      qn[c] = qe[c * NP + n] + a.c0 * r[c] + a.c1 * h1[t][c] + a.c2 * h2[t][c];
+      a.q_out[base + c * NP] = qn[c];
+      a.r_out[base + c * NP] = r[c];
+    }
+    // own traces of the updated fields at every face this node lies on
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii)
-        tr[(3 + ii) * NFP + j] = qe[(3 + voigt(ii, 0)) * NP + vn] * nrm[0] +
-                                 qe[(3 + voigt(ii, 1)) * NP + vn] * nrm[1] +
-                                 qe[(3 + voigt(ii, 2)) * NP + vn] * nrm[2];
+    for (int s = 0; s < 3; ++s) {
+      const int fj = a.nodeface[n * 3 + s];
+      if (fj < 0) break;
+      const int f = fj / NFP, j = fj - f * NFP;
+      const float n0 = nr[f * 3 + 0], n1 = nr[f * 3 + 1], n2 = nr[f * 3 + 2];
+      float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP + j;
+      if constexpr (PHYS == 0) {
+        tr[0] = qn[0];
+        tr[NFP] = n0 * qn[1] + n1 * qn[2] + n2 * qn[3];
+      } else {
+        tr[0] = qn[0];
+        tr[NFP] = qn[1];
+        tr[2 * NFP] = qn[2];
+        // s n with Voigt (11, 22, 33, 23, 13, 12)
+        tr[3 * NFP] = qn[3] * n0 + qn[8] * n1 + qn[7] * n2;
+        tr[4 * NFP] = qn[8] * n0 + qn[4] * n1 + qn[6] * n2;
+        tr[5 * NFP] = qn[7] * n0 + qn[6] * n1 + qn[5] * n2;
+      }
     }
   }
 }

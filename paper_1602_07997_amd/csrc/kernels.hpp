@@ -24,6 +24,7 @@ struct StepArgs {
   const float* LT;       // [4*NFP][NP] LT[fm][n] = L[n][fm]
   const int32_t* fmask;  // [4][NFP]
   const int32_t* perm;   // [6][NFP]
+  const int32_t* nodeface;  // [NP][3] face slots f*NFP+j containing node n, -1 padded
   float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
   int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))
   int xcd_remap;         // map consecutive tiles onto one XCD

@@ -427,6 +427,16 @@ std::unique_ptr<RefElement> build(int N) {
   ref->lift.assign(Lift.begin(), Lift.end());
   ref->nodes.assign(nodes.begin(), nodes.end());
 
+  // for every volume node, the face slots (f*Nfp + j) it occupies
+  ref->nodeface.assign(static_cast<size_t>(Np) * 3, -1);
+  for (int f = 0; f < 4; ++f)
+    for (int j = 0; j < Nfp; ++j) {
+      const int n = ref->fmask[f * Nfp + j];
+      int s = 0;
+      while (ref->nodeface[3 * n + s] >= 0) ++s;  // a node lies on at most three faces
+      ref->nodeface[3 * n + s] = f * Nfp + j;
+    }
+
   // face-node permutations for the six relative orientations
   ref->perm.resize(6 * Nfp);
   std::map<std::pair<int, int>, int> fidx;

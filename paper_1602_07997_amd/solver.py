@@ -201,7 +201,7 @@ class DGSolver:
         """Copy of an internal device buffer (see dg_debug_buffer)."""
         nbytes = C.c_size_t(0)
         check(lib.dg_debug_buffer(self._h, name.encode(), None, C.byref(nbytes)), "dg_debug_buffer")
-        dtype = np.int32 if name in ("conn", "fmask", "perm") else np.float32
+        dtype = np.int32 if name in ("conn", "fmask", "perm", "nodeface") else np.float32
         out = np.zeros(nbytes.value // 4, dtype=dtype)
         check(
             lib.dg_debug_buffer(self._h, name.encode(), out.ctypes.data_as(C.c_void_p), C.byref(nbytes)),
