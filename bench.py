@@ -8,7 +8,13 @@ two-layer (rho, c) = (1, 1) / (2, 1.5) by element centroid, Gaussian pressure
 pulse.  One benchmark step = one AB3 step (the fused volume + flux + LIFT +
 update kernel) on each of the eight meshes; value = total node updates / s.
 ``--config elastic`` runs the elastic sweep (log-uniform rho, lambda, mu in
-[0.5, 2], seed 1, Gaussian velocity pulse).
+[0.5, 2], seed 1, Gaussian velocity pulse).  ``--config batched`` runs 64
+independent acoustic meshes (K log-uniform in [2e3, 2e5] snapped to Kuhn
+boxes, N uniform in {2..6}, seed 2, per-mesh jitter and log-uniform
+coefficients), each member's kernel variant picked by the autotuner, all
+advanced together by the batch (one launch per degree/variant group, six-step
+HIP graph replays); the same meshes stepped one by one with the plain
+node-per-thread kernel are timed beside it.
 
 Prints one JSON line with the throughput, a roofline object for the kernel
 that takes the largest share of the time (algorithmic bytes and flops per
@@ -99,7 +105,7 @@ def init_fields(physics, xyz):
     return np.ascontiguousarray(np.moveaxis(f, 0, 1)).astype(np.float32)
 
 
-def run_gpu(physics, degrees, steps, warmup, log):
+def run_gpu(physics, degrees, steps, warmup, log, variant="valu"):
     import torch
 
     from paper_1602_07997_amd import DGSolver
@@ -109,11 +115,12 @@ def run_gpu(physics, degrees, steps, warmup, log):
     for N in degrees:
         n, mesh, coef = workload(physics, N)
         s = DGSolver(physics, N, mesh.elem_xyz, mesh.elem_topo, stream=stream)
+        s.variant = pick_variant(physics, N, variant)
         s.set_coefficients(torch.tensor(coef, dtype=torch.float32, device="cuda"))
         s.set_fields(torch.tensor(init_fields(physics, s.node_coordinates()), device="cuda"))
         dt = di.time_step(mesh, N, di.max_wave_speed(coef, physics))
         s.step(2, dt)  # Euler and two-step start-up
-        cases.append({"N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt})
+        cases.append({"N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt, "variant": s.variant})
         log(f"  set up {physics} N={N}: n={n} K={mesh.K} nodes={mesh.K * s.Np}")
     for c in cases:
         c["solver"].step(warmup, c["dt"])
@@ -141,6 +148,14 @@ def run_gpu(physics, degrees, steps, warmup, log):
         c["solver"].close()
         del c["solver"]
     return cases, wall
+
+
+def pick_variant(physics: str, N: int, requested: str) -> str:
+    """Kernel variant for one degree: 'valu', 'mfma', or 'auto' (MFMA where it
+    is built and N >= 3, the node-per-thread kernel otherwise)."""
+    if requested != "auto":
+        return requested
+    return "mfma" if (physics == "acoustic" and N >= 3) else "valu"
 
 
 def run_cpu_baseline(physics, degrees, steps, log):
@@ -183,14 +198,126 @@ def run_cpu_baseline(physics, degrees, steps, log):
     }
 
 
+def run_batched(steps, warmup, log, count=64, seed=2):
+    import torch
+
+    from paper_1602_07997_amd import DGBatch, DGSolver
+
+    recipe = di.batch_recipe(count=count, seed=seed)
+    stream = torch.cuda.Stream()
+    members = []
+    with torch.cuda.stream(stream):
+        for r in recipe:
+            mesh = di.kuhn_box(r["n"], jitter=0.1, seed=r["mesh_seed"])
+            coef = di.acoustic_loguniform(mesh, r["coef_seed"]).astype(np.float32)
+            s = DGSolver("acoustic", r["N"], mesh.elem_xyz, mesh.elem_topo, stream=stream)
+            s.set_coefficients(torch.tensor(coef, device="cuda"))
+            s.set_fields(torch.tensor(init_fields("acoustic", s.node_coordinates()), device="cuda"))
+            dt = di.time_step(mesh, r["N"], di.max_wave_speed(coef.astype(np.float64), "acoustic"))
+            members.append({"solver": s, "dt": dt, "N": r["N"], "K": mesh.K, "Np": s.Np})
+    total_nodes = sum(m["K"] * m["Np"] for m in members)
+    log(f"  batched: {count} meshes, {sum(m['K'] for m in members)} elements, {total_nodes} nodes")
+    dts = [m["dt"] for m in members]
+
+    def timed(fn, nsteps):
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        a.record(stream)
+        fn(nsteps)
+        z.record(stream)
+        z.synchronize()
+        return a.elapsed_time(z) * 1e-3, time.perf_counter() - t0
+
+    # plain FP32 path: node-per-thread kernel, one launch per mesh and step
+    for m in members:
+        m["solver"].step(2, m["dt"])
+
+    def one_by_one(n):
+        for _ in range(n):
+            for m in members:
+                m["solver"].step(1, m["dt"])
+
+    one_by_one(warmup)
+    t_plain, _ = timed(one_by_one, steps)
+    log(f"  one mesh at a time, node-per-thread: {t_plain / steps * 1e3:.3f} ms/step")
+    # autotuned variant per member, then the batch
+    t0 = time.perf_counter()
+    choice = {}
+    for m in members:
+        m["solver"].autotune(3, m["dt"])
+        choice.setdefault((m["N"], m["solver"].variant), 0)
+        choice[(m["N"], m["solver"].variant)] += 1
+    log(f"  autotune {time.perf_counter() - t0:.1f} s: {sorted(choice.items())}")
+    batch = DGBatch([m["solver"] for m in members], stream=stream, graph=True)
+    nsteps = 6 * max(1, steps // 6)
+    batch.step(6 * max(1, warmup // 6), dts)
+    t_batch, wall = timed(lambda n: batch.step(n, dts), nsteps)
+    log(f"  batched + autotuned + graph: {t_batch / nsteps * 1e3:.3f} ms/step")
+    energies = [m["solver"].energy() for m in members]
+    if not all(math.isfinite(e) for e in energies):
+        raise RuntimeError("non-finite energy in the batched run")
+    groups = batch.groups()
+    batch.close()
+    nbytes = sum(algorithmic_model("acoustic", m["N"])[0] * m["K"] for m in members)
+    for m in members:
+        m["solver"].close()
+    return {
+        "total_nodes": total_nodes, "steps": nsteps, "t_batch": t_batch, "wall": wall, "t_plain": t_plain,
+        "plain_steps": steps, "alg_bytes_per_step": nbytes, "groups": groups,
+        "choice": {f"N={k[0]}:{k[1]}": v for k, v in sorted(choice.items())},
+    }
+
+
+def main_batched(args, log):
+    r = run_batched(args.steps, args.warmup, log)
+    step_s = r["t_batch"] / r["steps"]
+    plain_s = r["t_plain"] / r["plain_steps"]
+    achieved = r["alg_bytes_per_step"] / step_s
+    out = {
+        "metric": METRIC,
+        "value": r["total_nodes"] / step_s,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "64 independent acoustic meshes, K log-uniform in [2e3, 2e5] (Kuhn boxes), N uniform in "
+            "{2..6}, seed 2; autotuned variant per mesh, batched launches replayed from a six-step HIP graph",
+            "physics": "acoustic",
+            "total_nodes": r["total_nodes"],
+            "groups": r["groups"],
+            "autotune_choice": r["choice"],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": None,
+            "kernel": "whole batched step (all group launches of one step)",
+        },
+        "cpu_baseline": None,
+        "plain_fp32_one_by_one": {"node_updates_per_s": r["total_nodes"] / plain_s, "ms_per_step": plain_s * 1e3},
+        "speedup_vs_plain": plain_s / step_s,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", choices=["acoustic", "elastic"], default="acoustic")
+    ap.add_argument("--config", choices=["acoustic", "elastic", "batched"], default="acoustic")
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--variant", choices=["valu", "mfma", "auto"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument(
@@ -232,8 +359,10 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"copy calibration: 3 device copies of {args.copy_calibration_mib} MiB")
         del src, dst
+    if physics == "batched":
+        return main_batched(args, log)
     log(f"bench: {physics} sweep N={degrees}, {args.steps} timed steps, {args.warmup} warm-up")
-    cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log)
+    cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log, args.variant)
 
     per = []
     for c in cases:
@@ -247,7 +376,7 @@ def main(argv=None):
         frac = (t_hbm if bound == "hbm" else t_alu) / t
         per.append(
             {
-                "N": c["N"], "n": c["n"], "K": c["K"], "nodes": c["K"] * c["Np"],
+                "N": c["N"], "n": c["n"], "K": c["K"], "nodes": c["K"] * c["Np"], "variant": c["variant"],
                 "kernel_us": round(t * 1e6, 2), "kernel_us_min": round(c["kernel_s_min"] * 1e6, 2),
                 "node_updates_per_s": c["K"] * c["Np"] / t,
                 "alg_bytes_per_elem": nbytes, "alg_flops_per_elem": flops,
@@ -257,7 +386,7 @@ def main(argv=None):
             }
         )
         log(
-            f"  N={c['N']}: {t * 1e6:8.1f} us/step  {c['K'] * c['Np'] / t:.3e} node-upd/s  "
+            f"  N={c['N']} {c['variant']:4s}: {t * 1e6:8.1f} us/step  {c['K'] * c['Np'] / t:.3e} node-upd/s  "
             f"{bw / 1e9:7.1f} GB/s  {fl / 1e12:6.2f} TFLOP/s  {bound} frac {frac:.3f}"
         )
     total_nodes = sum(c["K"] * c["Np"] for c in cases)
@@ -272,7 +401,7 @@ def main(argv=None):
         roof = {"bound": "alu", "achieved": nf / t / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(physics, dom["N"])
-    roof["kernel"] = f"dg_step_kernel<N={dom['N']},{physics}>"
+    roof["kernel"] = f"{'dg_step_mfma_acoustic' if dom['variant'] == 'mfma' else 'dg_step_kernel'}<N={dom['N']},{physics}>"
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -310,3 +310,22 @@ def n_nodes(N: int) -> int:
 def paper_scale_n(N: int, target_nodes: float = 2.0e6) -> int:
     """Subcubes per edge so that 6 n^3 N_p is closest to ~2M nodes."""
     return int(round((target_nodes / (6.0 * n_nodes(N))) ** (1.0 / 3.0)))
+
+
+def batch_recipe(count: int = 64, seed: int = 2, k_lo: float = 2.0e3, k_hi: float = 2.0e5,
+                 degrees=(2, 3, 4, 5, 6), n_lo: int = 7, n_hi: int = 32):
+    """Independent meshes of uneven size and degree for batched stepping.
+
+    Per mesh: K drawn log-uniform on [k_lo, k_hi] and snapped to the nearest
+    Kuhn box 6 n^3 with n in [n_lo, n_hi]; degree uniform over `degrees`;
+    its own jitter and coefficient seeds.  Returns a list of dicts with keys
+    n, K, N, mesh_seed, coef_seed.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        k = float(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi))))
+        n = int(np.clip(round((k / 6.0) ** (1.0 / 3.0)), n_lo, n_hi))
+        N = int(rng.choice(np.asarray(degrees)))
+        out.append({"n": n, "K": 6 * n ** 3, "N": N, "mesh_seed": 1000 + i, "coef_seed": 2000 + i})
+    return out

@@ -137,6 +137,17 @@ void dg_destroy(dg_solver* s);
 /* Replace the stream used by later calls (hipStream_t, NULL = default). */
 dg_status dg_set_stream(dg_solver* s, void* stream);
 
+/* Kernel variant of the step (default DG_VARIANT_VALU).  Both compute the
+ * same right-hand side of eqs. (5)-(6) / the elastic system and the update of
+ * eq. (4); they differ in how the D_j and LIFT products run:
+ *   DG_VARIANT_VALU  node per thread, vector ALU (all physics and degrees);
+ *   DG_VARIANT_MFMA  16-element tiles on FP32 matrix cores (acoustic).
+ * Returns DG_E_UNSUPPORTED for a combination that is not built.            */
+#define DG_VARIANT_VALU 0
+#define DG_VARIANT_MFMA 1
+dg_status dg_set_variant(dg_solver* s, int variant);
+dg_status dg_get_variant(dg_solver* s, int* variant);
+
 /* Wait for all work queued by the solver. */
 dg_status dg_synchronize(dg_solver* s);
 
@@ -193,6 +204,62 @@ dg_status dg_energy(dg_solver* s, double* e);
  * size on return; nothing is copied when dst is NULL or *bytes is too small
  * on entry (DG_E_SHAPE).  Synchronises the solver's stream.               */
 dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* bytes);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel choice and batches of meshes.                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Time every kernel variant built for the solver's physics and degree on the
+ * solver's own mesh: `steps` steps of size dt each, after one untimed step,
+ * timed with HIP events on the solver's stream.  The state (fields, AB3
+ * history, traces, step index) is saved to temporary device memory before
+ * and restored after, so the call does not advance the solution; it
+ * synchronises.  The fastest variant becomes the solver's variant.
+ * us_per_step (host float64 [DG_NUM_VARIANTS], may be NULL) receives the
+ * microseconds per step of each variant, -1 where not built.  The choice of
+ * kernel per degree and mesh follows the observation of Sec. 4 that the best
+ * implementation strategy depends on the degree.  Errors: DG_E_STATE (no
+ * coefficients or fields), DG_E_ARG, DG_E_HIP.                              */
+#define DG_NUM_VARIANTS 2
+dg_status dg_autotune(dg_solver* s, int steps, double dt, double* us_per_step);
+
+typedef struct dg_batch dg_batch;
+
+/* A batch steps `count` independent solvers together: one kernel launch per
+ * (degree, variant) group and step, over a device work list of (member,
+ * element tile) pairs, instead of one launch per mesh.  members is a host
+ * array of distinct solvers of one physics created on the current device;
+ * the batch keeps the pointers (not ownership): every member must outlive
+ * the batch.  Each member keeps its own buffers, coefficients and variant
+ * (the groups are rebuilt when a member's variant changes).  `stream` is the
+ * hipStream_t all batched work runs on (NULL = default stream).  Device
+ * memory for the work lists and argument tables is allocated here.  Errors:
+ * DG_E_ARG (null, repeated or mixed-physics members), DG_E_HIP.             */
+dg_status dg_batch_create(dg_solver* const* members, int count, void* stream, dg_batch** out);
+
+/* Release the batch (synchronises its stream; members are untouched). */
+void dg_batch_destroy(dg_batch* b);
+
+/* Record six consecutive batched steps in a HIP graph and replay it for
+ * whole runs of six steps (enable = 1), or launch kernel by kernel (0, the
+ * default).  The graph holds kernel nodes only; it needs a non-NULL stream
+ * (DG_E_STATE otherwise).                                                    */
+dg_status dg_batch_set_graph(dg_batch* b, int enable);
+
+/* Advance every member by `nsteps` steps of eq. (4); dt is host float64
+ * [count], member i's step size.  Members still in the start-up (step index
+ * below 2) take that step with their own launch; once all are in the AB3
+ * regime the steps are batched.  Members may start at different step
+ * indices.  Asynchronous on the batch's stream.  Errors: DG_E_ARG, DG_E_STATE
+ * (a member without coefficients or fields), DG_E_HIP.                      */
+dg_status dg_batch_step(dg_batch* b, int nsteps, const double* dt);
+
+/* Shape of the batch.  On return *ngroups is the number of launch groups;
+ * order, variant (host int32) and tiles (host int64, workgroups of the
+ * group's launch) receive one entry per group.  When any array is non-NULL,
+ * *ngroups on entry is their capacity (DG_E_SHAPE if too small); call with
+ * NULL arrays first to ask for the count.                                   */
+dg_status dg_batch_groups(dg_batch* b, int* ngroups, int32_t* order, int32_t* variant, int64_t* tiles);
 
 #ifdef __cplusplus
 }

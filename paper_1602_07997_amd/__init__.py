@@ -6,7 +6,7 @@ library is loaded on first use of any of the names below, so that the build
 module can run before it exists.
 """
 
-__all__ = ["DGSolver", "mesh_connectivity", "ref_sizes", "reference_operators"]
+__all__ = ["DGBatch", "DGSolver", "mesh_connectivity", "ref_sizes", "reference_operators"]
 
 
 def __getattr__(name):

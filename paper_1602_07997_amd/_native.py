@@ -23,6 +23,9 @@ DG_E_UNSUPPORTED = -6
 DG_E_UNSTABLE = -7
 DG_ACOUSTIC = 0
 DG_ELASTIC = 1
+DG_VARIANT_VALU = 0
+DG_VARIANT_MFMA = 1
+DG_NUM_VARIANTS = 2
 
 STATUS_NAMES = {
     DG_OK: "DG_OK",
@@ -68,6 +71,8 @@ SIGNATURES = {
     "dg_destroy": (None, [_p]),
     "dg_set_stream": (C.c_int, [_p, _p]),
     "dg_synchronize": (C.c_int, [_p]),
+    "dg_set_variant": (C.c_int, [_p, C.c_int]),
+    "dg_get_variant": (C.c_int, [_p, _ip]),
     "dg_node_coordinates": (C.c_int, [_p, _dp]),
     "dg_set_coefficients": (C.c_int, [_p, _p]),
     "dg_set_fields": (C.c_int, [_p, _p]),
@@ -79,6 +84,12 @@ SIGNATURES = {
     "dg_rhs": (C.c_int, [_p, _p, _p]),
     "dg_energy": (C.c_int, [_p, _dp]),
     "dg_debug_buffer": (C.c_int, [_p, C.c_char_p, _p, C.POINTER(C.c_size_t)]),
+    "dg_autotune": (C.c_int, [_p, C.c_int, C.c_double, _dp]),
+    "dg_batch_create": (C.c_int, [C.POINTER(_p), C.c_int, _p, C.POINTER(_p)]),
+    "dg_batch_destroy": (None, [_p]),
+    "dg_batch_set_graph": (C.c_int, [_p, C.c_int]),
+    "dg_batch_step": (C.c_int, [_p, C.c_int, _dp]),
+    "dg_batch_groups": (C.c_int, [_p, _ip, _i32p, _i32p, _i64p]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

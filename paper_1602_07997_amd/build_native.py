@@ -17,6 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdgwave.so")
 ARCH = "gfx950"
+ROCM_INCLUDE = "/opt/rocm/include"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 # Device code: gfx950 only; packed FP32 instructions disabled.
@@ -32,9 +33,11 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON]
     if src.endswith(".hip"):
-        cmd += ["-x", "hip", *DEVICE]
+        cmd = [_hipcc(), *COMMON, "-x", "hip", *DEVICE]
+    else:
+        # host-only C++ (set-up and the C ABI): no device code object
+        cmd = ["g++", *COMMON, "-D__HIP_PLATFORM_AMD__", "-I", ROCM_INCLUDE]
     cmd += ["-c", src, "-o", obj]
     subprocess.run(cmd, check=True)
     return obj
@@ -49,7 +52,10 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    subprocess.run([_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], check=True)
+    subprocess.run(
+        [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lamdhip64"],
+        check=True,
+    )
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

@@ -11,6 +11,7 @@
 #include "dg_internal.hpp"
 #include "dgwave.h"
 #include "kernels.hpp"
+#include "solver_state.hpp"
 
 namespace dgw {
 
@@ -25,48 +26,8 @@ const char* last_error() { return g_error.c_str(); }
 
 using dgw::set_error;
 
-struct dg_solver {
-  int physics = 0, N = 0, Np = 0, Nfp = 0, NF = 0, NT = 0, CB = 0, ncoef = 0;
-  int64_t K = 0;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  float* q = nullptr;
-  float* r[3] = {nullptr, nullptr, nullptr};
-  float* qf[2] = {nullptr, nullptr};
-  float* qf_tmp = nullptr;
-  float* geo = nullptr;
-  float* cf = nullptr;
-  float* coef = nullptr;
-  float* DT = nullptr;
-  float* LT = nullptr;
-  int32_t* conn = nullptr;
-  int32_t* fmask = nullptr;
-  int32_t* perm = nullptr;
-  int32_t* nodeface = nullptr;
-  double* J = nullptr;
-  double* mass = nullptr;
-  double* partial = nullptr;
-  double* e_out = nullptr;
-  int* flag = nullptr;
-  int cur = 0;     // trace buffer holding the traces of q
-  int64_t m = 0;   // step index
-  bool have_coef = false, have_fields = false;
-  int xcd_remap = 1;
-  std::vector<double> elem_xyz;  // host copy for node coordinates
-};
 
 namespace {
-
-#define DG_HIP(call)                                                   \
-  do {                                                                 \
-    hipError_t err_ = (call);                                          \
-    if (err_ != hipSuccess) {                                          \
-      std::ostringstream os_;                                          \
-      os_ << #call << ": " << hipGetErrorString(err_);                 \
-      set_error(os_.str());                                            \
-      return DG_E_HIP;                                                 \
-    }                                                                  \
-  } while (0)
 
 template <class T>
 hipError_t dev_alloc(T** p, size_t count) {
@@ -84,7 +45,7 @@ dg_status check_solver(const dg_solver* s) {
 void free_all(dg_solver* s) {
   void* ptrs[] = {s->q,  s->r[0], s->r[1], s->r[2], s->qf[0], s->qf[1], s->qf_tmp, s->geo,
                   s->cf, s->coef, s->DT,   s->LT,   s->conn,  s->fmask, s->perm,   s->nodeface, s->J,
-                  s->mass, s->partial, s->e_out, s->flag};
+                  s->mass, s->partial, s->e_out, s->flag, s->Dpack, s->Lpack};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -93,6 +54,45 @@ size_t field_count(const dg_solver* s) { return static_cast<size_t>(s->K) * s->N
 size_t trace_count(const dg_solver* s) { return static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp; }
 
 }  // namespace
+
+namespace dgw {
+
+StepArgs base_args(const dg_solver* s) {
+  StepArgs a{};
+  a.K = s->K;
+  a.geo = s->geo;
+  a.cf = s->cf;
+  a.conn = s->conn;
+  a.DT = s->DT;
+  a.LT = s->LT;
+  a.fmask = s->fmask;
+  a.perm = s->perm;
+  a.nodeface = s->nodeface;
+  a.Dpack = s->Dpack;
+  a.Lpack = s->Lpack;
+  a.xcd_remap = s->xcd_remap;
+  return a;
+}
+
+StepArgs step_args(const dg_solver* s, int64_t m, int cur, double dt) {
+  StepArgs a = base_args(s);
+  a.mode = kStepMode;
+  float c[3];
+  ab_coefficients(m, dt, c);
+  a.c0 = c[0];
+  a.c1 = c[1];
+  a.c2 = c[2];
+  a.q_in = s->q;
+  a.q_out = s->q;
+  a.r_out = s->r[m % 3];
+  a.r1 = s->r[(m + 2) % 3];
+  a.r2 = s->r[(m + 1) % 3];
+  a.qf_in = s->qf[cur];
+  a.qf_out = s->qf[cur ^ 1];
+  return a;
+}
+
+}  // namespace dgw
 
 extern "C" {
 
@@ -260,6 +260,30 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
       conn[s] = static_cast<int32_t>((kn << 5) | (static_cast<int64_t>(fn) << 3) | o);
     }
 
+  // ---- MFMA fragment-order packing: A[row = lane%16][k = 4*kk + lane/16] ----
+  const int MB = dgw::mfma_mblocks(order), KP = dgw::mfma_kpad(order), NFPP = dgw::mfma_face_pad(order);
+  const int KL = 4 * NFPP;
+  std::vector<float> Dpack(static_cast<size_t>(3) * MB * (KP / 4) * 64, 0.0f);
+  std::vector<float> Lpack(static_cast<size_t>(MB) * (KL / 4) * 64, 0.0f);
+  for (int j = 0; j < 3; ++j)
+    for (int mb = 0; mb < MB; ++mb)
+      for (int kk = 0; kk < KP / 4; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int row = mb * 16 + l % 16, col = kk * 4 + l / 16;
+          if (row < Np && col < Np)
+            Dpack[((static_cast<size_t>(j) * MB + mb) * (KP / 4) + kk) * 64 + l] =
+                static_cast<float>(ref->D[(static_cast<size_t>(j) * Np + row) * Np + col]);
+        }
+  for (int mb = 0; mb < MB; ++mb)
+    for (int kl = 0; kl < KL / 4; ++kl)
+      for (int l = 0; l < 64; ++l) {
+        const int row = mb * 16 + l % 16, slot = kl * 4 + l / 16;
+        const int f = slot / NFPP, jj = slot % NFPP;
+        if (row < Np && jj < Nfp)
+          Lpack[(static_cast<size_t>(mb) * (KL / 4) + kl) * 64 + l] =
+              static_cast<float>(ref->lift[static_cast<size_t>(row) * 4 * Nfp + f * Nfp + jj]);
+      }
+
   // ---- operators in the kernels' layouts (float32) ----
   std::vector<float> DT(3 * static_cast<size_t>(Np) * Np), LT(static_cast<size_t>(4) * Nfp * Np);
   for (int j = 0; j < 3; ++j)
@@ -316,6 +340,8 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
   if ((err = dev_alloc(&s->partial, static_cast<size_t>(eb))) != hipSuccess) return fail(err, "alloc partial");
   if ((err = dev_alloc(&s->e_out, 1)) != hipSuccess) return fail(err, "alloc e_out");
   if ((err = dev_alloc(&s->flag, 1)) != hipSuccess) return fail(err, "alloc flag");
+  if ((err = dev_alloc(&s->Dpack, Dpack.size())) != hipSuccess) return fail(err, "alloc Dpack");
+  if ((err = dev_alloc(&s->Lpack, Lpack.size())) != hipSuccess) return fail(err, "alloc Lpack");
 
   struct Up {
     void* dst;
@@ -331,6 +357,8 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
       {s->nodeface, ref->nodeface.data(), ref->nodeface.size() * sizeof(int32_t)},
       {s->J, J.data(), J.size() * sizeof(double)},
       {s->mass, ref->mass.data(), ref->mass.size() * sizeof(double)},
+      {s->Dpack, Dpack.data(), Dpack.size() * sizeof(float)},
+      {s->Lpack, Lpack.data(), Lpack.size() * sizeof(float)},
   };
   for (const auto& u : ups)
     if ((err = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice)) != hipSuccess)
@@ -351,6 +379,28 @@ void dg_destroy(dg_solver* s) {
 dg_status dg_set_stream(dg_solver* s, void* stream) {
   if (dg_status st = check_solver(s)) return st;
   s->stream = static_cast<hipStream_t>(stream);
+  return DG_OK;
+}
+
+dg_status dg_set_variant(dg_solver* s, int variant) {
+  if (dg_status st = check_solver(s)) return st;
+  if (!dgw::variant_supported(s->physics, s->N, variant)) {
+    std::ostringstream os;
+    os << "kernel variant " << variant << " is not available for this physics and degree";
+    set_error(os.str());
+    return DG_E_UNSUPPORTED;
+  }
+  s->variant = variant;
+  return DG_OK;
+}
+
+dg_status dg_get_variant(dg_solver* s, int* variant) {
+  if (dg_status st = check_solver(s)) return st;
+  if (!variant) {
+    set_error("null output");
+    return DG_E_ARG;
+  }
+  *variant = s->variant;
   return DG_OK;
 }
 
@@ -477,21 +527,6 @@ dg_status dg_step_index(dg_solver* s, int64_t* m) {
   return DG_OK;
 }
 
-static dgw::StepArgs base_args(dg_solver* s) {
-  dgw::StepArgs a{};
-  a.K = s->K;
-  a.geo = s->geo;
-  a.cf = s->cf;
-  a.conn = s->conn;
-  a.DT = s->DT;
-  a.LT = s->LT;
-  a.fmask = s->fmask;
-  a.perm = s->perm;
-  a.nodeface = s->nodeface;
-  a.xcd_remap = s->xcd_remap;
-  return a;
-}
-
 dg_status dg_step(dg_solver* s, int nsteps, double dt) {
   if (dg_status st = check_solver(s)) return st;
   if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) {
@@ -502,31 +537,11 @@ dg_status dg_step(dg_solver* s, int nsteps, double dt) {
     set_error("set coefficients and fields before stepping");
     return DG_E_STATE;
   }
-  dgw::StepArgs a = base_args(s);
-  a.mode = dgw::kStepMode;
   for (int i = 0; i < nsteps; ++i) {
-    const int64_t m = s->m;
-    double a1, a2, a3;
-    if (m == 0) {
-      a1 = 1.0; a2 = 0.0; a3 = 0.0;
-    } else if (m == 1) {
-      a1 = 1.5; a2 = -0.5; a3 = 0.0;
-    } else {
-      a1 = 23.0 / 12.0; a2 = -16.0 / 12.0; a3 = 5.0 / 12.0;
-    }
-    a.c0 = static_cast<float>(dt * a1);
-    a.c1 = static_cast<float>(dt * a2);
-    a.c2 = static_cast<float>(dt * a3);
-    a.q_in = s->q;
-    a.q_out = s->q;
-    a.r_out = s->r[m % 3];
-    a.r1 = s->r[(m + 2) % 3];
-    a.r2 = s->r[(m + 1) % 3];
-    a.qf_in = s->qf[s->cur];
-    a.qf_out = s->qf[s->cur ^ 1];
-    DG_HIP(dgw::launch_step(s->physics, s->N, a, s->stream));
+    const dgw::StepArgs a = dgw::step_args(s, s->m, s->cur, dt);
+    DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, s->stream));
     s->cur ^= 1;
-    s->m = m + 1;
+    s->m += 1;
   }
   return DG_OK;
 }
@@ -542,12 +557,12 @@ dg_status dg_rhs(dg_solver* s, const float* q, float* r) {
     return DG_E_STATE;
   }
   DG_HIP(dgw::launch_traces(s->physics, s->N, s->K, q, s->geo, s->fmask, s->qf_tmp, s->stream));
-  dgw::StepArgs a = base_args(s);
+  dgw::StepArgs a = dgw::base_args(s);
   a.mode = dgw::kRhsMode;
   a.q_in = q;
   a.r_out = r;
   a.qf_in = s->qf_tmp;
-  DG_HIP(dgw::launch_step(s->physics, s->N, a, s->stream));
+  DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, s->stream));
   return DG_OK;
 }
 

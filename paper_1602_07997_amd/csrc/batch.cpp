@@ -1,0 +1,433 @@
+// Kernel choice per solver (autotuning) and batches of meshes stepped with
+// one launch per (degree, variant) group.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "dg_internal.hpp"
+#include "dgwave.h"
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+using dgw::set_error;
+
+namespace {
+
+size_t field_floats(const dg_solver* s) { return static_cast<size_t>(s->K) * s->NF * s->Np; }
+size_t trace_floats(const dg_solver* s) { return static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp; }
+
+// Device copies of the solver state, released on scope exit.
+struct SavedState {
+  float* buf = nullptr;
+  ~SavedState() {
+    if (buf) (void)hipFree(buf);
+  }
+};
+
+}  // namespace
+
+struct dg_batch_group {
+  int N = 0, variant = 0;
+  std::vector<int> members;           // indices into dg_batch::members
+  dgw::StepArgs* args = nullptr;      // device [members][kBatchPhases]
+  int2* work = nullptr;               // device [nwork] (member slot, tile)
+  int64_t tiles = 0;                  // real work items
+  int64_t nwork = 0;                  // launched workgroups (padded to 8)
+};
+
+struct dg_batch {
+  std::vector<dg_solver*> members;
+  int physics = 0;
+  hipStream_t stream = nullptr;
+  std::vector<dg_batch_group> groups;
+  std::vector<int> group_variant;     // member variants the groups were built for
+  // argument tables: valid for member i at step m0[i] + p with trace buffer
+  // cur0[i] ^ (p & 1), for every p >= 0 (the tables have period kBatchPhases)
+  bool tables_valid = false;
+  std::vector<int64_t> m0;
+  std::vector<int> cur0;
+  std::vector<double> dt;
+  int64_t p = 0;                      // batched steps since the tables were built
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_groups(dg_batch* b) {
+  for (dg_batch_group& g : b->groups) {
+    if (g.args) (void)hipFree(g.args);
+    if (g.work) (void)hipFree(g.work);
+  }
+  b->groups.clear();
+}
+
+void drop_graph(dg_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Workgroup b of a launch of n tiles runs work item xcd_order(b): the
+// hardware deals workgroups round-robin to the 8 XCDs, so giving XCD x the
+// items [x*per, (x+1)*per) keeps an element's neighbours in one L2.
+std::vector<int2> xcd_order(const std::vector<int2>& items) {
+  const int64_t n = static_cast<int64_t>(items.size());
+  const int64_t per = (n + 7) / 8;
+  std::vector<int2> out(static_cast<size_t>(per * 8), int2{-1, 0});
+  for (int64_t w = 0; w < per * 8; ++w) {
+    const int64_t item = (w % 8) * per + w / 8;
+    if (item < n) out[static_cast<size_t>(w)] = items[static_cast<size_t>(item)];
+  }
+  return out;
+}
+
+dg_status build_groups(dg_batch* b) {
+  if (b->stream) DG_HIP(hipStreamSynchronize(b->stream));
+  else DG_HIP(hipDeviceSynchronize());
+  drop_graph(b);
+  free_groups(b);
+  b->tables_valid = false;
+  b->group_variant.clear();
+  std::vector<std::pair<int, int>> keys;
+  for (dg_solver* s : b->members) {
+    b->group_variant.push_back(s->variant);
+    const std::pair<int, int> key(s->N, s->variant);
+    if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+  }
+  std::sort(keys.begin(), keys.end());
+  for (const auto& key : keys) {
+    dg_batch_group g;
+    g.N = key.first;
+    g.variant = key.second;
+    std::vector<int2> items;
+    for (int i = 0; i < static_cast<int>(b->members.size()); ++i) {
+      const dg_solver* s = b->members[static_cast<size_t>(i)];
+      if (s->N != g.N || s->variant != g.variant) continue;
+      const int slot = static_cast<int>(g.members.size());
+      g.members.push_back(i);
+      const int64_t nt = dgw::tiles_for(b->physics, g.N, g.variant, s->K);
+      if (nt < 0) {
+        set_error("batch member has a kernel variant that is not built");
+        return DG_E_UNSUPPORTED;
+      }
+      for (int64_t t = 0; t < nt; ++t) {
+        if (t > 0x7fffffff) {
+          set_error("batch member too large");
+          return DG_E_SHAPE;
+        }
+        items.push_back(int2{slot, static_cast<int>(t)});
+      }
+    }
+    g.tiles = static_cast<int64_t>(items.size());
+    const std::vector<int2> work = xcd_order(items);
+    g.nwork = static_cast<int64_t>(work.size());
+    if (g.nwork > 0x7fffffff) {
+      set_error("batch launch too large");
+      return DG_E_SHAPE;
+    }
+    b->groups.push_back(g);
+    dg_batch_group& gg = b->groups.back();
+    DG_HIP(hipMalloc(reinterpret_cast<void**>(&gg.work), std::max<size_t>(work.size(), 1) * sizeof(int2)));
+    DG_HIP(hipMalloc(reinterpret_cast<void**>(&gg.args),
+                     gg.members.size() * dgw::kBatchPhases * sizeof(dgw::StepArgs)));
+    if (!work.empty())
+      DG_HIP(hipMemcpy(gg.work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
+  }
+  return DG_OK;
+}
+
+// Fill the argument tables from the members' current state.  Rare (after a
+// start-up step, a state change outside the batch or a new dt), so the upload
+// synchronises.
+dg_status build_tables(dg_batch* b, const double* dt) {
+  const size_t n = b->members.size();
+  b->m0.resize(n);
+  b->cur0.resize(n);
+  b->dt.assign(dt, dt + n);
+  for (size_t i = 0; i < n; ++i) {
+    b->m0[i] = b->members[i]->m;
+    b->cur0[i] = b->members[i]->cur;
+  }
+  for (dg_batch_group& g : b->groups) {
+    std::vector<dgw::StepArgs> h(g.members.size() * dgw::kBatchPhases);
+    for (size_t slot = 0; slot < g.members.size(); ++slot) {
+      const int i = g.members[slot];
+      const dg_solver* s = b->members[static_cast<size_t>(i)];
+      for (int ph = 0; ph < dgw::kBatchPhases; ++ph)
+        h[slot * dgw::kBatchPhases + ph] = dgw::step_args(s, b->m0[i] + ph, b->cur0[i] ^ (ph & 1), b->dt[i]);
+    }
+    DG_HIP(hipMemcpyAsync(g.args, h.data(), h.size() * sizeof(dgw::StepArgs), hipMemcpyHostToDevice, b->stream));
+    DG_HIP(hipStreamSynchronize(b->stream));
+  }
+  b->p = 0;
+  b->tables_valid = true;
+  return DG_OK;
+}
+
+bool tables_match(const dg_batch* b, const double* dt) {
+  if (!b->tables_valid) return false;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    const dg_solver* s = b->members[i];
+    if (s->m != b->m0[i] + b->p || s->cur != (b->cur0[i] ^ static_cast<int>(b->p & 1))) return false;
+    if (dt[i] != b->dt[i]) return false;
+  }
+  return true;
+}
+
+dg_status launch_groups(dg_batch* b, int phase) {
+  for (const dg_batch_group& g : b->groups)
+    DG_HIP(dgw::launch_step_batch(b->physics, g.N, g.variant, g.args, g.work, g.nwork, phase, b->stream));
+  return DG_OK;
+}
+
+void advance_members(dg_batch* b, int steps) {
+  for (dg_solver* s : b->members) {
+    s->m += steps;
+    s->cur ^= (steps & 1);
+  }
+  b->p += steps;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_autotune(dg_solver* s, int steps, double dt, double* us_per_step) {
+  if (!s) {
+    set_error("null solver");
+    return DG_E_ARG;
+  }
+  if (steps < 1 || !(dt > 0.0) || !std::isfinite(dt)) {
+    set_error("steps must be >= 1 and dt > 0");
+    return DG_E_ARG;
+  }
+  if (!s->have_coef || !s->have_fields) {
+    set_error("set coefficients and fields before tuning");
+    return DG_E_STATE;
+  }
+  const size_t nq = field_floats(s), nt = trace_floats(s);
+  SavedState saved;
+  DG_HIP(hipMalloc(reinterpret_cast<void**>(&saved.buf), (4 * nq + nt) * sizeof(float)));
+  const size_t fb = nq * sizeof(float);
+  DG_HIP(hipMemcpyAsync(saved.buf, s->q, fb, hipMemcpyDeviceToDevice, s->stream));
+  for (int i = 0; i < 3; ++i)
+    DG_HIP(hipMemcpyAsync(saved.buf + (1 + i) * nq, s->r[i], fb, hipMemcpyDeviceToDevice, s->stream));
+  DG_HIP(hipMemcpyAsync(saved.buf + 4 * nq, s->qf[s->cur], nt * sizeof(float), hipMemcpyDeviceToDevice,
+                        s->stream));
+  const int64_t m_saved = s->m;
+  const int cur_saved = s->cur;
+  const int variant_saved = s->variant;
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DG_HIP(hipEventCreate(&e0));
+  DG_HIP(hipEventCreate(&e1));
+  double best = -1.0;
+  int best_variant = variant_saved;
+  dg_status st = DG_OK;
+  for (int v = 0; v < DG_NUM_VARIANTS && st == DG_OK; ++v) {
+    double us = -1.0;
+    if (dgw::variant_supported(s->physics, s->N, v)) {
+      s->variant = v;
+      hipError_t err = hipSuccess;
+      for (int i = 0; i <= steps && err == hipSuccess; ++i) {
+        if (i == 1) err = hipEventRecord(e0, s->stream);
+        if (err == hipSuccess) {
+          const dgw::StepArgs a = dgw::step_args(s, s->m, s->cur, dt);
+          err = dgw::launch_step(s->physics, s->N, v, a, s->stream);
+          s->cur ^= 1;
+          s->m += 1;
+        }
+      }
+      if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) {
+        set_error(std::string("autotune: ") + hipGetErrorString(err));
+        st = DG_E_HIP;
+      }
+      us = 1000.0 * ms / steps;
+      if (st == DG_OK && (best < 0.0 || us < best)) {
+        best = us;
+        best_variant = v;
+      }
+      // restore the state before the next candidate (and at the end)
+      s->m = m_saved;
+      s->cur = cur_saved;
+      hipError_t rerr = hipMemcpyAsync(s->q, saved.buf, fb, hipMemcpyDeviceToDevice, s->stream);
+      for (int i = 0; i < 3 && rerr == hipSuccess; ++i)
+        rerr = hipMemcpyAsync(s->r[i], saved.buf + (1 + i) * nq, fb, hipMemcpyDeviceToDevice, s->stream);
+      if (rerr == hipSuccess)
+        rerr = hipMemcpyAsync(s->qf[s->cur], saved.buf + 4 * nq, nt * sizeof(float), hipMemcpyDeviceToDevice,
+                              s->stream);
+      if (rerr == hipSuccess) rerr = hipStreamSynchronize(s->stream);
+      if (rerr != hipSuccess && st == DG_OK) {
+        set_error(std::string("autotune restore: ") + hipGetErrorString(rerr));
+        st = DG_E_HIP;
+      }
+    }
+    if (us_per_step) us_per_step[v] = us;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->variant = st == DG_OK ? best_variant : variant_saved;
+  return st;
+}
+
+dg_status dg_batch_create(dg_solver* const* members, int count, void* stream, dg_batch** out) {
+  if (!members || !out || count < 1) {
+    set_error("dg_batch_create: need an output pointer and at least one member");
+    return DG_E_ARG;
+  }
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (!members[i]) {
+      set_error("dg_batch_create: null member");
+      return DG_E_ARG;
+    }
+    if (members[i]->physics != members[0]->physics || members[i]->device != members[0]->device) {
+      set_error("dg_batch_create: members must share physics and device");
+      return DG_E_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (members[j] == members[i]) {
+        set_error("dg_batch_create: repeated member");
+        return DG_E_ARG;
+      }
+  }
+  dg_batch* b = new dg_batch;
+  b->members.assign(members, members + count);
+  b->physics = members[0]->physics;
+  b->stream = static_cast<hipStream_t>(stream);
+  if (dg_status st = build_groups(b)) {
+    free_groups(b);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return DG_OK;
+}
+
+void dg_batch_destroy(dg_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  free_groups(b);
+  delete b;
+}
+
+dg_status dg_batch_set_graph(dg_batch* b, int enable) {
+  if (!b) {
+    set_error("null batch");
+    return DG_E_ARG;
+  }
+  if (enable && !b->stream) {
+    set_error("graph replay needs a non-default stream");
+    return DG_E_STATE;
+  }
+  if (!enable) drop_graph(b);
+  b->use_graph = enable != 0;
+  return DG_OK;
+}
+
+dg_status dg_batch_step(dg_batch* b, int nsteps, const double* dt) {
+  if (!b || !dt || nsteps < 0) {
+    set_error("dg_batch_step: bad arguments");
+    return DG_E_ARG;
+  }
+  const size_t n = b->members.size();
+  for (size_t i = 0; i < n; ++i) {
+    const dg_solver* s = b->members[i];
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) {
+      set_error("dg_batch_step: every dt must be positive and finite");
+      return DG_E_ARG;
+    }
+    if (!s->have_coef || !s->have_fields) {
+      set_error("dg_batch_step: a member has no coefficients or fields");
+      return DG_E_STATE;
+    }
+  }
+  for (size_t i = 0; i < n; ++i)
+    if (b->members[i]->variant != b->group_variant[i]) {
+      if (dg_status st = build_groups(b)) return st;
+      break;
+    }
+  int done = 0;
+  while (done < nsteps) {
+    bool startup = false;
+    for (const dg_solver* s : b->members) startup = startup || s->m < 2;
+    if (startup) {
+      // start-up steps use their own coefficients: one launch per member
+      for (size_t i = 0; i < n; ++i) {
+        dg_solver* s = b->members[i];
+        const dgw::StepArgs a = dgw::step_args(s, s->m, s->cur, dt[i]);
+        DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, b->stream));
+        s->m += 1;
+        s->cur ^= 1;
+      }
+      b->tables_valid = false;
+      ++done;
+      continue;
+    }
+    if (!tables_match(b, dt))
+      if (dg_status st = build_tables(b, dt)) return st;
+    const int phase = static_cast<int>(b->p % dgw::kBatchPhases);
+    if (b->use_graph && phase == 0 && nsteps - done >= dgw::kBatchPhases) {
+      if (!b->exec) {
+        DG_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        dg_status st = DG_OK;
+        for (int ph = 0; ph < dgw::kBatchPhases && st == DG_OK; ++ph) st = launch_groups(b, ph);
+        hipGraph_t graph = nullptr;
+        const hipError_t cerr = hipStreamEndCapture(b->stream, &graph);
+        if (st != DG_OK) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return st;
+        }
+        DG_HIP(cerr);
+        b->graph = graph;
+        DG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      }
+      DG_HIP(hipGraphLaunch(b->exec, b->stream));
+      advance_members(b, dgw::kBatchPhases);
+      done += dgw::kBatchPhases;
+      continue;
+    }
+    if (dg_status st = launch_groups(b, phase)) return st;
+    advance_members(b, 1);
+    ++done;
+  }
+  return DG_OK;
+}
+
+dg_status dg_batch_groups(dg_batch* b, int* ngroups, int32_t* order, int32_t* variant, int64_t* tiles) {
+  if (!b || !ngroups) {
+    set_error("null argument");
+    return DG_E_ARG;
+  }
+  const int n = static_cast<int>(b->groups.size());
+  const bool fill = order || variant || tiles;
+  const int cap = *ngroups;
+  *ngroups = n;
+  if (!fill) return DG_OK;
+  if (cap < n) {
+    set_error("group arrays too small");
+    return DG_E_SHAPE;
+  }
+  for (int i = 0; i < n; ++i) {
+    const dg_batch_group& g = b->groups[static_cast<size_t>(i)];
+    if (order) order[i] = g.N;
+    if (variant) variant[i] = g.variant;
+    if (tiles) tiles[i] = g.nwork;
+  }
+  return DG_OK;
+}
+
+}  // extern "C"

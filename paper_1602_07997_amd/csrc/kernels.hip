@@ -22,28 +22,14 @@
 
 #include <cmath>
 
+#include "dg_device.hpp"
 #include "kernels.hpp"
 
 namespace dgw {
 
 namespace {
 
-template <int N>
-struct Deg {
-  static constexpr int NP = (N + 1) * (N + 2) * (N + 3) / 6;
-  static constexpr int NFP = (N + 1) * (N + 2) / 2;
-};
-
-template <int PHYS>
-struct Phys;
-template <>
-struct Phys<0> {  // acoustic: p, v1, v2, v3
-  static constexpr int NF = 4, NT = 2, NAUX = 3, CB = 8;
-};
-template <>
-struct Phys<1> {  // elastic: v1, v2, v3, s11, s22, s33, s23, s13, s12
-  static constexpr int NF = 9, NT = 6, NAUX = 9, CB = 16;
-};
+using namespace dev;
 
 // Elements per workgroup, chosen so that KT*NP fills ~256 threads.
 template <int N, int PHYS>
@@ -53,41 +39,6 @@ struct Tile {
   static constexpr int KT =
       (N == 8 && PHYS == 0) ? 3 : (PHYS == 1 && N <= 2 ? (N == 1 ? 32 : 16) : (raw < 1 ? 1 : raw));
 };
-
-constexpr int kThreads = 256;
-
-// Voigt index of the symmetric stress component (i, j).
-__device__ __forceinline__ constexpr int voigt(int i, int j) {
-  return (i == j) ? i : (3 + (3 - i - j));  // (1,2)->3, (0,2)->4, (0,1)->5
-}
-
-// Outward unit normal and Fscale of reference face f from G (row-major 3x3):
-// n ~ G nref_f with nref = (0,0,-1), (0,-1,0), (1,1,1), (-1,0,0) for f = 0..3,
-// Fscale = |G nref_f|.  The reference normal is formed with 0/1 weights rather
-// than a chain of selects: hipcc (ROCm 7.2) turned such a chain into branches
-// that left face 3 with the face-1 value.
-__device__ __forceinline__ void face_normal(const float* G, int f, float n[3], float& fs) {
-  const float is0 = static_cast<float>(f == 0), is1 = static_cast<float>(f == 1);
-  const float is2 = static_cast<float>(f == 2), is3 = static_cast<float>(f == 3);
-  const float w0 = is2 - is3, w1 = is2 - is1, w2 = is2 - is0;
-  float v[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) v[i] = G[3 * i + 0] * w0 + G[3 * i + 1] * w1 + G[3 * i + 2] * w2;
-  fs = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  const float inv = 1.0f / fs;
-  n[0] = v[0] * inv;
-  n[1] = v[1] * inv;
-  n[2] = v[2] * inv;
-}
-
-__device__ __forceinline__ int64_t tile_of_block(int xcd_remap) {
-  const int64_t b = blockIdx.x;
-  if (!xcd_remap) return b;
-  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous range of tiles so that neighbours share an L2.
-  const int64_t per = gridDim.x / 8;  // grid is a multiple of 8 when remapping
-  return (b % 8) * per + b / 8;
-}
 
 // Number of lifted scalars per face node: acoustic (Fscale*penalty for p,
 // scalar velocity penalty along n), elastic (k_p a_p, k_s a_s, vector a_s),
@@ -106,8 +57,7 @@ struct LiftCols<1> {
 };
 
 template <int N, int PHYS>
-__global__ void __launch_bounds__(kThreads)
-dg_step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) {
   constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP, NFN = 4 * NFP;
   constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT, NAUX = Phys<PHYS>::NAUX;
   constexpr int CB = Phys<PHYS>::CB;
@@ -121,9 +71,9 @@ dg_step_kernel(StepArgs a) {
   __shared__ float s_lift[KT * NL * NFN];
   __shared__ float s_g[KT * 9];
   __shared__ float s_cf[KT * CB];
-  __shared__ float s_nrm[KT * 4 * 3];
+  constexpr int FW = FaceRec<PHYS>::W;
+  __shared__ float s_face[KT * 4 * FW];
 
-  const int64_t tile = tile_of_block(a.xcd_remap);
   const int64_t e0 = tile * KT;
   if (e0 >= a.K) return;  // whole workgroup exits together
   const int ne = static_cast<int>((a.K - e0) < KT ? (a.K - e0) : KT);
@@ -186,6 +136,11 @@ dg_step_kernel(StepArgs a) {
     }
     for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
     for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
+    // per-face constants, once per face (read straight from global memory)
+    for (int i = tid; i < ne * 4; i += kThreads) {
+      const int e = i >> 2, f = i & 3;
+      face_record<PHYS>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
+    }
   }
   __syncthreads();
 
@@ -217,29 +172,21 @@ dg_step_kernel(StepArgs a) {
     if (i >= ne * NFN) continue;
     const int e = i / NFN, fn = i - e * NFN;
     const int f = fn / NFP, j = fn - f * NFP;
-    float nrm[3], fs;
-    face_normal(s_g + 9 * e, f, nrm, fs);
-    if (j == 0) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) s_nrm[(e * 4 + f) * 3 + d] = nrm[d];
-    }
+    const float* rec = s_face + (e * 4 + f) * FW;
+    const float nrm[3] = {rec[0], rec[1], rec[2]};
     const int vn = a.fmask[f * NFP + j];
     const float* qe = s_q + e * NF * NP;
-    const float* cf = s_cf + e * CB;
     const bool wall = (word[t] & 7) == 7;
     float* lf = s_lift + e * NL * NFN + fn;
     if constexpr (PHYS == 0) {
       const float pM = qe[vn];
       const float vnM = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
-      const float ZM = cf[2];
       // rigid wall: mirror state p+ = p-, v.n+ = -v.n-
       const float pP = wall ? pM : nbt[t][0];
       const float vnP = wall ? -vnM : -nbt[t][1];  // neighbour stored v.n with its own normal
-      const float ZP = wall ? ZM : cf[4 + f];
-      const float kc = 2.0f / (ZM + ZP);
-      const float alpha = 0.5f * (pP - pM) - ZP * 0.5f * (vnP - vnM);
-      lf[0] = fs * cf[0] * kc * alpha;   // lifted into r^p
-      lf[NFN] = -fs * cf[3] * kc * alpha;  // lifted, then times n, into r^v
+      const float alpha = 0.5f * (pP - pM) - rec[3] * 0.5f * (vnP - vnM);
+      lf[0] = rec[4] * alpha;    // lifted into r^p
+      lf[NFN] = rec[5] * alpha;  // lifted, then times n, into r^v
     } else {
       float vM[3], tM[3], vP[3], tP[3];
 #pragma unroll
@@ -254,9 +201,7 @@ dg_step_kernel(StepArgs a) {
         vP[ii] = wall ? vM[ii] : nbt[t][ii];
         tP[ii] = wall ? -tM[ii] : -nbt[t][3 + ii];  // neighbour stored s n with its own normal
       }
-      const float ZpM = cf[3], ZsM = cf[4];
-      const float ZpP = wall ? ZpM : cf[8 + f];
-      const float ZsP = wall ? ZsM : cf[12 + f];
+      const float ZpP = rec[3], ZsP = rec[4], fs = rec[5];
       float jv[3], jt[3];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
@@ -265,10 +210,8 @@ dg_step_kernel(StepArgs a) {
       }
       const float jvn = jv[0] * nrm[0] + jv[1] * nrm[1] + jv[2] * nrm[2];
       const float jsnn = jt[0] * nrm[0] + jt[1] * nrm[1] + jt[2] * nrm[2];
-      const float kp = 2.0f / (ZpM + ZpP);
-      const float ks = 2.0f / (ZsM + ZsP);
-      lf[0] = fs * kp * (jsnn + ZpP * jvn);  // k_p alpha_p
-      lf[NFN] = fs * ks * (jsnn + ZsP * jvn);  // k_s alpha_s
+      lf[0] = fs * rec[6] * (jsnn + ZpP * jvn);    // k_p alpha_p
+      lf[NFN] = fs * rec[7] * (jsnn + ZsP * jvn);  // k_s alpha_s
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) lf[(2 + ii) * NFN] = fs * (jt[ii] + ZsP * jv[ii]);  // vector alpha_s
     }
@@ -286,7 +229,7 @@ dg_step_kernel(StepArgs a) {
     const float* ax = s_aux + e * NAUX * NP;
     const float* lf = s_lift + e * NL * NFN;
     const float* cf = s_cf + e * CB;
-    const float* nr = s_nrm + e * 12;
+    const float* fr = s_face + e * 4 * FW;  // face records of this element
     float r[NF];
     // per-face lifts of the penalty scalars
     float L[4][NL];
@@ -320,8 +263,8 @@ dg_step_kernel(StepArgs a) {
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
         r[1 + ii] = -irho * (G[3 * ii + 0] * T0 + G[3 * ii + 1] * T1 + G[3 * ii + 2] * T2) +
-                    (nr[0 * 3 + ii] * L[0][1] + nr[1 * 3 + ii] * L[1][1] + nr[2 * 3 + ii] * L[2][1] +
-                     nr[3 * 3 + ii] * L[3][1]);
+                    (fr[0 * FW + ii] * L[0][1] + fr[1 * FW + ii] * L[1][1] + fr[2 * FW + ii] * L[2][1] +
+                     fr[3 * FW + ii] * L[3][1]);
     } else {
       float Dv[3][3], dS[3];
 #pragma unroll
@@ -360,8 +303,8 @@ dg_step_kernel(StepArgs a) {
       float l1sum = 0.f;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const float ks = 2.0f / (cf[4] + cf[12 + f]);
-        const float n0 = nr[f * 3 + 0], n1 = nr[f * 3 + 1], n2 = nr[f * 3 + 2];
+        const float ks = fr[f * FW + 7];
+        const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
         const float nf[3] = {n0, n1, n2};
         const float a1 = cp * L[f][0] - cs * L[f][1];
         const float b2 = 2.0f * mu * (L[f][0] - L[f][1]);
@@ -408,7 +351,7 @@ dg_step_kernel(StepArgs a) {
       const int fj = a.nodeface[n * 3 + s];
       if (fj < 0) break;
       const int f = fj / NFP, j = fj - f * NFP;
-      const float n0 = nr[f * 3 + 0], n1 = nr[f * 3 + 1], n2 = nr[f * 3 + 2];
+      const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
       float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP + j;
       if constexpr (PHYS == 0) {
         tr[0] = qn[0];
@@ -424,6 +367,23 @@ dg_step_kernel(StepArgs a) {
       }
     }
   }
+}
+
+template <int N, int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_step_kernel(StepArgs a) {
+  step_valu_tile<N, PHYS>(a, tile_of_block(a.xcd_remap));
+}
+
+// Many meshes of one degree in one launch: workgroup b runs tile work[b].y of
+// member work[b].x with that member's arguments for this step's phase.
+template <int N, int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_step_kernel_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
+  const int2 w = work[blockIdx.x];
+  if (w.x < 0) return;  // padding entry of the work list
+  const StepArgs a = args[w.x * kBatchPhases + phase];
+  step_valu_tile<N, PHYS>(a, w.y);
 }
 
 // Own traces of a field array (initial state, right-hand-side evaluation).
@@ -596,6 +556,15 @@ hipError_t step_impl(const StepArgs& a, hipStream_t s) {
 }
 
 template <int N, int PHYS>
+hipError_t step_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_step_kernel_batch<N, PHYS>), dim3(static_cast<unsigned>(ntiles)), dim3(kThreads), 0, s,
+                     args, work, phase);
+  return hipGetLastError();
+}
+
+template <int N, int PHYS>
 hipError_t trace_impl(int64_t K, const float* q, const float* geo, const int32_t* fmask, float* qf,
                       hipStream_t s) {
   const int64_t items = K * 4 * Deg<N>::NFP;
@@ -640,7 +609,18 @@ int64_t energy_blocks_impl(int N, int64_t K) {
 int coef_block(int physics) { return physics == 0 ? Phys<0>::CB : Phys<1>::CB; }
 int num_traces(int physics) { return physics == 0 ? Phys<0>::NT : Phys<1>::NT; }
 
-hipError_t launch_step(int physics, int N, const StepArgs& a, hipStream_t s) {
+hipError_t launch_step_mfma(int physics, int N, const StepArgs& a, hipStream_t s);
+
+bool variant_supported(int physics, int N, int variant) {
+  if (N < 1 || N > 8 || (physics != 0 && physics != 1)) return false;
+  if (variant == kVariantValu) return true;
+  if (variant == kVariantMfma) return physics == 0;
+  return false;
+}
+
+hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
+  if (variant == kVariantMfma) return launch_step_mfma(physics, N, a, s);
+  if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_impl<n, p>(a, s)
   if (physics == 0) {
     switch (N) {
@@ -663,6 +643,53 @@ hipError_t launch_step(int physics, int N, const StepArgs& a, hipStream_t s) {
       case 6: return CALL(6, 1);
       case 7: return CALL(7, 1);
       case 8: return CALL(8, 1);
+    }
+  }
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+int64_t tiles_for(int physics, int N, int variant, int64_t K) {
+  const int E = tile_elements(physics, N, variant);
+  return E > 0 ? (K + E - 1) / E : -1;
+}
+
+int tile_elements(int physics, int N, int variant) {
+  if (!variant_supported(physics, N, variant)) return -1;
+  if (variant == kVariantMfma) return mfma_tile_elements(N);
+#define TE(n, p) Tile<n, p>::KT
+  if (physics == 0) {
+    switch (N) {
+      case 1: return TE(1, 0); case 2: return TE(2, 0); case 3: return TE(3, 0); case 4: return TE(4, 0);
+      case 5: return TE(5, 0); case 6: return TE(6, 0); case 7: return TE(7, 0); case 8: return TE(8, 0);
+    }
+  } else {
+    switch (N) {
+      case 1: return TE(1, 1); case 2: return TE(2, 1); case 3: return TE(3, 1); case 4: return TE(4, 1);
+      case 5: return TE(5, 1); case 6: return TE(6, 1); case 7: return TE(7, 1); case 8: return TE(8, 1);
+    }
+  }
+#undef TE
+  return -1;
+}
+
+hipError_t launch_step_batch_mfma(int physics, int N, const StepArgs* args, const int2* work, int64_t ntiles,
+                                  int phase, hipStream_t s);
+
+hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* args, const int2* work,
+                             int64_t ntiles, int phase, hipStream_t s) {
+  if (variant == kVariantMfma) return launch_step_batch_mfma(physics, N, args, work, ntiles, phase, s);
+  if (variant != kVariantValu) return hipErrorInvalidValue;
+#define CALL(n, p) step_batch_impl<n, p>(args, work, ntiles, phase, s)
+  if (physics == 0) {
+    switch (N) {
+      case 1: return CALL(1, 0); case 2: return CALL(2, 0); case 3: return CALL(3, 0); case 4: return CALL(4, 0);
+      case 5: return CALL(5, 0); case 6: return CALL(6, 0); case 7: return CALL(7, 0); case 8: return CALL(8, 0);
+    }
+  } else {
+    switch (N) {
+      case 1: return CALL(1, 1); case 2: return CALL(2, 1); case 3: return CALL(3, 1); case 4: return CALL(4, 1);
+      case 5: return CALL(5, 1); case 6: return CALL(6, 1); case 7: return CALL(7, 1); case 8: return CALL(8, 1);
     }
   }
 #undef CALL

@@ -171,6 +171,18 @@ class DGSolver:
         )
         return q, (r1 if m.value >= 1 else None), (r2 if m.value >= 2 else None), m.value
 
+    VARIANTS = {"valu": nat.DG_VARIANT_VALU, "mfma": nat.DG_VARIANT_MFMA}
+
+    @property
+    def variant(self) -> str:
+        v = C.c_int()
+        check(lib.dg_get_variant(self._h, C.byref(v)), "dg_get_variant")
+        return {b: a for a, b in self.VARIANTS.items()}[v.value]
+
+    @variant.setter
+    def variant(self, name: str):
+        check(lib.dg_set_variant(self._h, self.VARIANTS[name]), "dg_set_variant")
+
     @property
     def step_index(self) -> int:
         m = C.c_int64()
@@ -179,6 +191,17 @@ class DGSolver:
 
     def step(self, nsteps: int, dt: float):
         check(lib.dg_step(self._h, int(nsteps), float(dt)), "dg_step")
+
+    def autotune(self, steps: int, dt: float) -> dict:
+        """Times every built variant on this mesh and keeps the fastest.
+
+        Returns microseconds per step by variant name (None where not built).
+        The solver's state is restored, so the solution does not advance.
+        """
+        us = np.zeros(nat.DG_NUM_VARIANTS)
+        check(lib.dg_autotune(self._h, int(steps), float(dt), _dptr(us)), "dg_autotune")
+        names = {b: a for a, b in self.VARIANTS.items()}
+        return {names[v]: (float(us[v]) if us[v] >= 0 else None) for v in range(nat.DG_NUM_VARIANTS)}
 
     def rhs(self, q, out=None):
         out = self.empty_fields() if out is None else out
@@ -211,3 +234,63 @@ class DGSolver:
 
     def synchronize(self):
         check(lib.dg_synchronize(self._h), "dg_synchronize")
+
+
+class DGBatch:
+    """Many solvers of one physics stepped together (one launch per degree
+    and variant group and step; optionally replayed from a HIP graph).
+
+    The batch keeps references to its members; they must stay open while it
+    lives.
+    """
+
+    def __init__(self, members, stream=None, graph: bool = False):
+        import torch
+
+        self.members = list(members)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        arr = (C.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        h = C.c_void_p()
+        check(
+            lib.dg_batch_create(
+                C.cast(arr, C.POINTER(C.c_void_p)), len(self.members), C.c_void_p(stream.cuda_stream), C.byref(h)
+            ),
+            "dg_batch_create",
+        )
+        self._h = h
+        if graph:
+            self.set_graph(True)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, enable: bool):
+        check(lib.dg_batch_set_graph(self._h, int(bool(enable))), "dg_batch_set_graph")
+
+    def step(self, nsteps: int, dt):
+        dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (len(self.members),)))
+        check(lib.dg_batch_step(self._h, int(nsteps), _dptr(dts)), "dg_batch_step")
+
+    def groups(self):
+        """[(degree, variant name, workgroups per launch)] of the launch groups."""
+        n = C.c_int(0)
+        check(lib.dg_batch_groups(self._h, C.byref(n), None, None, None), "dg_batch_groups")
+        order = np.zeros(n.value, dtype=np.int32)
+        variant = np.zeros(n.value, dtype=np.int32)
+        tiles = np.zeros(n.value, dtype=np.int64)
+        check(
+            lib.dg_batch_groups(self._h, C.byref(n), _i32ptr(order), _i32ptr(variant), _i64ptr(tiles)),
+            "dg_batch_groups",
+        )
+        names = {b: a for a, b in DGSolver.VARIANTS.items()}
+        return [(int(o), names[int(v)], int(t)) for o, v, t in zip(order, variant, tiles)]

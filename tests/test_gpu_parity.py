@@ -183,3 +183,33 @@ def test_device_tables_and_face_normals(physics):
         normals[:, :, i] = tr[:, :, 1 if physics == "acoustic" else 3 + i, 0]
     for f in range(4):
         np.testing.assert_allclose(normals[:, f], c.geo.normals[:, f], atol=1e-6)
+
+
+@pytest.mark.parametrize("N", DEGREES)
+def test_mfma_variant_parity(N):
+    """FP32 MFMA variant (acoustic): one right-hand side and 20 AB3 steps
+    against the oracle, on a mesh whose element count leaves a ragged tile."""
+    log(f"mfma variant acoustic N={N}")
+    c = Case("acoustic", N, 0, jitter=0.1, seed=50 + N, coef_kind="random", init="smooth",
+             dims=(3, 2, 3) if N <= 4 else (2, 2, 1))
+    c.solver.variant = "mfma"
+    assert c.solver.variant == "mfma"
+    r = c.solver.rhs(c.to_gpu(c.q0_gpu))
+    torch.cuda.synchronize()
+    err_r, _ = c.rel_l2(c.to_host(r), c.oracle.rhs(c.q0))
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    c.solver.step(20, c.dt)
+    q = c.to_host(c.solver.get_fields())
+    err_q, _ = c.rel_l2(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt))
+    log(f"  rhs rel L2 {err_r:.3e}, 20 steps {err_q:.3e}")
+    assert err_r <= 2e-6 and err_q <= 1e-5
+
+
+def test_variant_rejected_where_not_built():
+    from paper_1602_07997_amd._native import DG_E_UNSUPPORTED, DGError
+
+    c = Case("elastic", 2, 1, jitter=0.0, coef_kind="random", init="smooth")
+    with pytest.raises(DGError) as ei:
+        c.solver.variant = "mfma"
+    assert ei.value.status == DG_E_UNSUPPORTED
+    assert c.solver.variant == "valu"
