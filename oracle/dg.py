@@ -60,7 +60,11 @@ class _Base:
     def __init__(self, mesh: MeshGeometry, coef: np.ndarray):
         self.mesh = mesh
         self.ref = mesh.ref
-        self.coef = np.asarray(coef, dtype=float)
+        # real coefficients in float64; complex ones are kept (complex-step
+        # derivatives of functions of the coefficients)
+        self.coef = np.asarray(coef)
+        if not np.iscomplexobj(self.coef):
+            self.coef = self.coef.astype(float)
         if self.coef.shape != (mesh.K, self.ncoef):
             raise ValueError("coefficient array has the wrong shape")
         self.K = mesh.K
@@ -181,7 +185,7 @@ class ElasticOracle(_Base):
     def __init__(self, mesh, coef):
         super().__init__(mesh, coef)
         rho, lam, mu = self.coef[:, 0], self.coef[:, 1], self.coef[:, 2]
-        if np.any(mu <= 0.0):
+        if np.any(np.real(mu) <= 0.0):
             raise ValueError("the elastic flux needs mu > 0")
         self.rho, self.lam, self.mu = rho, lam, mu
         self.cp = np.sqrt((lam + 2.0 * mu) / rho)
