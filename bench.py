@@ -317,7 +317,7 @@ def main(argv=None):
     ap.add_argument("--config", choices=["acoustic", "elastic", "batched"], default="acoustic")
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
-    ap.add_argument("--variant", choices=["valu", "mfma", "auto"], default="auto")
+    ap.add_argument("--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "auto"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument(

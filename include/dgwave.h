@@ -137,14 +137,21 @@ void dg_destroy(dg_solver* s);
 /* Replace the stream used by later calls (hipStream_t, NULL = default). */
 dg_status dg_set_stream(dg_solver* s, void* stream);
 
-/* Kernel variant of the step (default DG_VARIANT_VALU).  Both compute the
- * same right-hand side of eqs. (5)-(6) / the elastic system and the update of
+/* Kernel variant of the step (default DG_VARIANT_VALU).  All compute the
+ * right-hand side of eqs. (5)-(6) / the elastic system and the update of
  * eq. (4); they differ in how the D_j and LIFT products run:
- *   DG_VARIANT_VALU  node per thread, vector ALU (all physics and degrees);
- *   DG_VARIANT_MFMA  16-element tiles on FP32 matrix cores (acoustic).
- * Returns DG_E_UNSUPPORTED for a combination that is not built.            */
+ *   DG_VARIANT_VALU       node per thread, vector ALU (all physics, degrees);
+ *   DG_VARIANT_MFMA       element tiles on FP32 matrix cores (acoustic);
+ *   DG_VARIANT_MFMA_BF16  BF16 matrix cores with FP32 accumulation, both
+ *                         operands split x = x_hi + x_lo and the products
+ *                         D_hi x_hi + D_hi x_lo + D_lo x_hi (acoustic);
+ *   DG_VARIANT_MFMA_F16   the same with FP16 halves (acoustic).
+ * Fields, r and the update stay FP32 in every variant.  Returns
+ * DG_E_UNSUPPORTED for a combination that is not built.                    */
 #define DG_VARIANT_VALU 0
 #define DG_VARIANT_MFMA 1
+#define DG_VARIANT_MFMA_BF16 2
+#define DG_VARIANT_MFMA_F16 3
 dg_status dg_set_variant(dg_solver* s, int variant);
 dg_status dg_get_variant(dg_solver* s, int* variant);
 
@@ -220,7 +227,7 @@ dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* byt
  * kernel per degree and mesh follows the observation of Sec. 4 that the best
  * implementation strategy depends on the degree.  Errors: DG_E_STATE (no
  * coefficients or fields), DG_E_ARG, DG_E_HIP.                              */
-#define DG_NUM_VARIANTS 2
+#define DG_NUM_VARIANTS 4
 dg_status dg_autotune(dg_solver* s, int steps, double dt, double* us_per_step);
 
 typedef struct dg_batch dg_batch;
@@ -260,6 +267,60 @@ dg_status dg_batch_step(dg_batch* b, int nsteps, const double* dt);
  * *ngroups on entry is their capacity (DG_E_SHAPE if too small); call with
  * NULL arrays first to ask for the count.                                   */
 dg_status dg_batch_groups(dg_batch* b, int* ngroups, int32_t* order, int32_t* variant, int64_t* tiles);
+
+/* ------------------------------------------------------------------------ */
+/* Misfit and its coefficient gradient (adjoint).                           */
+/* ------------------------------------------------------------------------ */
+
+/* Locate n points (host float64 [n][3]) in the solver's mesh: elem (host
+ * int64 [n]) the first element whose barycentric coordinates are all >=
+ * -1e-12, weights (host float64 [n][Np], may be NULL) the nodal Lagrange
+ * weights of the point (u(x) = weights . u_nodes; the expansion of eq. (1)).
+ * DG_E_ARG if a point lies outside the mesh.                                  */
+dg_status dg_locate_points(dg_solver* s, int64_t n, const double* xyz, int64_t* elem, double* weights);
+
+typedef struct dg_misfit dg_misfit;
+
+/* A least-squares problem on the solver's mesh and coefficients:
+ *   forward: q^0 = 0, steps of eq. (4) of size dt with the point source
+ *     f(t_m) b added to r^m, b = (1/J_k) M^{-1} l(x_s) (the projection of a
+ *     Dirac mass) in the source fields: acoustic p, elastic s11, s22, s33;
+ *     wavelet (host float64 [nsteps+1]) holds f(t_m), t_m = m dt;
+ *   receivers: u(t_m) = l(x_r) . q in the recorded fields (acoustic p;
+ *     elastic v1, v2, v3), channel index = receiver * fields + field;
+ *   misfit: J = 1/2 dt sum_{m=1..nsteps} sum_channels (u - d)^2.
+ * src_xyz / rec_xyz are host float64 [n][3].  The forward states are kept
+ * every checkpoint_every steps; the gradient recomputes the steps between
+ * checkpoints.  Device memory: about (checkpoint_every + 3 nsteps /
+ * checkpoint_every + 9) field arrays.  The solver must outlive the misfit;
+ * the misfit uses its own state buffers (the solver's fields are not
+ * touched).  Errors: DG_E_ARG (bad sizes, a point outside the mesh),
+ * DG_E_HIP.                                                                  */
+dg_status dg_misfit_create(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
+                           const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
+                           dg_misfit** out);
+void dg_misfit_destroy(dg_misfit* f);
+
+/* Number of receiver channels, or -1 for a NULL misfit. */
+int64_t dg_misfit_channels(dg_misfit* f);
+
+/* Forward solve with the solver's current coefficients.  data (device
+ * float32 [nsteps+1][channels], may be NULL) is copied; traces (device
+ * float32 [nsteps+1][channels], may be NULL) receives the receiver values;
+ * *J (host, may be NULL) the misfit against data (0 without data; the call
+ * then synchronises).  Errors: DG_E_STATE (no coefficients), DG_E_HIP.      */
+dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, double* J);
+
+/* Gradient of J with respect to the per-element coefficients (acoustic
+ * (rho, c), elastic (rho, lambda, mu)), device float32 [K][ncoef], by the
+ * discrete adjoint of the forward steps (exact up to rounding): the reverse
+ * recursion runs on the forward step kernel through A^T = P W A P W^{-1}
+ * (W the energy weight, P = -1 on velocities), checkpointed segments are
+ * recomputed, and the coefficient derivatives of the energy weight and of
+ * the upwind penalty are accumulated per element in float64.  Needs a
+ * preceding dg_misfit_forward with data and unchanged coefficients.
+ * Errors: DG_E_STATE, DG_E_HIP.                                             */
+dg_status dg_misfit_gradient(dg_misfit* f, float* grad);
 
 #ifdef __cplusplus
 }

@@ -6,10 +6,14 @@ library is loaded on first use of any of the names below, so that the build
 module can run before it exists.
 """
 
-__all__ = ["DGBatch", "DGSolver", "mesh_connectivity", "ref_sizes", "reference_operators"]
+__all__ = ["DGBatch", "DGMisfit", "DGSolver", "misfit", "mesh_connectivity", "ref_sizes", "reference_operators"]
 
 
 def __getattr__(name):
+    if name in ("DGMisfit", "misfit"):
+        from . import adjoint
+
+        return getattr(adjoint, name)
     if name in __all__:
         from . import solver
 

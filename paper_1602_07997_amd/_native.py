@@ -25,7 +25,9 @@ DG_ACOUSTIC = 0
 DG_ELASTIC = 1
 DG_VARIANT_VALU = 0
 DG_VARIANT_MFMA = 1
-DG_NUM_VARIANTS = 2
+DG_VARIANT_MFMA_BF16 = 2
+DG_VARIANT_MFMA_F16 = 3
+DG_NUM_VARIANTS = 4
 
 STATUS_NAMES = {
     DG_OK: "DG_OK",
@@ -90,6 +92,14 @@ SIGNATURES = {
     "dg_batch_set_graph": (C.c_int, [_p, C.c_int]),
     "dg_batch_step": (C.c_int, [_p, C.c_int, _dp]),
     "dg_batch_groups": (C.c_int, [_p, _ip, _i32p, _i32p, _i64p]),
+    "dg_locate_points": (C.c_int, [_p, _i64, _dp, _i64p, _dp]),
+    "dg_misfit_create": (
+        C.c_int, [_p, _i64, C.c_double, C.c_int, C.c_int, _dp, _dp, C.c_int, _dp, C.POINTER(_p)]
+    ),
+    "dg_misfit_destroy": (None, [_p]),
+    "dg_misfit_channels": (_i64, [_p]),
+    "dg_misfit_forward": (C.c_int, [_p, _p, _p, _dp]),
+    "dg_misfit_gradient": (C.c_int, [_p, _p]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

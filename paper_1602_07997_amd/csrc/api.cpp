@@ -11,6 +11,7 @@
 #include "dg_internal.hpp"
 #include "dgwave.h"
 #include "kernels.hpp"
+#include "mfma_pack.hpp"
 #include "solver_state.hpp"
 
 namespace dgw {
@@ -48,6 +49,11 @@ void free_all(dg_solver* s) {
                   s->mass, s->partial, s->e_out, s->flag, s->Dpack, s->Lpack};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (int v = 0; v < 2; ++v)
+    for (int h = 0; h < 2; ++h) {
+      if (s->D16[v][h]) (void)hipFree(s->D16[v][h]);
+      if (s->L16[v][h]) (void)hipFree(s->L16[v][h]);
+    }
 }
 
 size_t field_count(const dg_solver* s) { return static_cast<size_t>(s->K) * s->NF * s->Np; }
@@ -70,6 +76,11 @@ StepArgs base_args(const dg_solver* s) {
   a.nodeface = s->nodeface;
   a.Dpack = s->Dpack;
   a.Lpack = s->Lpack;
+  const int p16 = s->variant == kVariantMfmaF16 ? 1 : 0;
+  a.D16h = s->D16[p16][0];
+  a.D16l = s->D16[p16][1];
+  a.L16h = s->L16[p16][0];
+  a.L16l = s->L16[p16][1];
   a.xcd_remap = s->xcd_remap;
   return a;
 }
@@ -260,29 +271,22 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
       conn[s] = static_cast<int32_t>((kn << 5) | (static_cast<int64_t>(fn) << 3) | o);
     }
 
-  // ---- MFMA fragment-order packing: A[row = lane%16][k = 4*kk + lane/16] ----
-  const int MB = dgw::mfma_mblocks(order), KP = dgw::mfma_kpad(order), NFPP = dgw::mfma_face_pad(order);
-  const int KL = 4 * NFPP;
-  std::vector<float> Dpack(static_cast<size_t>(3) * MB * (KP / 4) * 64, 0.0f);
-  std::vector<float> Lpack(static_cast<size_t>(MB) * (KL / 4) * 64, 0.0f);
-  for (int j = 0; j < 3; ++j)
-    for (int mb = 0; mb < MB; ++mb)
-      for (int kk = 0; kk < KP / 4; ++kk)
-        for (int l = 0; l < 64; ++l) {
-          const int row = mb * 16 + l % 16, col = kk * 4 + l / 16;
-          if (row < Np && col < Np)
-            Dpack[((static_cast<size_t>(j) * MB + mb) * (KP / 4) + kk) * 64 + l] =
-                static_cast<float>(ref->D[(static_cast<size_t>(j) * Np + row) * Np + col]);
-        }
-  for (int mb = 0; mb < MB; ++mb)
-    for (int kl = 0; kl < KL / 4; ++kl)
-      for (int l = 0; l < 64; ++l) {
-        const int row = mb * 16 + l % 16, slot = kl * 4 + l / 16;
-        const int f = slot / NFPP, jj = slot % NFPP;
-        if (row < Np && jj < Nfp)
-          Lpack[(static_cast<size_t>(mb) * (KL / 4) + kl) * 64 + l] =
-              static_cast<float>(ref->lift[static_cast<size_t>(row) * 4 * Nfp + f * Nfp + jj]);
-      }
+  // ---- MFMA fragment packing (FP32, and the BF16 / FP16 hi + lo splits) ----
+  std::vector<float> Dpack, Lpack;
+  std::vector<uint16_t> D16[2][2], L16[2][2];  // [bf16, f16][hi, lo]
+  {
+    const dgw::MfmaPacking p32 = dgw::mfma_packing(order, dgw::kVariantMfma);
+    for (int j = 0; j < 3; ++j) dgw::pack_fp32(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p32.MB, p32.KP, Dpack);
+    dgw::pack_fp32(ref->lift.data(), Np, 4 * Nfp, p32.MB, p32.KL, Lpack);
+    const int vars[2] = {dgw::kVariantMfmaBf16, dgw::kVariantMfmaF16};
+    for (int v = 0; v < 2; ++v) {
+      const dgw::MfmaPacking p16 = dgw::mfma_packing(order, vars[v]);
+      for (int j = 0; j < 3; ++j)
+        dgw::pack_split16(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p16.MB, p16.KP, v == 0,
+                          D16[v][0], D16[v][1]);
+      dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, v == 0, L16[v][0], L16[v][1]);
+    }
+  }
 
   // ---- operators in the kernels' layouts (float32) ----
   std::vector<float> DT(3 * static_cast<size_t>(Np) * Np), LT(static_cast<size_t>(4) * Nfp * Np);
@@ -342,6 +346,17 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
   if ((err = dev_alloc(&s->flag, 1)) != hipSuccess) return fail(err, "alloc flag");
   if ((err = dev_alloc(&s->Dpack, Dpack.size())) != hipSuccess) return fail(err, "alloc Dpack");
   if ((err = dev_alloc(&s->Lpack, Lpack.size())) != hipSuccess) return fail(err, "alloc Lpack");
+  for (int v = 0; v < 2; ++v)
+    for (int h = 0; h < 2; ++h) {
+      if ((err = dev_alloc(&s->D16[v][h], D16[v][h].size())) != hipSuccess) return fail(err, "alloc D16");
+      if ((err = dev_alloc(&s->L16[v][h], L16[v][h].size())) != hipSuccess) return fail(err, "alloc L16");
+      if ((err = hipMemcpy(s->D16[v][h], D16[v][h].data(), D16[v][h].size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(err, "upload D16");
+      if ((err = hipMemcpy(s->L16[v][h], L16[v][h].data(), L16[v][h].size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(err, "upload L16");
+    }
 
   struct Up {
     void* dst;

@@ -23,6 +23,9 @@ struct RefElement {
   std::vector<double> nodes;   // [Np][3]
   std::vector<double> D;       // [3][Np][Np]
   std::vector<double> mass;    // [Np][Np]
+  std::vector<double> minv;    // [Np][Np] inverse mass matrix
+  std::vector<double> vinv;    // [Np][Np] inverse Vandermonde of the orthonormal basis
+  std::vector<double> face_mass;  // [Nfp][Nfp] face mass in the parameter triangle
   std::vector<double> lift;    // [Np][4*Nfp]
   std::vector<int32_t> fmask;  // [4][Nfp]
   std::vector<int32_t> perm;   // [6][Nfp]
@@ -31,6 +34,9 @@ struct RefElement {
 
 // Builds (and caches) the reference element; returns nullptr for bad N.
 const RefElement* reference_element(int N);
+
+// Lagrange weights of the nodal basis at reference point xi: w [Np].
+void lagrange_weights(const RefElement* ref, const double xi[3], double* w);
 
 // Face connectivity from topological vertex ids; returns an error message or "".
 std::string connect_faces(int64_t K, const int64_t* topo, int64_t* e2e, int32_t* e2f,

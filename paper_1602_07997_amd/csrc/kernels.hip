@@ -609,17 +609,17 @@ int64_t energy_blocks_impl(int N, int64_t K) {
 int coef_block(int physics) { return physics == 0 ? Phys<0>::CB : Phys<1>::CB; }
 int num_traces(int physics) { return physics == 0 ? Phys<0>::NT : Phys<1>::NT; }
 
-hipError_t launch_step_mfma(int physics, int N, const StepArgs& a, hipStream_t s);
+static bool is_mfma(int variant) { return mfma_precision(variant) >= 0; }
 
 bool variant_supported(int physics, int N, int variant) {
   if (N < 1 || N > 8 || (physics != 0 && physics != 1)) return false;
   if (variant == kVariantValu) return true;
-  if (variant == kVariantMfma) return physics == 0;
+  if (is_mfma(variant)) return physics == 0;
   return false;
 }
 
 hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
-  if (variant == kVariantMfma) return launch_step_mfma(physics, N, a, s);
+  if (is_mfma(variant)) return launch_step_mfma(physics, N, variant, a, s);
   if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_impl<n, p>(a, s)
   if (physics == 0) {
@@ -656,7 +656,7 @@ int64_t tiles_for(int physics, int N, int variant, int64_t K) {
 
 int tile_elements(int physics, int N, int variant) {
   if (!variant_supported(physics, N, variant)) return -1;
-  if (variant == kVariantMfma) return mfma_tile_elements(N);
+  if (is_mfma(variant)) return mfma_packing(N, variant).E;
 #define TE(n, p) Tile<n, p>::KT
   if (physics == 0) {
     switch (N) {
@@ -673,12 +673,10 @@ int tile_elements(int physics, int N, int variant) {
   return -1;
 }
 
-hipError_t launch_step_batch_mfma(int physics, int N, const StepArgs* args, const int2* work, int64_t ntiles,
-                                  int phase, hipStream_t s);
 
 hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* args, const int2* work,
                              int64_t ntiles, int phase, hipStream_t s) {
-  if (variant == kVariantMfma) return launch_step_batch_mfma(physics, N, args, work, ntiles, phase, s);
+  if (is_mfma(variant)) return launch_step_batch_mfma(physics, N, variant, args, work, ntiles, phase, s);
   if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_batch_impl<n, p>(args, work, ntiles, phase, s)
   if (physics == 0) {

@@ -25,8 +25,12 @@ struct StepArgs {
   const int32_t* fmask;  // [4][NFP]
   const int32_t* perm;   // [6][NFP]
   const int32_t* nodeface;  // [NP][3] face slots f*NFP+j containing node n, -1 padded
-  const float* Dpack;    // MFMA variant: D_j in 16x4 fragment order [3][MB][KP/4][64]
-  const float* Lpack;    // MFMA variant: LIFT, face blocks padded to NFPP, [MB][4*NFPP/4][64]
+  const float* Dpack;    // FP32 MFMA: D_j in 16x4 fragment order [3][MB][KP/4][64]
+  const float* Lpack;    // FP32 MFMA: merged LIFT [MB][KL/4][64]
+  const uint16_t* D16h;  // 16-bit MFMA: D_j split hi / lo, 16x16 fragments [3][MB][KP/16][64][4]
+  const uint16_t* D16l;
+  const uint16_t* L16h;  // 16-bit MFMA: merged LIFT split hi / lo [MB][KL/16][64][4]
+  const uint16_t* L16l;
   float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
   int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))
   int xcd_remap;         // map consecutive tiles onto one XCD
@@ -41,14 +45,23 @@ int coef_block(int physics);
 int num_traces(int physics);
 
 // Kernel variants of the step.
-constexpr int kVariantValu = 0;  // node per thread, VALU contractions
-constexpr int kVariantMfma = 1;  // element tiles, FP32 MFMA contractions
+constexpr int kVariantValu = 0;      // node per thread, VALU contractions
+constexpr int kVariantMfma = 1;      // element tiles, FP32 MFMA contractions
+constexpr int kVariantMfmaBf16 = 2;  // BF16 MFMA, three split products, FP32 accumulation
+constexpr int kVariantMfmaF16 = 3;   // FP16 MFMA, three split products, FP32 accumulation
+constexpr int kNumVariants = 4;
 bool variant_supported(int physics, int N, int variant);
 
-// Fragment-order packing used by the MFMA variant (host side).
-int mfma_mblocks(int N);        // ceil(Np / 16)
-int mfma_kpad(int N);           // Np rounded up to a multiple of 4
-int mfma_face_pad(int N);       // Nfp rounded up to a multiple of 4
+// Fragment packing of the MFMA variants: node blocks MB, padded volume K (KP)
+// and LIFT K (KL), k per instruction KS, elements per tile E.
+struct MfmaPacking {
+  int MB = 0, KP = 0, KL = 0, KS = 0, E = 0;
+};
+int mfma_precision(int variant);  // 0 FP32, 1 BF16, 2 FP16, -1 not an MFMA variant
+MfmaPacking mfma_packing(int N, int variant);
+hipError_t launch_step_mfma(int physics, int N, int variant, const StepArgs& a, hipStream_t s);
+hipError_t launch_step_batch_mfma(int physics, int N, int variant, const StepArgs* args, const int2* work,
+                                  int64_t ntiles, int phase, hipStream_t s);
 
 hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s);
 
@@ -57,9 +70,58 @@ hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipSt
 constexpr int kBatchPhases = 6;
 int tile_elements(int physics, int N, int variant);  // elements per workgroup tile
 int64_t tiles_for(int physics, int N, int variant, int64_t K);
-int mfma_tile_elements(int N);
 hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* args, const int2* work,
                              int64_t ntiles, int phase, hipStream_t s);
+// Point injection: for each distinct element elem[u], entries
+// e in [start[u], start[u+1]) add a_e * vec[e][:] to q[elem[u]][field[e]][:],
+// a_e = amp when chan[e] < 0, else traces[chan[e]] - data[chan[e]]; the
+// element's own traces in qf are then rewritten.
+struct InjectArgs {
+  int nelem;
+  float* q;
+  float* qf;
+  const float* geo;
+  const int32_t* fmask;
+  const int64_t* elem;    // [nelem]
+  const int32_t* start;   // [nelem + 1]
+  const int32_t* field;   // [entries]
+  const int32_t* chan;    // [entries]
+  const float* vec;       // [entries][Np]
+  float amp;
+  const float* traces;    // receiver values of this step (chan >= 0 entries)
+  const float* data;      // data of this step
+};
+hipError_t launch_inject(int physics, int N, const InjectArgs& a, hipStream_t s);
+// out[ch] = w[ch] . q[elem[ch]][field[ch]][:]
+hipError_t launch_record(int physics, int N, int nch, const float* q, const int64_t* elem, const int32_t* field,
+                         const float* w, float* out, hipStream_t s);
+
+// Per-step accumulation of the coefficient gradient (see kernels_adjoint.hip).
+constexpr int kGradAccStride = 20;  // float64 accumulators per element
+struct GradArgs {
+  int64_t K;
+  const float* phi1;      // phi_{m+1}, phi_{m+2}, phi_{m+3}
+  const float* phi2;
+  const float* phi3;
+  float c0, c1, c2;       // chi_m = c0 phi1 + c1 phi2 + c2 phi3
+  const float* r;         // A q_m  [K][NF][Np]
+  const float* tr;        // traces of q_m [K][4][NT][Nfp]
+  const float* geo;
+  const float* cf;
+  const int32_t* conn;
+  const int32_t* fmask;
+  const int32_t* perm;
+  const float* mass;      // [Np][Np]
+  const float* face_mass; // [Nfp][Nfp]
+  const double* J;        // [K]
+  double* gacc;           // [K][kGradAccStride]
+};
+hipError_t launch_grad_accum(int physics, int N, const GradArgs& a, hipStream_t s);
+hipError_t launch_grad_finalize(int physics, int64_t K, const double* gacc, const int32_t* conn, const float* coef,
+                                float* grad, hipStream_t s);
+hipError_t launch_fill_zero_f64(int64_t n, double* p, hipStream_t s);
+hipError_t launch_fill_zero_f32(int64_t n, float* p, hipStream_t s);
+
 hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const float* geo,
                          const int32_t* fmask, float* qf, hipStream_t s);
 hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int32_t* conn,

@@ -1,21 +1,37 @@
-// MFMA variant of the fused DG step (acoustic), FP32 matrix cores on gfx950.
+// MFMA variants of the fused DG step (acoustic), gfx950 matrix cores.
 //
 // The volume and LIFT products of eqs. (5)-(6) become small GEMMs with the
-// element as the column index: for a tile of E = 16*NBLK elements
-//   T_j   = D_j p                       (3 products [Np x Np][Np x E])
-//   div   = sum_j D_j U_j,  U_j = sum_i g_ij v_i      (same D_j fragments)
-//   Lp    = L Pp            (merged LIFT of the pressure penalty, all faces)
-//   Lv_f  = L_f Pv_f        (LIFT of the scalar velocity penalty, per face;
-//                            the face normal is applied afterwards)
-// on v_mfma_f32_16x16x4_f32.  A operands (D_j, L) are packed on the host in
-// 16x4 fragment order so that every A load is one coalesced 256-byte access;
-// B operands come from LDS laid out [field][node][element] with the element
-// fastest.  Each (16-row node block, 16-element column block) pair of the
-// tile is owned by one wave, whose accumulators hold all four fields of its
-// nodes: the epilogue combines them with the element's geometry and
-// coefficients, applies the AB3 update and writes q, r and the own traces,
-// exactly as the node-per-thread variant does.
+// element as the column index.  For a tile of E = 16 NBLK elements:
+//   T_j = D_j p,   dv = sum_j D_j U_j  (U_j = sum_i g_ij v_i)    K = Np
+//   lp  = L Pp,    lv_i = L (Pv n_i)   (L the merged LIFT)       K = 4 Nfp
+// with Pp = Fscale rho c^2 k_c alpha and Pv = -Fscale c k_c alpha the
+// upwind penalties of Sec. 2.1 at every face node.  Three precisions:
+//   PREC 0  FP32 v_mfma_f32_16x16x4_f32;
+//   PREC 1  BF16 v_mfma_f32_16x16x16_bf16 with FP32 accumulation and the
+//           split x = x_hi + x_lo of both operands, D x ~ D_hi x_hi +
+//           D_hi x_lo + D_lo x_hi (the dropped D_lo x_lo is ~2^-16 |D||x|);
+//   PREC 2  FP16 v_mfma_f32_16x16x16_f16 with the same three products
+//           (~2^-22 |D||x| dropped).
+// Operators are split and packed on the host in fragment order; the
+// right-hand operands (p, U_j, the penalties) are formed and split once per
+// tile in LDS.  Fields, r and the update stay FP32.
+//
+// Phases of one workgroup (4 wavefronts):
+//   A1  per-element constants and face records into LDS; connectivity words
+//       and neighbour traces of the tile's face nodes into registers;
+//   A2  p and U_j of every node into LDS (B operands); upwind alpha of every
+//       face node into registers;
+//   C1  volume products, one (16-node block, 16-element block) pair per
+//       wavefront in turn;
+//   B2  penalty operands into the same LDS region;
+//   C2  LIFT products, then the epilogue: the pair's right-hand sides are
+//       combined in the accumulator layout, transposed through a per-wave LDS
+//       scratch so that every global access is a run of 16 consecutive
+//       nodes, and the AB3 update, q / r writes and own-trace emission
+//       follow.
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
 
 #include "dg_device.hpp"
 #include "kernels.hpp"
@@ -27,25 +43,28 @@ namespace {
 using namespace dev;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 
-template <int N>
-struct MfmaShape {
+constexpr int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+template <int N, int PREC>
+struct MShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
-  static constexpr int MB = (NP + 15) / 16;       // 16-row node blocks
-  static constexpr int KP = (NP + 3) / 4 * 4;     // K padding of the volume products
-  static constexpr int NFPP = (NFP + 3) / 4 * 4;  // each face's block padded to whole k-steps
-  static constexpr int KL = 4 * NFPP;             // K of the LIFT product
-  // 16-element column blocks per workgroup: enough (node block, column block)
-  // pairs for four waves while the LDS tile stays small.
-  static constexpr int NBLK = (N <= 4) ? 4 : (N == 6 ? 2 : 1);
-  static constexpr int E = 16 * NBLK;
-  static constexpr int ES = E;  // LDS row stride of the B operands
+  static constexpr int KS = PREC == 0 ? 4 : 16;  // k per instruction
+  static constexpr int MB = (NP + 15) / 16;      // 16-row node blocks
+  static constexpr int KP = rup(NP, KS);         // volume K, zero padded
+  static constexpr int KL = rup(4 * NFP, KS);    // LIFT K (merged faces), zero padded
+  static constexpr int KMAX = KP > KL ? KP : KL;
+  static constexpr int NBLK = (N <= 2) ? 4 : (N == 3 ? 2 : 1);
+  static constexpr int E = 16 * NBLK;            // elements per tile
+  static constexpr int PAIRS = MB * NBLK;
+  static constexpr int REGION = 4 * KMAX * E;    // 4-byte words of B operands
 };
 
-// Column swizzle of the [row][element] B-operand arrays (row stride E): a
-// bijection on [0, E) per row chosen so that the 16x4 fragment reads (lanes
-// split over four consecutive rows) and the staging writes (consecutive rows,
-// one element) both touch 32 distinct LDS banks.
+// Column swizzle of the FP32 [row][E] operand arrays: a bijection on [0, E)
+// per row that keeps the fragment reads conflict-free and spreads the
+// row-consecutive staging writes over the banks.
 template <int E>
 __device__ __forceinline__ int swz(int m, int e) {
   if constexpr (E == 16)
@@ -54,25 +73,91 @@ __device__ __forceinline__ int swz(int m, int e) {
     return (((e >> 4) ^ (m & 1)) << 4) + ((e & 15) ^ ((m >> 1) & 15));
 }
 
-__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+// Round to nearest even: float -> bfloat16 bits.
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+// x = hi + lo in the 16-bit format of PREC (bit patterns).
+template <int PREC>
+__device__ __forceinline__ void split16(float x, uint16_t& hi, uint16_t& lo) {
+  if constexpr (PREC == 1) {
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+  } else {
+    const _Float16 h = static_cast<_Float16>(x);
+    const _Float16 l = static_cast<_Float16>(x - static_cast<float>(h));
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  }
+}
+
+// B operand region: set s (0..3), row k, column e.
+//   FP32:   word s*KMAX*E + k*E + swz(k, e)
+//   16-bit: hi at unit s*KMAX*E + ((k/4)*E + e)*4 + k%4, lo 4*KMAX*E units later
+template <int N, int PREC>
+struct BRegion {
+  using S = MShape<N, PREC>;
+  float* w;
+  __device__ __forceinline__ void put(int s, int k, int e, float x) const {
+    if constexpr (PREC == 0) {
+      w[(s * S::KMAX + k) * S::E + swz<S::E>(k, e)] = x;
+    } else {
+      uint16_t* u = reinterpret_cast<uint16_t*>(w);
+      uint16_t hi, lo;
+      split16<PREC>(x, hi, lo);
+      const int idx = s * S::KMAX * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+      u[idx] = hi;
+      u[4 * S::KMAX * S::E + idx] = lo;
+    }
+  }
+};
+
+struct Frag16 {
+  shortx4 hi, lo;
+};
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int N>
-__device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) {
-  using S = MfmaShape<N>;
-  constexpr int NP = S::NP, NFP = S::NFP, NFN = 4 * NFP;
-  constexpr int MB = S::MB, KP = S::KP, NFPP = S::NFPP, KL = S::KL;
-  constexpr int NBLK = S::NBLK, E = S::E, ES = S::ES;
-  constexpr int NF = 4, NT = 2, CB = 8;
-  constexpr int FIT = (E * NFN + kThreads - 1) / kThreads;
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma16(shortx4 a, shortx4 b, floatx4 c) {
+  if constexpr (PREC == 1) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(halfx4, a), __builtin_bit_cast(halfx4, b), c,
+                                                 0, 0, 0);
+  }
+}
 
-  __shared__ float s_q[NF * KP * ES];  // [c][m][e]
-  __shared__ float s_fl[2 * KL * ES];  // [scalar][f*NFPP + j][e]
+// acc += A B with the split products (small terms first)
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma_split(const Frag16& a, const Frag16& b, floatx4 c) {
+  c = mfma16<PREC>(a.lo, b.hi, c);
+  c = mfma16<PREC>(a.hi, b.lo, c);
+  return mfma16<PREC>(a.hi, b.hi, c);
+}
+
+template <int N, int PREC>
+__device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) {
+  using S = MShape<N, PREC>;
+  constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KMAX = S::KMAX, E = S::E;
+  constexpr int NF = 4, NT = 2, CB = 8;
+  constexpr int FW = FaceRec<0>::W;
+  constexpr int NIT = (E * KP + kThreads - 1) / kThreads;  // node items (incl. padding) per thread
+  constexpr int FIT = (E * KL + kThreads - 1) / kThreads;  // face-slot items (incl. padding) per thread
+  constexpr int SCR = 16 * 17;                             // per-wave transpose scratch
+  constexpr int PPW = (S::PAIRS + 3) / 4;                  // pairs per wavefront (at most)
+
+  __shared__ float s_B[S::REGION];
   __shared__ float s_g[E * 9];
   __shared__ float s_cf[E * CB];
-  constexpr int FW = FaceRec<0>::W;
   __shared__ float s_face[E * 4 * FW];
+  __shared__ float s_scr[4 * SCR];
 
   const int64_t e0 = tile * E;
   if (e0 >= a.K) return;  // whole workgroup exits together
@@ -80,262 +165,382 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const bool step = (a.mode == kStepMode);
+  const BRegion<N, PREC> breg{s_B};
 
-  // ---- phase A: neighbour traces, zero padding, tile staging --------------
-  int word[FIT];
-  float nbt[FIT][NT];
+  // ---- A1: constants, face records, neighbour traces ----------------------
+  for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
+  for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
+  for (int i = tid; i < ne * 4; i += kThreads) {
+    const int e = i >> 2, f = i & 3;
+    face_record<0>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
+  }
+  // face-slot items: i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP
+  float pP[FIT], vnP[FIT];
+  bool wall[FIT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kThreads;
-    word[t] = 7;
-    nbt[t][0] = nbt[t][1] = 0.0f;
-    if (i < ne * NFN) {
-      const int e = i / NFN, fn = i - e * NFN;
-      const int f = fn / NFP, j = fn - f * NFP;
+    pP[t] = vnP[t] = 0.0f;
+    wall[t] = true;
+    const int e = i / KL, slot = i - e * KL;
+    if (e < ne && slot < 4 * NFP) {
+      const int f = slot / NFP, j = slot - f * NFP;
       const int w = a.conn[(e0 + e) * 4 + f];
-      word[t] = w;
-      if ((w & 7) != 7) {
+      wall[t] = (w & 7) == 7;
+      if (!wall[t]) {
         const int64_t kn = static_cast<int64_t>(w >> 5);
         const int fnb = (w >> 3) & 3;
         const int jn = a.perm[(w & 7) * NFP + j];
         const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
-        nbt[t][0] = tr[0];
-        nbt[t][1] = tr[NFP];
+        pP[t] = tr[0];
+        vnP[t] = -tr[NFP];  // the neighbour stored v.n with its own normal
       }
-    }
-  }
-  // padded rows (m >= NP) and padded columns (e >= ne) of the B operands are 0
-  for (int i = tid; i < NF * KP * ES; i += kThreads) {
-    const int row = i / ES, m = row % KP, e = i % ES;
-    if (m >= NP || e >= ne) s_q[row * ES + swz<E>(m, e)] = 0.0f;
-  }
-  for (int i = tid; i < 2 * KL * ES; i += kThreads) s_fl[i] = 0.0f;
-  {
-    const float* src = a.q_in + e0 * NF * NP;
-    for (int i = tid; i < ne * NF * NP; i += kThreads) {
-      const int e = i / (NF * NP), rem = i - e * (NF * NP);
-      const int c = rem / NP, m = rem - c * NP;
-      s_q[(c * KP + m) * ES + swz<E>(m, e)] = src[i];
-    }
-    for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
-    for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
-    for (int i = tid; i < ne * 4; i += kThreads) {
-      const int e = i >> 2, f = i & 3;
-      face_record<0>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
     }
   }
   __syncthreads();
 
-  // ---- phase B: upwind penalties times Fscale at the real face nodes -------
+  // ---- A2: volume operands p, U_j; upwind alpha at the face slots ---------
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i >= E * KP) continue;
+    // items over (e, n) with n < KP so that the zero padding is written too
+    const int e = i / KP, n = i - e * KP;
+    float p = 0.f, u0 = 0.f, u1 = 0.f, u2 = 0.f;
+    if (e < ne && n < NP) {
+      const float* qe = a.q_in + (e0 + e) * NF * NP;
+      p = qe[n];
+      const float v0 = qe[NP + n], v1 = qe[2 * NP + n], v2 = qe[3 * NP + n];
+      const float* G = s_g + 9 * e;
+      u0 = G[0] * v0 + G[3] * v1 + G[6] * v2;
+      u1 = G[1] * v0 + G[4] * v1 + G[7] * v2;
+      u2 = G[2] * v0 + G[5] * v1 + G[8] * v2;
+    }
+    breg.put(0, n, e, p);
+    breg.put(1, n, e, u0);
+    breg.put(2, n, e, u1);
+    breg.put(3, n, e, u2);
+  }
+  float alpha[FIT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kThreads;
-    if (i >= ne * NFN) continue;
-    const int e = i / NFN, fn = i - e * NFN;
-    const int f = fn / NFP, j = fn - f * NFP;
-    const float* rec = s_face + (e * 4 + f) * FW;
-    const float nrm[3] = {rec[0], rec[1], rec[2]};
-    const int vn = a.fmask[f * NFP + j];
-    const bool wall = (word[t] & 7) == 7;
-    const int cv = swz<E>(vn, e);
-    const float pM = s_q[(0 * KP + vn) * ES + cv];
-    const float vnM = nrm[0] * s_q[(1 * KP + vn) * ES + cv] + nrm[1] * s_q[(2 * KP + vn) * ES + cv] +
-                      nrm[2] * s_q[(3 * KP + vn) * ES + cv];
-    // rigid wall: mirror state p+ = p-, v.n+ = -v.n-
-    const float pP = wall ? pM : nbt[t][0];
-    const float vnP = wall ? -vnM : -nbt[t][1];  // neighbour stored v.n with its own normal
-    const float alpha = 0.5f * (pP - pM) - rec[3] * 0.5f * (vnP - vnM);
-    const int slot = f * NFPP + j;
-    const int cs = swz<E>(slot, e);
-    s_fl[(0 * KL + slot) * ES + cs] = rec[4] * alpha;
-    s_fl[(1 * KL + slot) * ES + cs] = rec[5] * alpha;
+    alpha[t] = 0.0f;
+    const int e = i / KL, slot = i - e * KL;
+    if (e < ne && slot < 4 * NFP) {
+      const int f = slot / NFP, j = slot - f * NFP;
+      const float* rec = s_face + (e * 4 + f) * FW;
+      const int vn = a.fmask[f * NFP + j];
+      const float* qe = a.q_in + (e0 + e) * NF * NP;
+      const float pM = qe[vn];
+      const float vnM = rec[0] * qe[NP + vn] + rec[1] * qe[2 * NP + vn] + rec[2] * qe[3 * NP + vn];
+      // rigid wall: mirror state p+ = p-, v.n+ = -v.n-
+      const float pp = wall[t] ? pM : pP[t];
+      const float vp = wall[t] ? -vnM : vnP[t];
+      alpha[t] = 0.5f * (pp - pM) - rec[3] * 0.5f * (vp - vnM);
+    }
   }
   __syncthreads();
 
-  // ---- phase C: one (node block, column block) pair per wave --------------
-  const int kq = lane >> 4;  // k offset of this lane in a 16x4 fragment / row quad of C
-  for (int p = wave; p < MB * NBLK; p += 4) {
+  // ---- C1: volume products ---------------------------------------------------
+  const int kq = lane >> 4;  // row quad of the accumulator / k group of the operands
+  floatx4 T0[PPW], T1[PPW], T2[PPW], DV[PPW];
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+    const int p = wave + 4 * q;
+    T0[q] = T1[q] = T2[q] = DV[q] = floatx4{0, 0, 0, 0};
+    if (p >= S::PAIRS) continue;
     const int mb = p % MB, nb = p / MB;
-    const int el = nb * 16 + (lane & 15);  // this lane's element (column)
-    const bool live = el < ne;
-    float G[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) G[t] = live ? s_g[el * 9 + t] : 0.0f;
-    // AB3 history of this lane's four nodes, issued before the products
-    float h1[4][NF], h2[4][NF];
-    const bool use1 = step && (a.c1 != 0.0f), use2 = step && (a.c2 != 0.0f);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int n = mb * 16 + 4 * kq + r;
-      const bool ok = live && n < NP;
-      const int64_t base = (e0 + el) * NF * NP + n;
-#pragma unroll
-      for (int c = 0; c < NF; ++c) {
-        h1[r][c] = (ok && use1) ? a.r1[base + c * NP] : 0.0f;
-        h2[r][c] = (ok && use2) ? a.r2[base + c * NP] : 0.0f;
+    const int col = nb * 16 + (lane & 15);
+    if constexpr (PREC == 0) {
+      const float* Dp = a.Dpack + static_cast<int64_t>(mb) * (KP / 4) * 64 + lane;
+      constexpr int JS = MB * (KP / 4) * 64;
+#pragma unroll 4
+      for (int kk = 0; kk < KP / 4; ++kk) {
+        const int k = kk * 4 + kq;
+        const int c = swz<E>(k, col);
+        const float bp = s_B[(0 * KMAX + k) * E + c];
+        const float b0 = s_B[(1 * KMAX + k) * E + c];
+        const float b1 = s_B[(2 * KMAX + k) * E + c];
+        const float b2 = s_B[(3 * KMAX + k) * E + c];
+        const float a0 = Dp[kk * 64], a1 = Dp[JS + kk * 64], a2 = Dp[2 * JS + kk * 64];
+        T0[q] = mfma_f32(a0, bp, T0[q]);
+        T1[q] = mfma_f32(a1, bp, T1[q]);
+        T2[q] = mfma_f32(a2, bp, T2[q]);
+        DV[q] = mfma_f32(a0, b0, DV[q]);
+        DV[q] = mfma_f32(a1, b1, DV[q]);
+        DV[q] = mfma_f32(a2, b2, DV[q]);
+      }
+    } else {
+      const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
+      constexpr int LO = 4 * KMAX * E;
+      constexpr int JS = MB * (KP / 16) * 64;  // fragments between D_0, D_1, D_2
+      const shortx4* Dh = reinterpret_cast<const shortx4*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
+      const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
+#pragma unroll 2
+      for (int kk = 0; kk < KP / 16; ++kk) {
+        const int off = ((kk * 4 + kq) * E + col) * 4;
+        Frag16 bp, b0, b1, b2;
+        bp.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
+        bp.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
+        b0.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
+        b0.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
+        b1.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
+        b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
+        b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
+        b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
+        const Frag16 a0{Dh[kk * 64], Dl[kk * 64]};
+        const Frag16 a1{Dh[JS + kk * 64], Dl[JS + kk * 64]};
+        const Frag16 a2{Dh[2 * JS + kk * 64], Dl[2 * JS + kk * 64]};
+        T0[q] = mfma_split<PREC>(a0, bp, T0[q]);
+        T1[q] = mfma_split<PREC>(a1, bp, T1[q]);
+        T2[q] = mfma_split<PREC>(a2, bp, T2[q]);
+        DV[q] = mfma_split<PREC>(a0, b0, DV[q]);
+        DV[q] = mfma_split<PREC>(a1, b1, DV[q]);
+        DV[q] = mfma_split<PREC>(a2, b2, DV[q]);
       }
     }
-    floatx4 T0 = {0, 0, 0, 0}, T1 = T0, T2 = T0, d0 = T0, d1 = T0, d2 = T0;
-    const float* Dp = a.Dpack + static_cast<int64_t>(mb) * (KP / 4) * 64 + lane;
-    constexpr int JS = MB * (KP / 4) * 64;  // stride between D_0, D_1, D_2
-    // fully unrolled so that the A fragments of all k-steps are requested
-    // before the first product needs them
-#pragma unroll
-    for (int kk = 0; kk < KP / 4; ++kk) {
-      const int m = kk * 4 + kq;
-      const int cm = swz<E>(m, el);
-      const float bp = s_q[(0 * KP + m) * ES + cm];
-      const float v0 = s_q[(1 * KP + m) * ES + cm];
-      const float v1 = s_q[(2 * KP + m) * ES + cm];
-      const float v2 = s_q[(3 * KP + m) * ES + cm];
-      const float u0 = G[0] * v0 + G[3] * v1 + G[6] * v2;
-      const float u1 = G[1] * v0 + G[4] * v1 + G[7] * v2;
-      const float u2 = G[2] * v0 + G[5] * v1 + G[8] * v2;
-      const float a0 = Dp[kk * 64], a1 = Dp[JS + kk * 64], a2 = Dp[2 * JS + kk * 64];
-      T0 = mfma4(a0, bp, T0);
-      d0 = mfma4(a0, u0, d0);
-      T1 = mfma4(a1, bp, T1);
-      d1 = mfma4(a1, u1, d1);
-      T2 = mfma4(a2, bp, T2);
-      d2 = mfma4(a2, u2, d2);
-    }
-    floatx4 lp = {0, 0, 0, 0}, lv0 = lp, lv1 = lp, lv2 = lp, lv3 = lp;
-    const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
-#define DGW_LIFT_FACE(F, ACC)                                                   \
-  _Pragma("unroll") for (int kf = 0; kf < NFPP / 4; ++kf) {                     \
-    const int kl = (F) * (NFPP / 4) + kf;                                       \
-    const int slot = kl * 4 + kq;                                               \
-    const int csl = swz<E>(slot, el);                                           \
-    const float bfp = s_fl[(0 * KL + slot) * ES + csl];                         \
-    const float bfv = s_fl[(1 * KL + slot) * ES + csl];                         \
-    const float al = Lp[kl * 64];                                               \
-    lp = mfma4(al, bfp, lp);                                                    \
-    ACC = mfma4(al, bfv, ACC);                                                  \
   }
-    DGW_LIFT_FACE(0, lv0)
-    DGW_LIFT_FACE(1, lv1)
-    DGW_LIFT_FACE(2, lv2)
-    DGW_LIFT_FACE(3, lv3)
-#undef DGW_LIFT_FACE
-    if (!live) continue;
-    const float* cf = s_cf + el * CB;
-    const float rc2 = cf[0], irho = cf[1];
-    const float* fr = s_face + el * 4 * FW;
+  __syncthreads();
+
+  // ---- B2: penalty operands (the region is reused) -------------------------
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int n = mb * 16 + 4 * kq + r;
-      if (n >= NP) continue;
-      float rr[NF];
-      rr[0] = -rc2 * (d0[r] + d1[r] + d2[r]) + lp[r];
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i >= E * KL) continue;
+    const int e = i / KL, slot = i - e * KL;
+    float fp = 0.f, f0 = 0.f, f1 = 0.f, f2 = 0.f;
+    if (e < ne && slot < 4 * NFP) {
+      const int f = slot / NFP;
+      const float* rec = s_face + (e * 4 + f) * FW;
+      fp = rec[4] * alpha[t];
+      const float fv = rec[5] * alpha[t];
+      f0 = fv * rec[0];
+      f1 = fv * rec[1];
+      f2 = fv * rec[2];
+    }
+    breg.put(0, slot, e, fp);
+    breg.put(1, slot, e, f0);
+    breg.put(2, slot, e, f1);
+    breg.put(3, slot, e, f2);
+  }
+  __syncthreads();
+
+  // ---- C2: LIFT products and the epilogue, pair by pair ---------------------
+  float* scr = s_scr + wave * SCR;
+  const int nl = lane & 15, eg = lane >> 4;
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii)
-        rr[1 + ii] = -irho * (G[3 * ii + 0] * T0[r] + G[3 * ii + 1] * T1[r] + G[3 * ii + 2] * T2[r]) +
-                     (fr[0 * FW + ii] * lv0[r] + fr[1 * FW + ii] * lv1[r] + fr[2 * FW + ii] * lv2[r] +
-                      fr[3 * FW + ii] * lv3[r]);
-      const int64_t base = (e0 + el) * NF * NP + n;
-      if (!step) {
-#pragma unroll
-        for (int c = 0; c < NF; ++c) a.r_out[base + c * NP] = rr[c];
-        continue;
+  for (int q = 0; q < PPW; ++q) {
+    const int p = wave + 4 * q;
+    if (p >= S::PAIRS) continue;
+    const int mb = p % MB, nb = p / MB;
+    const int col = nb * 16 + nl;
+    floatx4 lp = {0, 0, 0, 0}, l0 = lp, l1 = lp, l2 = lp;
+    if constexpr (PREC == 0) {
+      const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
+#pragma unroll 4
+      for (int kk = 0; kk < KL / 4; ++kk) {
+        const int k = kk * 4 + kq;
+        const int c = swz<E>(k, col);
+        const float al = Lp[kk * 64];
+        lp = mfma_f32(al, s_B[(0 * KMAX + k) * E + c], lp);
+        l0 = mfma_f32(al, s_B[(1 * KMAX + k) * E + c], l0);
+        l1 = mfma_f32(al, s_B[(2 * KMAX + k) * E + c], l1);
+        l2 = mfma_f32(al, s_B[(3 * KMAX + k) * E + c], l2);
       }
-      float qn[NF];
-#pragma unroll
-      for (int c = 0; c < NF; ++c) {
-        qn[c] = s_q[(c * KP + n) * ES + swz<E>(n, el)] + a.c0 * rr[c] + a.c1 * h1[r][c] + a.c2 * h2[r][c];
-        a.q_out[base + c * NP] = qn[c];
-        a.r_out[base + c * NP] = rr[c];
+    } else {
+      const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
+      constexpr int LO = 4 * KMAX * E;
+      const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
+      const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
+#pragma unroll 2
+      for (int kk = 0; kk < KL / 16; ++kk) {
+        const int off = ((kk * 4 + kq) * E + col) * 4;
+        const Frag16 al{Lh[kk * 64], Ll[kk * 64]};
+        Frag16 b;
+        b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
+        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
+        lp = mfma_split<PREC>(al, b, lp);
+        b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
+        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
+        l0 = mfma_split<PREC>(al, b, l0);
+        b.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
+        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
+        l1 = mfma_split<PREC>(al, b, l1);
+        b.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
+        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
+        l2 = mfma_split<PREC>(al, b, l2);
       }
+    }
+    // right-hand sides in the accumulator layout: row 4*kq + r, column nl
+    float rr[4][4];
+    {
+      const int ec = col < ne ? col : 0;
+      const float* G = s_g + 9 * ec;
+      const float rc2 = s_cf[ec * CB + 0], irho = s_cf[ec * CB + 1];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        rr[0][r] = -rc2 * DV[q][r] + lp[r];
+        rr[1][r] = -irho * (G[0] * T0[q][r] + G[1] * T1[q][r] + G[2] * T2[q][r]) + l0[r];
+        rr[2][r] = -irho * (G[3] * T0[q][r] + G[4] * T1[q][r] + G[5] * T2[q][r]) + l1[r];
+        rr[3][r] = -irho * (G[6] * T0[q][r] + G[7] * T1[q][r] + G[8] * T2[q][r]) + l2[r];
+      }
+    }
+    // transpose field by field through the wave's scratch:
+    // lane -> (node mb*16 + nl, element nb*16 + eg + 4 it)
+    const int n = mb * 16 + nl;
+    float rt[4][4];  // [field][it]
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) scr[nl * 17 + 4 * kq + r] = rr[c][r];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int it = 0; it < 4; ++it) rt[c][it] = scr[(eg + 4 * it) * 17 + nl];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    float qn[4][4];
+    if (step) {
+      float qo[4][4], h1[4][4], h2[4][4];
+      const bool use1 = a.c1 != 0.0f, use2 = a.c2 != 0.0f;
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int e = nb * 16 + eg + 4 * it;
+        const bool ok = e < ne && n < NP;
+        const int64_t base = (e0 + e) * NF * NP + n;
+#pragma unroll
+        for (int c = 0; c < NF; ++c) {
+          qo[c][it] = ok ? a.q_in[base + c * NP] : 0.0f;
+          h1[c][it] = (ok && use1) ? a.r1[base + c * NP] : 0.0f;
+          h2[c][it] = (ok && use2) ? a.r2[base + c * NP] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < 4; ++it)
+#pragma unroll
+        for (int c = 0; c < NF; ++c) qn[c][it] = qo[c][it] + a.c0 * rt[c][it] + a.c1 * h1[c][it] + a.c2 * h2[c][it];
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int e = nb * 16 + eg + 4 * it;
+      if (e >= ne || n >= NP) continue;
+      const int64_t base = (e0 + e) * NF * NP + n;
+#pragma unroll
+      for (int c = 0; c < NF; ++c) a.r_out[base + c * NP] = rt[c][it];
+      if (!step) continue;
+#pragma unroll
+      for (int c = 0; c < NF; ++c) a.q_out[base + c * NP] = qn[c][it];
+      const float* fr = s_face + e * 4 * FW;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int fj = a.nodeface[n * 3 + s];
         if (fj < 0) break;
         const int f = fj / NFP, j = fj - f * NFP;
-        float* tr = a.qf_out + ((e0 + el) * 4 + f) * NT * NFP + j;
-        tr[0] = qn[0];
-        tr[NFP] = fr[f * FW + 0] * qn[1] + fr[f * FW + 1] * qn[2] + fr[f * FW + 2] * qn[3];
+        float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP + j;
+        tr[0] = qn[0][it];
+        tr[NFP] = fr[f * FW + 0] * qn[1][it] + fr[f * FW + 1] * qn[2][it] + fr[f * FW + 2] * qn[3][it];
       }
     }
   }
 }
 
-template <int N>
+template <int N, int PREC>
 __global__ void __launch_bounds__(kThreads)
 dg_step_mfma_acoustic(StepArgs a) {
-  step_mfma_tile<N>(a, tile_of_block(a.xcd_remap));
+  step_mfma_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
 }
 
-template <int N>
+template <int N, int PREC>
 __global__ void __launch_bounds__(kThreads)
 dg_step_mfma_acoustic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
   const StepArgs a = args[w.x * kBatchPhases + phase];
-  step_mfma_tile<N>(a, w.y);
+  step_mfma_tile<N, PREC>(a, w.y);
 }
 
-template <int N>
+template <int N, int PREC>
 hipError_t mfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic_batch<N>), dim3(static_cast<unsigned>(ntiles)), dim3(kThreads), 0, s,
-                     args, work, phase);
+  hipLaunchKernelGGL((dg_step_mfma_acoustic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(kThreads), 0,
+                     s, args, work, phase);
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, int PREC>
 hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
-  constexpr int E = MfmaShape<N>::E;
+  constexpr int E = MShape<N, PREC>::E;
   int64_t tiles = (a.K + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic<N>), dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+template <int N, int PREC>
+MfmaPacking packing_of() {
+  using S = MShape<N, PREC>;
+  return MfmaPacking{S::MB, S::KP, S::KL, S::KS, S::E};
 }
 
 }  // namespace
 
-int mfma_tile_elements(int N) {
-  switch (N) {
-    case 1: return MfmaShape<1>::E; case 2: return MfmaShape<2>::E; case 3: return MfmaShape<3>::E;
-    case 4: return MfmaShape<4>::E; case 5: return MfmaShape<5>::E; case 6: return MfmaShape<6>::E;
-    case 7: return MfmaShape<7>::E; case 8: return MfmaShape<8>::E;
-  }
-  return -1;
+int mfma_precision(int variant) {
+  return variant == kVariantMfma ? 0 : (variant == kVariantMfmaBf16 ? 1 : (variant == kVariantMfmaF16 ? 2 : -1));
 }
 
-hipError_t launch_step_batch_mfma(int physics, int N, const StepArgs* args, const int2* work, int64_t ntiles,
-                                  int phase, hipStream_t s) {
-  if (physics != 0) return hipErrorInvalidValue;
-  switch (N) {
-    case 1: return mfma_batch_impl<1>(args, work, ntiles, phase, s);
-    case 2: return mfma_batch_impl<2>(args, work, ntiles, phase, s);
-    case 3: return mfma_batch_impl<3>(args, work, ntiles, phase, s);
-    case 4: return mfma_batch_impl<4>(args, work, ntiles, phase, s);
-    case 5: return mfma_batch_impl<5>(args, work, ntiles, phase, s);
-    case 6: return mfma_batch_impl<6>(args, work, ntiles, phase, s);
-    case 7: return mfma_batch_impl<7>(args, work, ntiles, phase, s);
-    case 8: return mfma_batch_impl<8>(args, work, ntiles, phase, s);
+#define DGW_MFMA_DISPATCH(CALL)                                                          \
+  switch (mfma_precision(variant)) {                                                     \
+    case 0:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 0); case 2: return CALL(2, 0); case 3: return CALL(3, 0); \
+        case 4: return CALL(4, 0); case 5: return CALL(5, 0); case 6: return CALL(6, 0); \
+        case 7: return CALL(7, 0); case 8: return CALL(8, 0);                            \
+      }                                                                                  \
+      break;                                                                             \
+    case 1:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 1); case 2: return CALL(2, 1); case 3: return CALL(3, 1); \
+        case 4: return CALL(4, 1); case 5: return CALL(5, 1); case 6: return CALL(6, 1); \
+        case 7: return CALL(7, 1); case 8: return CALL(8, 1);                            \
+      }                                                                                  \
+      break;                                                                             \
+    case 2:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 2); case 2: return CALL(2, 2); case 3: return CALL(3, 2); \
+        case 4: return CALL(4, 2); case 5: return CALL(5, 2); case 6: return CALL(6, 2); \
+        case 7: return CALL(7, 2); case 8: return CALL(8, 2);                            \
+      }                                                                                  \
+      break;                                                                             \
   }
+
+MfmaPacking mfma_packing(int N, int variant) {
+#define CALL(n, p) packing_of<n, p>()
+  DGW_MFMA_DISPATCH(CALL)
+#undef CALL
+  return MfmaPacking{};
+}
+
+hipError_t launch_step_mfma(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
+  if (physics != 0) return hipErrorInvalidValue;
+#define CALL(n, p) mfma_impl<n, p>(a, s)
+  DGW_MFMA_DISPATCH(CALL)
+#undef CALL
   return hipErrorInvalidValue;
 }
 
-int mfma_mblocks(int N) { return (((N + 1) * (N + 2) * (N + 3) / 6) + 15) / 16; }
-int mfma_kpad(int N) { return (((N + 1) * (N + 2) * (N + 3) / 6) + 3) / 4 * 4; }
-int mfma_face_pad(int N) { return (((N + 1) * (N + 2) / 2) + 3) / 4 * 4; }
-
-hipError_t launch_step_mfma(int physics, int N, const StepArgs& a, hipStream_t s) {
+hipError_t launch_step_batch_mfma(int physics, int N, int variant, const StepArgs* args, const int2* work,
+                                  int64_t ntiles, int phase, hipStream_t s) {
   if (physics != 0) return hipErrorInvalidValue;
-  switch (N) {
-    case 1: return mfma_impl<1>(a, s);
-    case 2: return mfma_impl<2>(a, s);
-    case 3: return mfma_impl<3>(a, s);
-    case 4: return mfma_impl<4>(a, s);
-    case 5: return mfma_impl<5>(a, s);
-    case 6: return mfma_impl<6>(a, s);
-    case 7: return mfma_impl<7>(a, s);
-    case 8: return mfma_impl<8>(a, s);
-  }
+#define CALL(n, p) mfma_batch_impl<n, p>(args, work, ntiles, phase, s)
+  DGW_MFMA_DISPATCH(CALL)
+#undef CALL
   return hipErrorInvalidValue;
 }
+
+#undef DGW_MFMA_DISPATCH
 
 }  // namespace dgw

@@ -1,0 +1,24 @@
+// Host packing of operators into MFMA fragment order (see mfma_pack.cpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace dgw {
+
+uint16_t bf16_round(float x);
+float bf16_float(uint16_t h);
+uint16_t f16_round(float x);
+float f16_float(uint16_t h);
+
+// A (rows x cols, row-major) as 16x4 FP32 fragments, lane l holding
+// A[mb*16 + l%16][4 kk + l/16]; appended to out as [MB][KP/4][64].
+void pack_fp32(const double* A, int rows, int cols, int MB, int KP, std::vector<float>& out);
+
+// A as 16x16 fragments of 16-bit pairs x = hi + lo, lane l holding
+// A[mb*16 + l%16][16 kk + 4 (l/16) + t], t = 0..3; appended as
+// [MB][K16/16][64][4] to hi and lo.
+void pack_split16(const double* A, int rows, int cols, int MB, int K16, bool bf16, std::vector<uint16_t>& hi,
+                  std::vector<uint16_t>& lo);
+
+}  // namespace dgw

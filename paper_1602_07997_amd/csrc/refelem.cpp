@@ -392,6 +392,8 @@ std::unique_ptr<RefElement> build(int N) {
   Mat M = matmul(transpose(Vinv, Np, Np), Vinv, Np, Np, Np);
   Mat Minv = matmul(V, transpose(V, Np, Np), Np, Np, Np);
   ref->mass.assign(M.begin(), M.end());
+  ref->minv.assign(Minv.begin(), Minv.end());
+  ref->vinv.assign(Vinv.begin(), Vinv.end());
 
   // face masks from the lattice
   std::map<std::array<int, 4>, int> index;
@@ -418,6 +420,7 @@ std::unique_ptr<RefElement> build(int N) {
   }
   Mat V2inv = inverse(V2, Nfp);
   Mat Ef = matmul(transpose(V2inv, Nfp, Nfp), V2inv, Nfp, Nfp, Nfp);
+  ref->face_mass.assign(Ef.begin(), Ef.end());
   Mat Emb(static_cast<size_t>(Np) * 4 * Nfp, 0);
   for (int f = 0; f < 4; ++f)
     for (int i = 0; i < Nfp; ++i)
@@ -462,6 +465,18 @@ std::mutex g_cache_mutex;
 std::unique_ptr<RefElement> g_cache[kMaxOrder + 1];
 
 }  // namespace
+
+void lagrange_weights(const RefElement* ref, const double xi[3], double* w) {
+  // u(xi) = psi(xi)^T V^{-1} u_nodes, so l(xi) = V^{-T} psi(xi)
+  std::vector<real> psi;
+  tet_basis<real>(ref->N, xi[0], xi[1], xi[2], psi);
+  const int Np = ref->Np;
+  for (int n = 0; n < Np; ++n) {
+    real acc = 0;
+    for (int m = 0; m < Np; ++m) acc += psi[m] * static_cast<real>(ref->vinv[m * Np + n]);
+    w[n] = static_cast<double>(acc);
+  }
+}
 
 const RefElement* reference_element(int N) {
   if (N < 1 || N > kMaxOrder) return nullptr;

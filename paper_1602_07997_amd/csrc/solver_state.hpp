@@ -53,6 +53,8 @@ struct dg_solver {
   int variant = 0;
   float* Dpack = nullptr;
   float* Lpack = nullptr;
+  uint16_t* D16[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [bf16, f16][hi, lo]
+  uint16_t* L16[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   std::vector<double> elem_xyz;  // host copy for node coordinates
 };
 

@@ -171,7 +171,12 @@ class DGSolver:
         )
         return q, (r1 if m.value >= 1 else None), (r2 if m.value >= 2 else None), m.value
 
-    VARIANTS = {"valu": nat.DG_VARIANT_VALU, "mfma": nat.DG_VARIANT_MFMA}
+    VARIANTS = {
+        "valu": nat.DG_VARIANT_VALU,
+        "mfma": nat.DG_VARIANT_MFMA,
+        "mfma_bf16": nat.DG_VARIANT_MFMA_BF16,
+        "mfma_f16": nat.DG_VARIANT_MFMA_F16,
+    }
 
     @property
     def variant(self) -> str:
@@ -234,6 +239,14 @@ class DGSolver:
 
     def synchronize(self):
         check(lib.dg_synchronize(self._h), "dg_synchronize")
+
+    def locate_points(self, xyz):
+        """(element [n], Lagrange weights [n, Np]) of host points [n, 3]."""
+        x = np.ascontiguousarray(np.atleast_2d(xyz), dtype=np.float64)
+        elem = np.zeros(len(x), dtype=np.int64)
+        w = np.zeros((len(x), self.Np))
+        check(lib.dg_locate_points(self._h, len(x), _dptr(x), _i64ptr(elem), _dptr(w)), "dg_locate_points")
+        return elem, w
 
 
 class DGBatch:
