@@ -40,9 +40,11 @@ if ROOT not in sys.path:
 
 import dginputs as di  # noqa: E402
 
+FP32_VARIANTS = ("valu", "mfma")  # candidates of the FP32 autotuned path
 METRIC = "DG node-updates/s and % roofline, acoustic+elastic N=1..8: FP32 vs mixed/batched"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 FP32_PEAK = 157.3e12  # flop/s, MI355X FP32 vector / matrix
+MFMA16_PEAK = 2.5e15  # flop/s, MI355X dense BF16 / FP16 matrix
 
 
 def algorithmic_model(physics: str, N: int):
@@ -67,19 +69,52 @@ def algorithmic_model(physics: str, N: int):
     return nbytes, flops
 
 
-def measured_traffic(physics: str, N: int):
+def kernel_source(variant: str) -> str:
+    name = "kernels.hip" if variant == "valu" else "kernels_mfma.hip"
+    return os.path.join(ROOT, "paper_1602_07997_amd", "csrc", name)
+
+
+def kernel_name(physics: str, N: int, variant: str) -> str:
+    if variant == "valu":
+        return f"dg_step_kernel<N={N},{physics}>"
+    prec = {"mfma": 0, "mfma_bf16": 1, "mfma_f16": 2}[variant]
+    return f"dg_step_mfma_acoustic<N={N},PREC={prec}>"
+
+
+def contraction_flops(physics: str, N: int) -> int:
+    """Flops per element of the D_j and LIFT products (the part the MFMA
+    variants run on matrix cores): acoustic 12 Np^2 + 32 Np Nfp (four
+    products with D_j, four with the merged LIFT)."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Nfp = (N + 1) * (N + 2) // 2
+    return 12 * Np * Np + 32 * Np * Nfp if physics == "acoustic" else 36 * Np * Np + 72 * Np * Nfp
+
+
+def compute_floor(physics: str, N: int, variant: str) -> float:
+    """Seconds per element at the compute peak: FP32 for the FP32 variants;
+    for the split 16-bit variants the contractions cost three 16-bit
+    products at the dense BF16/FP16 matrix peak and the rest FP32."""
+    _, flops = algorithmic_model(physics, N)
+    if variant in ("mfma_bf16", "mfma_f16"):
+        cf = contraction_flops(physics, N)
+        return 3 * cf / MFMA16_PEAK + (flops - cf) / FP32_PEAK
+    return flops / FP32_PEAK
+
+
+def measured_traffic(physics: str, N: int, variant: str):
     """HBM bytes per launch of the step kernel from the committed counter
     summary (profiles/dg_step_<physics>_sweep_traffic.md), or None when the
     kernel source has changed since the counters were taken."""
     import hashlib
     import re
 
-    src = os.path.join(ROOT, "paper_1602_07997_amd", "csrc", "kernels.hip")
     path = os.path.join(ROOT, "profiles", f"dg_step_{physics}_sweep_traffic.md")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-    pat = re.compile(rf"^traffic {physics} N={N} bytes_per_launch=(\d+) kernel_sha1=([0-9a-f]+)$")
+    sha = hashlib.sha1(open(kernel_source(variant), "rb").read()).hexdigest()[:12]
+    pat = re.compile(
+        rf"^traffic {physics} N={N} variant={variant} bytes_per_launch=(\d+) kernel_sha1=([0-9a-f]+)$"
+    )
     for line in open(path):
         m = pat.match(line.strip())
         if m and m.group(2) == sha:
@@ -115,13 +150,19 @@ def run_gpu(physics, degrees, steps, warmup, log, variant="valu"):
     for N in degrees:
         n, mesh, coef = workload(physics, N)
         s = DGSolver(physics, N, mesh.elem_xyz, mesh.elem_topo, stream=stream)
-        s.variant = pick_variant(physics, N, variant)
         s.set_coefficients(torch.tensor(coef, dtype=torch.float32, device="cuda"))
         s.set_fields(torch.tensor(init_fields(physics, s.node_coordinates()), device="cuda"))
         dt = di.time_step(mesh, N, di.max_wave_speed(coef, physics))
         s.step(2, dt)  # Euler and two-step start-up
-        cases.append({"N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt, "variant": s.variant})
-        log(f"  set up {physics} N={N}: n={n} K={mesh.K} nodes={mesh.K * s.Np}")
+        tuned = None
+        if variant in ("auto", "auto-mixed"):
+            tuned = s.autotune(3, dt, FP32_VARIANTS if variant == "auto" else None)
+        else:
+            s.variant = variant
+        cases.append({"N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt, "variant": s.variant,
+                      "autotune_us": tuned})
+        log(f"  set up {physics} N={N}: n={n} K={mesh.K} nodes={mesh.K * s.Np} variant={s.variant}"
+            + (f" (autotune us/step {tuned})" if tuned else ""))
     for c in cases:
         c["solver"].step(warmup, c["dt"])
     torch.cuda.synchronize()
@@ -148,14 +189,6 @@ def run_gpu(physics, degrees, steps, warmup, log, variant="valu"):
         c["solver"].close()
         del c["solver"]
     return cases, wall
-
-
-def pick_variant(physics: str, N: int, requested: str) -> str:
-    """Kernel variant for one degree: 'valu', 'mfma', or 'auto' (MFMA where it
-    is built and N >= 3, the node-per-thread kernel otherwise)."""
-    if requested != "auto":
-        return requested
-    return "mfma" if (physics == "acoustic" and N >= 3) else "valu"
 
 
 def run_cpu_baseline(physics, degrees, steps, log):
@@ -198,7 +231,7 @@ def run_cpu_baseline(physics, degrees, steps, log):
     }
 
 
-def run_batched(steps, warmup, log, count=64, seed=2):
+def run_batched(steps, warmup, log, count=64, seed=2, candidates=FP32_VARIANTS):
     import torch
 
     from paper_1602_07997_amd import DGBatch, DGSolver
@@ -246,7 +279,7 @@ def run_batched(steps, warmup, log, count=64, seed=2):
     t0 = time.perf_counter()
     choice = {}
     for m in members:
-        m["solver"].autotune(3, m["dt"])
+        m["solver"].autotune(3, m["dt"], candidates)
         choice.setdefault((m["N"], m["solver"].variant), 0)
         choice[(m["N"], m["solver"].variant)] += 1
     log(f"  autotune {time.perf_counter() - t0:.1f} s: {sorted(choice.items())}")
@@ -270,8 +303,17 @@ def run_batched(steps, warmup, log, count=64, seed=2):
     }
 
 
+def dtype_of(variants) -> str:
+    mixed = [v for v in variants if v in ("mfma_bf16", "mfma_f16")]
+    if not mixed:
+        return "f32"
+    halves = "/".join(sorted({"bf16" if v == "mfma_bf16" else "f16" for v in mixed}))
+    return f"f32 fields, {halves} hi+lo split products with f32 accumulation in the contractions"
+
+
 def main_batched(args, log):
-    r = run_batched(args.steps, args.warmup, log)
+    cands = None if args.variant == "auto-mixed" else FP32_VARIANTS
+    r = run_batched(args.steps, args.warmup, log, candidates=cands)
     step_s = r["t_batch"] / r["steps"]
     plain_s = r["t_plain"] / r["plain_steps"]
     achieved = r["alg_bytes_per_step"] / step_s
@@ -286,7 +328,7 @@ def main_batched(args, log):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_of([k.split(":")[1] for k in r["choice"]]),
         "data": "synthetic",
         "config": {
             "workload": "64 independent acoustic meshes, K log-uniform in [2e3, 2e5] (Kuhn boxes), N uniform in "
@@ -317,7 +359,11 @@ def main(argv=None):
     ap.add_argument("--config", choices=["acoustic", "elastic", "batched"], default="acoustic")
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
-    ap.add_argument("--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "auto"], default="auto")
+    ap.add_argument(
+        "--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "auto", "auto-mixed"], default="auto",
+        help="kernel variant for every degree; 'auto' lets the autotuner pick among the FP32 variants per "
+        "degree, 'auto-mixed' also among the BF16/FP16 split-product variants",
+    )
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument(
@@ -371,8 +417,8 @@ def main(argv=None):
         bw = nbytes * c["K"] / t
         fl = flops * c["K"] / t
         t_hbm = nbytes * c["K"] / HBM_PEAK
-        t_alu = flops * c["K"] / FP32_PEAK
-        bound = "hbm" if t_hbm >= t_alu else "alu"
+        t_alu = compute_floor(physics, c["N"], c["variant"]) * c["K"]
+        bound = "hbm" if t_hbm >= t_alu else ("mfma" if c["variant"].startswith("mfma") else "alu")
         frac = (t_hbm if bound == "hbm" else t_alu) / t
         per.append(
             {
@@ -382,7 +428,8 @@ def main(argv=None):
                 "alg_bytes_per_elem": nbytes, "alg_flops_per_elem": flops,
                 "achieved_GBps": bw / 1e9, "achieved_TFLOPs": fl / 1e12,
                 "bound": bound, "frac": frac,
-                "traffic_bytes": measured_traffic(physics, c["N"]),
+                "traffic_bytes": measured_traffic(physics, c["N"], c["variant"]),
+                "autotune_us": c["autotune_us"],
             }
         )
         log(
@@ -397,11 +444,17 @@ def main(argv=None):
     t = dom["kernel_us"] * 1e-6
     if dom["bound"] == "hbm":
         roof = {"bound": "hbm", "achieved": nb / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
     else:
-        roof = {"bound": "alu", "achieved": nf / t / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(physics, dom["N"])
-    roof["kernel"] = f"{'dg_step_mfma_acoustic' if dom['variant'] == 'mfma' else 'dg_step_kernel'}<N={dom['N']},{physics}>"
+        # compute-bound: algorithmic flops against the variant's own floor
+        # (FP32 peak; for the split 16-bit variants the contractions are
+        # priced as three products at the 16-bit matrix peak)
+        peak = dom["alg_flops_per_elem"] / compute_floor(physics, dom["N"], dom["variant"])
+        roof = {"bound": "mfma" if dom["variant"].startswith("mfma") else "alu",
+                "achieved": nf / t / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(physics, dom["N"], dom["variant"])
+    roof["kernel"] = kernel_name(physics, dom["N"], dom["variant"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -419,7 +472,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_of(sorted({c["variant"] for c in cases})),
         "data": "synthetic",
         "config": {
             "workload": f"{physics} sweep N={degrees[0]}..{degrees[-1]}, one ~2M-node jittered Kuhn cube per degree, "

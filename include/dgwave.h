@@ -216,19 +216,21 @@ dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* byt
 /* Kernel choice and batches of meshes.                                     */
 /* ------------------------------------------------------------------------ */
 
-/* Time every kernel variant built for the solver's physics and degree on the
+/* Time the kernel variants built for the solver's physics and degree on the
  * solver's own mesh: `steps` steps of size dt each, after one untimed step,
- * timed with HIP events on the solver's stream.  The state (fields, AB3
+ * timed with HIP events on the solver's stream.  `candidates` is a bit mask
+ * of the variants to consider (bit v for variant v; 0 = all of them).  The state (fields, AB3
  * history, traces, step index) is saved to temporary device memory before
  * and restored after, so the call does not advance the solution; it
  * synchronises.  The fastest variant becomes the solver's variant.
  * us_per_step (host float64 [DG_NUM_VARIANTS], may be NULL) receives the
- * microseconds per step of each variant, -1 where not built.  The choice of
+ * microseconds per step of each variant, -1 where not built or not a
+ * candidate.  The choice of
  * kernel per degree and mesh follows the observation of Sec. 4 that the best
  * implementation strategy depends on the degree.  Errors: DG_E_STATE (no
  * coefficients or fields), DG_E_ARG, DG_E_HIP.                              */
 #define DG_NUM_VARIANTS 4
-dg_status dg_autotune(dg_solver* s, int steps, double dt, double* us_per_step);
+dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, double* us_per_step);
 
 typedef struct dg_batch dg_batch;
 

@@ -86,7 +86,7 @@ SIGNATURES = {
     "dg_rhs": (C.c_int, [_p, _p, _p]),
     "dg_energy": (C.c_int, [_p, _dp]),
     "dg_debug_buffer": (C.c_int, [_p, C.c_char_p, _p, C.POINTER(C.c_size_t)]),
-    "dg_autotune": (C.c_int, [_p, C.c_int, C.c_double, _dp]),
+    "dg_autotune": (C.c_int, [_p, C.c_int, C.c_double, C.c_uint, _dp]),
     "dg_batch_create": (C.c_int, [C.POINTER(_p), C.c_int, _p, C.POINTER(_p)]),
     "dg_batch_destroy": (None, [_p]),
     "dg_batch_set_graph": (C.c_int, [_p, C.c_int]),

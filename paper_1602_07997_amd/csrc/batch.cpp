@@ -200,7 +200,7 @@ void advance_members(dg_batch* b, int steps) {
 
 extern "C" {
 
-dg_status dg_autotune(dg_solver* s, int steps, double dt, double* us_per_step) {
+dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, double* us_per_step) {
   if (!s) {
     set_error("null solver");
     return DG_E_ARG;
@@ -234,7 +234,8 @@ dg_status dg_autotune(dg_solver* s, int steps, double dt, double* us_per_step) {
   dg_status st = DG_OK;
   for (int v = 0; v < DG_NUM_VARIANTS && st == DG_OK; ++v) {
     double us = -1.0;
-    if (dgw::variant_supported(s->physics, s->N, v)) {
+    const bool wanted = candidates == 0u || ((candidates >> v) & 1u);
+    if (wanted && dgw::variant_supported(s->physics, s->N, v)) {
       s->variant = v;
       hipError_t err = hipSuccess;
       for (int i = 0; i <= steps && err == hipSuccess; ++i) {

@@ -197,14 +197,20 @@ class DGSolver:
     def step(self, nsteps: int, dt: float):
         check(lib.dg_step(self._h, int(nsteps), float(dt)), "dg_step")
 
-    def autotune(self, steps: int, dt: float) -> dict:
-        """Times every built variant on this mesh and keeps the fastest.
+    def autotune(self, steps: int, dt: float, candidates=None) -> dict:
+        """Times the built variants (all, or the names in ``candidates``) on
+        this mesh and keeps the fastest.
 
-        Returns microseconds per step by variant name (None where not built).
-        The solver's state is restored, so the solution does not advance.
+        Returns microseconds per step by variant name (None where not built
+        or not a candidate).  The solver's state is restored, so the solution
+        does not advance.
         """
+        mask = 0
+        if candidates is not None:
+            for name in candidates:
+                mask |= 1 << self.VARIANTS[name]
         us = np.zeros(nat.DG_NUM_VARIANTS)
-        check(lib.dg_autotune(self._h, int(steps), float(dt), _dptr(us)), "dg_autotune")
+        check(lib.dg_autotune(self._h, int(steps), float(dt), mask, _dptr(us)), "dg_autotune")
         names = {b: a for a, b in self.VARIANTS.items()}
         return {names[v]: (float(us[v]) if us[v] >= 0 else None) for v in range(nat.DG_NUM_VARIANTS)}
 

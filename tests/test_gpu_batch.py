@@ -227,3 +227,14 @@ def test_batch_recipe_shapes():
     log(f"  smallest member N={c.N} K={c.mesh.K}: {err:.2e}")
     assert err <= 1e-5
     batch.close()
+
+
+def test_autotune_candidate_mask():
+    c = Case("acoustic", 4, 2, jitter=0.1, seed=8, coef_kind="random", init="gaussian")
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    times = c.solver.autotune(2, c.dt, ["valu"])
+    assert times["valu"] is not None and all(times[v] is None for v in ("mfma", "mfma_bf16", "mfma_f16"))
+    assert c.solver.variant == "valu"
+    times = c.solver.autotune(2, c.dt, ["mfma", "mfma_bf16"])
+    assert times["valu"] is None and times["mfma_f16"] is None
+    assert c.solver.variant in ("mfma", "mfma_bf16")
