@@ -69,8 +69,11 @@ def algorithmic_model(physics: str, N: int):
     return nbytes, flops
 
 
-def kernel_source(variant: str) -> str:
-    name = "kernels.hip" if variant == "valu" else "kernels_mfma.hip"
+def kernel_source(variant: str, physics: str = "acoustic") -> str:
+    if variant == "valu":
+        name = "kernels.hip"
+    else:
+        name = "kernels_mfma.hip" if physics == "acoustic" else "kernels_mfma_elastic.hip"
     return os.path.join(ROOT, "paper_1602_07997_amd", "csrc", name)
 
 
@@ -78,7 +81,7 @@ def kernel_name(physics: str, N: int, variant: str) -> str:
     if variant == "valu":
         return f"dg_step_kernel<N={N},{physics}>"
     prec = {"mfma": 0, "mfma_bf16": 1, "mfma_f16": 2}[variant]
-    return f"dg_step_mfma_acoustic<N={N},PREC={prec}>"
+    return f"dg_step_mfma_{physics}<N={N},PREC={prec}>"
 
 
 def contraction_flops(physics: str, N: int) -> int:
@@ -111,7 +114,7 @@ def measured_traffic(physics: str, N: int, variant: str):
     path = os.path.join(ROOT, "profiles", f"dg_step_{physics}_sweep_traffic.md")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha1(open(kernel_source(variant), "rb").read()).hexdigest()[:12]
+    sha = hashlib.sha1(open(kernel_source(variant, physics), "rb").read()).hexdigest()[:12]
     pat = re.compile(
         rf"^traffic {physics} N={N} variant={variant} bytes_per_launch=(\d+) kernel_sha1=([0-9a-f]+)$"
     )

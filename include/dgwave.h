@@ -140,12 +140,13 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
 /* Kernel variant of the step (default DG_VARIANT_VALU).  All compute the
  * right-hand side of eqs. (5)-(6) / the elastic system and the update of
  * eq. (4); they differ in how the D_j and LIFT products run:
- *   DG_VARIANT_VALU       node per thread, vector ALU (all physics, degrees);
- *   DG_VARIANT_MFMA       element tiles on FP32 matrix cores (acoustic);
+ *   DG_VARIANT_VALU       node per thread, vector ALU;
+ *   DG_VARIANT_MFMA       element tiles on FP32 matrix cores;
  *   DG_VARIANT_MFMA_BF16  BF16 matrix cores with FP32 accumulation, both
  *                         operands split x = x_hi + x_lo and the products
- *                         D_hi x_hi + D_hi x_lo + D_lo x_hi (acoustic);
- *   DG_VARIANT_MFMA_F16   the same with FP16 halves (acoustic).
+ *                         D_hi x_hi + D_hi x_lo + D_lo x_hi;
+ *   DG_VARIANT_MFMA_F16   the same with FP16 halves.
+ * Every variant is built for both physics and N = 1..8.
  * Fields, r and the update stay FP32 in every variant.  Returns
  * DG_E_UNSUPPORTED for a combination that is not built.                    */
 #define DG_VARIANT_VALU 0

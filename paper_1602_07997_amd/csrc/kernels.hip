@@ -614,12 +614,13 @@ static bool is_mfma(int variant) { return mfma_precision(variant) >= 0; }
 bool variant_supported(int physics, int N, int variant) {
   if (N < 1 || N > 8 || (physics != 0 && physics != 1)) return false;
   if (variant == kVariantValu) return true;
-  if (is_mfma(variant)) return physics == 0;
+  if (is_mfma(variant)) return true;
   return false;
 }
 
 hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
-  if (is_mfma(variant)) return launch_step_mfma(physics, N, variant, a, s);
+  if (is_mfma(variant))
+    return physics == 1 ? launch_step_mfma_elastic(N, variant, a, s) : launch_step_mfma(physics, N, variant, a, s);
   if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_impl<n, p>(a, s)
   if (physics == 0) {
@@ -656,7 +657,7 @@ int64_t tiles_for(int physics, int N, int variant, int64_t K) {
 
 int tile_elements(int physics, int N, int variant) {
   if (!variant_supported(physics, N, variant)) return -1;
-  if (is_mfma(variant)) return mfma_packing(N, variant).E;
+  if (is_mfma(variant)) return physics == 1 ? mfma_elastic_tile_elements(N, variant) : mfma_packing(N, variant).E;
 #define TE(n, p) Tile<n, p>::KT
   if (physics == 0) {
     switch (N) {
@@ -676,7 +677,9 @@ int tile_elements(int physics, int N, int variant) {
 
 hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* args, const int2* work,
                              int64_t ntiles, int phase, hipStream_t s) {
-  if (is_mfma(variant)) return launch_step_batch_mfma(physics, N, variant, args, work, ntiles, phase, s);
+  if (is_mfma(variant))
+    return physics == 1 ? launch_step_batch_mfma_elastic(N, variant, args, work, ntiles, phase, s)
+                        : launch_step_batch_mfma(physics, N, variant, args, work, ntiles, phase, s);
   if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_batch_impl<n, p>(args, work, ntiles, phase, s)
   if (physics == 0) {

@@ -60,6 +60,11 @@ struct MfmaPacking {
 int mfma_precision(int variant);  // 0 FP32, 1 BF16, 2 FP16, -1 not an MFMA variant
 MfmaPacking mfma_packing(int N, int variant);
 hipError_t launch_step_mfma(int physics, int N, int variant, const StepArgs& a, hipStream_t s);
+// Elastic MFMA kernels (512-thread workgroups).
+int mfma_elastic_tile_elements(int N, int variant);
+hipError_t launch_step_mfma_elastic(int N, int variant, const StepArgs& a, hipStream_t s);
+hipError_t launch_step_batch_mfma_elastic(int N, int variant, const StepArgs* args, const int2* work, int64_t ntiles,
+                                          int phase, hipStream_t s);
 hipError_t launch_step_batch_mfma(int physics, int N, int variant, const StepArgs* args, const int2* work,
                                   int64_t ntiles, int phase, hipStream_t s);
 

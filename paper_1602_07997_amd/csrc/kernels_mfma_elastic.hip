@@ -1,0 +1,501 @@
+// MFMA variants of the fused DG step, isotropic elastic system (Sec. 2.1 and
+// the elastic right-hand side of Sec. 3.2), gfx950 matrix cores.
+//
+// With the element as the GEMM column, for a tile of E = 16 NBLK elements:
+//   Dv_il = D_l v_i                 (9 products, K = Np)
+//   dS_i  = sum_l D_l S_il,  S_il = sum_a g_al s_ia   (K = Np, S formed per k-step)
+//   Lv_i, Ls_v = L B_c              (9 products over the merged 4 Nfp face nodes)
+// where the LIFT operands B are the upwind penalties of Sec. 2.1 already
+// combined with the element's coefficients and the face normal:
+//   Bv_i = n_i (c_p A1 - c_s A2) + k_s c_s A3_i
+//   Bs_ij = 2 mu (A1 - A2) n_i n_j + mu k_s (n_i A3_j + A3_i n_j) + delta_ij lambda A1
+//   A1 = Fs k_p (s_nn + Zp+ v_n), A2 = Fs k_s (s_nn + Zs+ v_n), A3 = Fs (s n + Zs+ v)
+// (jumps halved).  The right-hand side is then
+//   r_v_i = (1/rho) dS_i + Lv_i,
+//   r_s_ij = mu (dv_i/dx_j + dv_j/dx_i) + delta_ij lambda div v + Ls_ij,
+//   dv_i/dx_j = sum_l g_jl Dv_il.
+// Precisions as in the acoustic kernel: FP32 16x16x4, or BF16 / FP16
+// 16x16x16 with both operands split hi + lo and three products accumulated in
+// FP32.  Workgroups of 8 wavefronts; phases:
+//   A1  constants and face records into LDS;
+//   A2  LIFT operands of every face node into LDS (neighbour traces gathered
+//       here);
+//   C2  LIFT products, kept in registers;
+//   B1  the tile's nine fields into the same LDS region;
+//   C1  volume products and the epilogue (transpose through a per-wave LDS
+//       scratch, AB3 update, q / r writes, own traces), pair by pair.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dg_device.hpp"
+#include "kernels.hpp"
+#include "mfma_common.hpp"
+
+namespace dgw {
+
+namespace {
+
+using namespace dev;
+using namespace mfma;
+
+constexpr int kEThreads = 512;  // eight wavefronts
+
+template <int N, int PREC>
+struct EShape {
+  static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
+  static constexpr int KS = PREC == 0 ? 4 : 16;
+  static constexpr int MB = (NP + 15) / 16;
+  static constexpr int KP = rup(NP, KS);
+  static constexpr int KL = rup(4 * NFP, KS);
+  static constexpr int KMAX = KP > KL ? KP : KL;
+  static constexpr int NBLK = (N == 1) ? 4 : (N <= 3 ? 2 : 1);
+  static constexpr int E = 16 * NBLK;
+  static constexpr int PAIRS = MB * NBLK;
+  static constexpr int NSET = 9;
+  static constexpr int REGION = NSET * KMAX * E;  // 4-byte words
+};
+
+// Operand region, set s, row k, column e.
+//   FP32 sets (PREC 0, and the volume sets of every precision):
+//     PREC 0:  word (s*KMAX + k)*E + swz(k, e)
+//     else:    word s*KMAX*E + ((k/4)*E + e)*4 + k%4   (4 consecutive k contiguous)
+//   16-bit split sets (LIFT operands of PREC 1, 2): hi at unit
+//     s*KMAX*E + ((k/4)*E + e)*4 + k%4, lo NSET*KMAX*E units later.
+template <int N, int PREC>
+struct ERegion {
+  using S = EShape<N, PREC>;
+  float* w;
+  __device__ __forceinline__ int f32_word(int s, int k, int e) const {
+    if constexpr (PREC == 0)
+      return (s * S::KMAX + k) * S::E + swz<S::E>(k, e);
+    else
+      return s * S::KMAX * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+  }
+  __device__ __forceinline__ void put_f32(int s, int k, int e, float x) const { w[f32_word(s, k, e)] = x; }
+  __device__ __forceinline__ void put_split(int s, int k, int e, float x) const {
+    if constexpr (PREC == 0) {
+      put_f32(s, k, e, x);
+    } else {
+      uint16_t* u = reinterpret_cast<uint16_t*>(w);
+      uint16_t hi, lo;
+      split16<PREC>(x, hi, lo);
+      const int idx = s * S::KMAX * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+      u[idx] = hi;
+      u[S::NSET * S::KMAX * S::E + idx] = lo;
+    }
+  }
+};
+
+template <int PREC>
+__device__ __forceinline__ Frag16 split4(const float4& x) {
+  uint16_t h0, l0, h1, l1, h2, l2, h3, l3;
+  split16<PREC>(x.x, h0, l0);
+  split16<PREC>(x.y, h1, l1);
+  split16<PREC>(x.z, h2, l2);
+  split16<PREC>(x.w, h3, l3);
+  Frag16 f;
+  f.hi = shortx4{static_cast<short>(h0), static_cast<short>(h1), static_cast<short>(h2), static_cast<short>(h3)};
+  f.lo = shortx4{static_cast<short>(l0), static_cast<short>(l1), static_cast<short>(l2), static_cast<short>(l3)};
+  return f;
+}
+
+template <int N, int PREC>
+__device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_t tile) {
+  using S = EShape<N, PREC>;
+  constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KMAX = S::KMAX, E = S::E;
+  constexpr int NF = 9, NT = 6, CB = 16;
+  constexpr int FW = FaceRec<1>::W;
+  constexpr int NW = kEThreads / 64;
+  constexpr int NIT = (E * KP + kEThreads - 1) / kEThreads;
+  constexpr int FIT = (E * KL + kEThreads - 1) / kEThreads;
+  constexpr int SCR = 16 * 17;
+  constexpr int PPW = (S::PAIRS + NW - 1) / NW;
+
+  __shared__ float s_B[S::REGION];
+  __shared__ float s_g[E * 9];
+  __shared__ float s_cf[E * CB];
+  __shared__ float s_face[E * 4 * FW];
+  __shared__ float s_scr[NW * SCR];
+
+  const int64_t e0 = tile * E;
+  if (e0 >= a.K) return;  // whole workgroup exits together
+  const int ne = static_cast<int>((a.K - e0) < E ? (a.K - e0) : E);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, nl = lane & 15;
+  const bool step = (a.mode == kStepMode);
+  const ERegion<N, PREC> reg{s_B};
+
+  // ---- A1 -------------------------------------------------------------------
+  for (int i = tid; i < ne * 9; i += kEThreads) s_g[i] = a.geo[e0 * 9 + i];
+  for (int i = tid; i < ne * CB; i += kEThreads) s_cf[i] = a.cf[e0 * CB + i];
+  for (int i = tid; i < ne * 4; i += kEThreads) {
+    const int e = i >> 2, f = i & 3;
+    face_record<1>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
+  }
+  __syncthreads();
+
+  // ---- A2: LIFT operands at every face slot ---------------------------------
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kEThreads;
+    if (i >= E * KL) continue;
+    const int e = i / KL, slot = i - e * KL;
+    float b[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) b[c] = 0.0f;
+    if (e < ne && slot < 4 * NFP) {
+      const int f = slot / NFP, j = slot - f * NFP;
+      const float* rec = s_face + (e * 4 + f) * FW;
+      const float n0 = rec[0], n1 = rec[1], n2 = rec[2];
+      const float nn[3] = {n0, n1, n2};
+      const int vn = a.fmask[f * NFP + j];
+      const float* qe = a.q_in + (e0 + e) * NF * NP;
+      float vM[3], tM[3], vP[3], tP[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) vM[ii] = qe[ii * NP + vn];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+        tM[ii] = qe[(3 + voigt(ii, 0)) * NP + vn] * n0 + qe[(3 + voigt(ii, 1)) * NP + vn] * n1 +
+                 qe[(3 + voigt(ii, 2)) * NP + vn] * n2;
+      const int w = a.conn[(e0 + e) * 4 + f];
+      if ((w & 7) == 7) {
+        // traction-free wall: mirror state v+ = v-, (s n)+ = -(s n)-
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          vP[ii] = vM[ii];
+          tP[ii] = -tM[ii];
+        }
+      } else {
+        const int64_t kn = static_cast<int64_t>(w >> 5);
+        const int fnb = (w >> 3) & 3;
+        const int jn = a.perm[(w & 7) * NFP + j];
+        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          vP[ii] = tr[ii * NFP];
+          tP[ii] = -tr[(3 + ii) * NFP];  // the neighbour stored s n with its own normal
+        }
+      }
+      float jv[3], jt[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        jv[ii] = 0.5f * (vP[ii] - vM[ii]);
+        jt[ii] = 0.5f * (tP[ii] - tM[ii]);
+      }
+      const float jvn = jv[0] * n0 + jv[1] * n1 + jv[2] * n2;
+      const float jsnn = jt[0] * n0 + jt[1] * n1 + jt[2] * n2;
+      const float ZpP = rec[3], ZsP = rec[4], fs = rec[5], kp = rec[6], ks = rec[7];
+      const float A1 = fs * kp * (jsnn + ZpP * jvn);
+      const float A2 = fs * ks * (jsnn + ZsP * jvn);
+      float A3[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) A3[ii] = fs * (jt[ii] + ZsP * jv[ii]);
+      const float* cf = s_cf + e * CB;
+      const float lam = cf[0], mu = cf[1], cp = cf[5], cs = cf[6];
+      const float a1 = cp * A1 - cs * A2;
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) b[ii] = nn[ii] * a1 + ks * cs * A3[ii];
+      const float b2 = 2.0f * mu * (A1 - A2), c3 = mu * ks;
+      const int vi[6] = {0, 1, 2, 1, 0, 0};
+      const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        const int ii = vi[v], jj = vj[v];
+        float x = b2 * nn[ii] * nn[jj] + c3 * (nn[ii] * A3[jj] + A3[ii] * nn[jj]);
+        if (ii == jj) x += lam * A1;
+        b[3 + v] = x;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) reg.put_split(c, slot, e, b[c]);
+  }
+  __syncthreads();
+
+  // ---- C2: LIFT products (kept) ---------------------------------------------
+  floatx4 LL[PPW][9];
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) LL[q][c] = floatx4{0, 0, 0, 0};
+    const int p = wave + NW * q;
+    if (p >= S::PAIRS) continue;
+    const int mb = p % MB, nb = p / MB;
+    const int col = nb * 16 + nl;
+    if constexpr (PREC == 0) {
+      const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
+#pragma unroll 2
+      for (int kk = 0; kk < KL / 4; ++kk) {
+        const int k = kk * 4 + kq;
+        const float al = Lp[kk * 64];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) LL[q][c] = mfma_f32(al, s_B[reg.f32_word(c, k, col)], LL[q][c]);
+      }
+    } else {
+      const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
+      constexpr int LO = S::NSET * KMAX * E;
+      const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
+      const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
+      for (int kk = 0; kk < KL / 16; ++kk) {
+        const int off = ((kk * 4 + kq) * E + col) * 4;
+        const Frag16 al{Lh[kk * 64], Ll[kk * 64]};
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          Frag16 b;
+          b.hi = *reinterpret_cast<const shortx4*>(u + c * KMAX * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + c * KMAX * E + off);
+          LL[q][c] = mfma_split<PREC>(al, b, LL[q][c]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- B1: the nine fields (FP32) -------------------------------------------
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = tid + t * kEThreads;
+    if (i >= E * KP) continue;
+    const int e = i / KP, n = i - e * KP;
+    const bool ok = e < ne && n < NP;
+    const float* qe = a.q_in + (e0 + e) * NF * NP;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) reg.put_f32(c, n, e, ok ? qe[c * NP + n] : 0.0f);
+  }
+  __syncthreads();
+
+  // ---- C1: volume products and the epilogue, pair by pair -------------------
+  float* scr = s_scr + wave * SCR;
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+    const int p = wave + NW * q;
+    if (p >= S::PAIRS) continue;
+    const int mb = p % MB, nb = p / MB;
+    const int col = nb * 16 + nl;
+    const int ec = col < ne ? col : 0;
+    float G[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) G[t] = s_g[9 * ec + t];
+    floatx4 Dv[3][3], dS[3];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) {
+      dS[ii] = floatx4{0, 0, 0, 0};
+#pragma unroll
+      for (int l = 0; l < 3; ++l) Dv[ii][l] = floatx4{0, 0, 0, 0};
+    }
+    if constexpr (PREC == 0) {
+      const float* Dp = a.Dpack + static_cast<int64_t>(mb) * (KP / 4) * 64 + lane;
+      constexpr int JS = MB * (KP / 4) * 64;
+#pragma unroll 2
+      for (int kk = 0; kk < KP / 4; ++kk) {
+        const int k = kk * 4 + kq;
+        float x[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) x[c] = s_B[reg.f32_word(c, k, col)];
+        const float d[3] = {Dp[kk * 64], Dp[JS + kk * 64], Dp[2 * JS + kk * 64]};
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          const float si0 = x[3 + voigt(ii, 0)], si1 = x[3 + voigt(ii, 1)], si2 = x[3 + voigt(ii, 2)];
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            Dv[ii][l] = mfma_f32(d[l], x[ii], Dv[ii][l]);
+            const float ax = G[0 * 3 + l] * si0 + G[1 * 3 + l] * si1 + G[2 * 3 + l] * si2;
+            dS[ii] = mfma_f32(d[l], ax, dS[ii]);
+          }
+        }
+      }
+    } else {
+      constexpr int JS = MB * (KP / 16) * 64;
+      const shortx4* Dh = reinterpret_cast<const shortx4*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
+      const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
+      for (int kk = 0; kk < KP / 16; ++kk) {
+        float4 x[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) x[c] = *reinterpret_cast<const float4*>(s_B + reg.f32_word(c, kk * 16 + 4 * kq, col));
+        Frag16 d[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) d[l] = Frag16{Dh[l * JS + kk * 64], Dl[l * JS + kk * 64]};
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          const Frag16 vb = split4<PREC>(x[ii]);
+          const float4 s0 = x[3 + voigt(ii, 0)], s1 = x[3 + voigt(ii, 1)], s2 = x[3 + voigt(ii, 2)];
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            Dv[ii][l] = mfma_split<PREC>(d[l], vb, Dv[ii][l]);
+            const float g0 = G[0 * 3 + l], g1 = G[1 * 3 + l], g2 = G[2 * 3 + l];
+            float4 ax;
+            ax.x = g0 * s0.x + g1 * s1.x + g2 * s2.x;
+            ax.y = g0 * s0.y + g1 * s1.y + g2 * s2.y;
+            ax.z = g0 * s0.z + g1 * s1.z + g2 * s2.z;
+            ax.w = g0 * s0.w + g1 * s1.w + g2 * s2.w;
+            dS[ii] = mfma_split<PREC>(d[l], split4<PREC>(ax), dS[ii]);
+          }
+        }
+      }
+    }
+    // right-hand sides in the accumulator layout (rows 4 kq + r, column nl)
+    const float* cf = s_cf + ec * CB;
+    const float lam = cf[0], mu = cf[1], irho = cf[2];
+    float rr[9][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float gv[3][3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+          gv[ii][jj] = G[3 * jj + 0] * Dv[ii][0][r] + G[3 * jj + 1] * Dv[ii][1][r] + G[3 * jj + 2] * Dv[ii][2][r];
+      const float divv = gv[0][0] + gv[1][1] + gv[2][2];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) rr[ii][r] = irho * dS[ii][r] + LL[q][ii][r];
+      const int vi[6] = {0, 1, 2, 1, 0, 0};
+      const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        const int ii = vi[v], jj = vj[v];
+        float x = mu * (gv[ii][jj] + gv[jj][ii]) + LL[q][3 + v][r];
+        if (ii == jj) x += lam * divv;
+        rr[3 + v][r] = x;
+      }
+    }
+    // transpose, update and write field by field; lane -> (node mb*16 + nl, element nb*16 + kq + 4 it)
+    const int n = mb * 16 + nl;
+    const bool use1 = step && a.c1 != 0.0f, use2 = step && a.c2 != 0.0f;
+    float qn[9][4];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) scr[nl * 17 + 4 * kq + r] = rr[c][r];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      float rt[4];
+#pragma unroll
+      for (int it = 0; it < 4; ++it) rt[it] = scr[(kq + 4 * it) * 17 + nl];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int e = nb * 16 + kq + 4 * it;
+        qn[c][it] = 0.0f;
+        if (e >= ne || n >= NP) continue;
+        const int64_t base = (e0 + e) * NF * NP + c * NP + n;
+        a.r_out[base] = rt[it];
+        if (!step) continue;
+        const float h1 = use1 ? a.r1[base] : 0.0f;
+        const float h2 = use2 ? a.r2[base] : 0.0f;
+        qn[c][it] = a.q_in[base] + a.c0 * rt[it] + a.c1 * h1 + a.c2 * h2;
+        a.q_out[base] = qn[c][it];
+      }
+    }
+    if (!step) continue;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int e = nb * 16 + kq + 4 * it;
+      if (e >= ne || n >= NP) continue;
+      const float* fr = s_face + e * 4 * FW;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const int fj = a.nodeface[n * 3 + s];
+        if (fj < 0) break;
+        const int f = fj / NFP, j = fj - f * NFP;
+        const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
+        float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP + j;
+        tr[0] = qn[0][it];
+        tr[NFP] = qn[1][it];
+        tr[2 * NFP] = qn[2][it];
+        // s n with Voigt (11, 22, 33, 23, 13, 12)
+        tr[3 * NFP] = qn[3][it] * n0 + qn[8][it] * n1 + qn[7][it] * n2;
+        tr[4 * NFP] = qn[8][it] * n0 + qn[4][it] * n1 + qn[6][it] * n2;
+        tr[5 * NFP] = qn[7][it] * n0 + qn[6][it] * n1 + qn[5][it] * n2;
+      }
+    }
+  }
+}
+
+template <int N, int PREC>
+__global__ void __launch_bounds__(kEThreads)
+dg_step_mfma_elastic(StepArgs a) {
+  step_mfma_elastic_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
+}
+
+template <int N, int PREC>
+__global__ void __launch_bounds__(kEThreads)
+dg_step_mfma_elastic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
+  const int2 w = work[blockIdx.x];
+  if (w.x < 0) return;  // padding entry of the work list
+  const StepArgs a = args[w.x * kBatchPhases + phase];
+  step_mfma_elastic_tile<N, PREC>(a, w.y);
+}
+
+template <int N, int PREC>
+hipError_t emfma_impl(const StepArgs& a, hipStream_t s) {
+  constexpr int E = EShape<N, PREC>::E;
+  int64_t tiles = (a.K + E - 1) / E;
+  if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(kEThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N, int PREC>
+hipError_t emfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_step_mfma_elastic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(kEThreads), 0,
+                     s, args, work, phase);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define DGW_EMFMA_DISPATCH(CALL)                                                         \
+  switch (mfma_precision(variant)) {                                                     \
+    case 0:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 0); case 2: return CALL(2, 0); case 3: return CALL(3, 0); \
+        case 4: return CALL(4, 0); case 5: return CALL(5, 0); case 6: return CALL(6, 0); \
+        case 7: return CALL(7, 0); case 8: return CALL(8, 0);                            \
+      }                                                                                  \
+      break;                                                                             \
+    case 1:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 1); case 2: return CALL(2, 1); case 3: return CALL(3, 1); \
+        case 4: return CALL(4, 1); case 5: return CALL(5, 1); case 6: return CALL(6, 1); \
+        case 7: return CALL(7, 1); case 8: return CALL(8, 1);                            \
+      }                                                                                  \
+      break;                                                                             \
+    case 2:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 2); case 2: return CALL(2, 2); case 3: return CALL(3, 2); \
+        case 4: return CALL(4, 2); case 5: return CALL(5, 2); case 6: return CALL(6, 2); \
+        case 7: return CALL(7, 2); case 8: return CALL(8, 2);                            \
+      }                                                                                  \
+      break;                                                                             \
+  }
+
+int mfma_elastic_tile_elements(int N, int variant) {
+#define CALL(n, p) EShape<n, p>::E
+  DGW_EMFMA_DISPATCH(CALL)
+#undef CALL
+  return -1;
+}
+
+hipError_t launch_step_mfma_elastic(int N, int variant, const StepArgs& a, hipStream_t s) {
+#define CALL(n, p) emfma_impl<n, p>(a, s)
+  DGW_EMFMA_DISPATCH(CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_batch_mfma_elastic(int N, int variant, const StepArgs* args, const int2* work, int64_t ntiles,
+                                          int phase, hipStream_t s) {
+#define CALL(n, p) emfma_batch_impl<n, p>(args, work, ntiles, phase, s)
+  DGW_EMFMA_DISPATCH(CALL)
+#undef CALL
+  return hipErrorInvalidValue;
+}
+
+#undef DGW_EMFMA_DISPATCH
+
+}  // namespace dgw

@@ -1,0 +1,79 @@
+// Helpers shared by the MFMA step kernels (gfx950 matrix cores): operand
+// types, the FP32 operand-array swizzle, 16-bit splits and the split products.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dgw {
+namespace mfma {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+
+constexpr int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+// Column swizzle of the FP32 [row][E] operand arrays: a bijection on [0, E)
+// per row that keeps the fragment reads conflict-free and spreads the
+// row-consecutive staging writes over the banks.
+template <int E>
+__device__ __forceinline__ int swz(int m, int e) {
+  if constexpr (E == 16)
+    return e ^ ((m >> 1) & 15);
+  else
+    return (((e >> 4) ^ (m & 1)) << 4) + ((e & 15) ^ ((m >> 1) & 15));
+}
+
+// Round to nearest even: float -> bfloat16 bits.
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+// x = hi + lo in the 16-bit format of PREC (bit patterns).
+template <int PREC>
+__device__ __forceinline__ void split16(float x, uint16_t& hi, uint16_t& lo) {
+  if constexpr (PREC == 1) {
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+  } else {
+    const _Float16 h = static_cast<_Float16>(x);
+    const _Float16 l = static_cast<_Float16>(x - static_cast<float>(h));
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  }
+}
+
+struct Frag16 {
+  shortx4 hi, lo;
+};
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma16(shortx4 a, shortx4 b, floatx4 c) {
+  if constexpr (PREC == 1) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(halfx4, a), __builtin_bit_cast(halfx4, b), c,
+                                                 0, 0, 0);
+  }
+}
+
+// acc += A B with the split products (small terms first)
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma_split(const Frag16& a, const Frag16& b, floatx4 c) {
+  c = mfma16<PREC>(a.lo, b.hi, c);
+  c = mfma16<PREC>(a.hi, b.lo, c);
+  return mfma16<PREC>(a.hi, b.hi, c);
+}
+
+
+}  // namespace mfma
+}  // namespace dgw

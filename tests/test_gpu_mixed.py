@@ -1,4 +1,4 @@
-"""Mixed-precision MFMA variants (acoustic) against the FP64 oracle.
+"""Mixed-precision MFMA variants (acoustic and elastic) against the FP64 oracle.
 
 The BF16 / FP16 variants split both operands of the volume and LIFT
 products into 16-bit halves and accumulate D_hi x_hi + D_hi x_lo + D_lo x_hi
@@ -17,11 +17,12 @@ from tests._cases import Case, log
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("physics", ["acoustic", "elastic"])
 @pytest.mark.parametrize("variant", ["mfma_bf16", "mfma_f16"])
 @pytest.mark.parametrize("N", list(range(1, 9)))
-def test_mixed_precision_parity(N, variant):
-    log(f"{variant} acoustic N={N}")
-    c = Case("acoustic", N, 0, jitter=0.1, seed=70 + N, coef_kind="random", init="smooth",
+def test_mixed_precision_parity(N, variant, physics):
+    log(f"{variant} {physics} N={N}")
+    c = Case(physics, N, 0, jitter=0.1, seed=70 + N, coef_kind="random", init="smooth",
              dims=(3, 2, 3) if N <= 4 else (2, 2, 1))
     c.solver.variant = variant
     assert c.solver.variant == variant
@@ -38,18 +39,19 @@ def test_mixed_precision_parity(N, variant):
     assert err_q <= 1e-4 and np.all(per_q <= 1e-4)
 
 
+@pytest.mark.parametrize("physics", ["acoustic", "elastic"])
 @pytest.mark.parametrize("variant", ["mfma", "mfma_bf16", "mfma_f16"])
-def test_mfma_variants_in_batches(variant):
+def test_mfma_variants_in_batches(variant, physics):
     """A batch of meshes of several degrees on one MFMA variant follows the
     members' own trajectories."""
     from paper_1602_07997_amd import DGBatch, DGSolver
 
     cases = []
     for i, (N, dims) in enumerate([(2, (2, 3, 2)), (3, (3, 2, 2)), (5, (2, 2, 1)), (3, (2, 2, 2))]):
-        c = Case("acoustic", N, None, jitter=0.1, seed=90 + i, coef_kind="random", dims=dims)
+        c = Case(physics, N, None, jitter=0.1, seed=90 + i, coef_kind="random", dims=dims)
         c.solver.variant = variant
         c.solver.set_fields(c.to_gpu(c.q0_gpu))
-        t = DGSolver("acoustic", N, c.mesh.elem_xyz, c.mesh.elem_topo)
+        t = DGSolver(physics, N, c.mesh.elem_xyz, c.mesh.elem_topo)
         t.set_coefficients(torch.tensor(c.coef, dtype=torch.float32, device="cuda"))
         t.variant = variant
         t.set_fields(c.to_gpu(c.q0_gpu))
