@@ -40,7 +40,7 @@ if ROOT not in sys.path:
 
 import dginputs as di  # noqa: E402
 
-FP32_VARIANTS = ("valu", "mfma")  # candidates of the FP32 autotuned path
+FP32_VARIANTS = ("valu", "mfma", "elem")  # candidates of the FP32 autotuned path
 METRIC = "DG node-updates/s and % roofline, acoustic+elastic N=1..8: FP32 vs mixed/batched"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 FP32_PEAK = 157.3e12  # flop/s, MI355X FP32 vector / matrix
@@ -72,6 +72,8 @@ def algorithmic_model(physics: str, N: int):
 def kernel_source(variant: str, physics: str = "acoustic") -> str:
     if variant == "valu":
         name = "kernels.hip"
+    elif variant == "elem":
+        name = "kernels_elem.hip"
     else:
         name = "kernels_mfma.hip" if physics == "acoustic" else "kernels_mfma_elastic.hip"
     return os.path.join(ROOT, "paper_1602_07997_amd", "csrc", name)
@@ -80,6 +82,8 @@ def kernel_source(variant: str, physics: str = "acoustic") -> str:
 def kernel_name(physics: str, N: int, variant: str) -> str:
     if variant == "valu":
         return f"dg_step_kernel<N={N},{physics}>"
+    if variant == "elem":
+        return f"dg_step_elem_kernel<N={N},{physics}>"
     prec = {"mfma": 0, "mfma_bf16": 1, "mfma_f16": 2}[variant]
     return f"dg_step_mfma_{physics}<N={N},PREC={prec}>"
 
@@ -363,7 +367,7 @@ def main(argv=None):
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument(
-        "--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "auto", "auto-mixed"], default="auto",
+        "--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "elem", "auto", "auto-mixed"], default="auto",
         help="kernel variant for every degree; 'auto' lets the autotuner pick among the FP32 variants per "
         "degree, 'auto-mixed' also among the BF16/FP16 split-product variants",
     )

@@ -145,14 +145,17 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
  *   DG_VARIANT_MFMA_BF16  BF16 matrix cores with FP32 accumulation, both
  *                         operands split x = x_hi + x_lo and the products
  *                         D_hi x_hi + D_hi x_lo + D_lo x_hi;
- *   DG_VARIANT_MFMA_F16   the same with FP16 halves.
- * Every variant is built for both physics and N = 1..8.
+ *   DG_VARIANT_MFMA_F16   the same with FP16 halves;
+ *   DG_VARIANT_ELEM       one element per thread, all in registers
+ *                         (acoustic N = 1, 2; elastic N = 1).
+ * The VALU and MFMA variants are built for both physics and N = 1..8.
  * Fields, r and the update stay FP32 in every variant.  Returns
  * DG_E_UNSUPPORTED for a combination that is not built.                    */
 #define DG_VARIANT_VALU 0
 #define DG_VARIANT_MFMA 1
 #define DG_VARIANT_MFMA_BF16 2
 #define DG_VARIANT_MFMA_F16 3
+#define DG_VARIANT_ELEM 4
 dg_status dg_set_variant(dg_solver* s, int variant);
 dg_status dg_get_variant(dg_solver* s, int* variant);
 
@@ -230,7 +233,7 @@ dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* byt
  * kernel per degree and mesh follows the observation of Sec. 4 that the best
  * implementation strategy depends on the degree.  Errors: DG_E_STATE (no
  * coefficients or fields), DG_E_ARG, DG_E_HIP.                              */
-#define DG_NUM_VARIANTS 4
+#define DG_NUM_VARIANTS 5
 dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, double* us_per_step);
 
 typedef struct dg_batch dg_batch;

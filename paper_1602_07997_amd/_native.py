@@ -27,7 +27,8 @@ DG_VARIANT_VALU = 0
 DG_VARIANT_MFMA = 1
 DG_VARIANT_MFMA_BF16 = 2
 DG_VARIANT_MFMA_F16 = 3
-DG_NUM_VARIANTS = 4
+DG_VARIANT_ELEM = 4
+DG_NUM_VARIANTS = 5
 
 STATUS_NAMES = {
     DG_OK: "DG_OK",

@@ -615,12 +615,14 @@ bool variant_supported(int physics, int N, int variant) {
   if (N < 1 || N > 8 || (physics != 0 && physics != 1)) return false;
   if (variant == kVariantValu) return true;
   if (is_mfma(variant)) return true;
+  if (variant == kVariantElem) return elem_supported(physics, N);
   return false;
 }
 
 hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
   if (is_mfma(variant))
     return physics == 1 ? launch_step_mfma_elastic(N, variant, a, s) : launch_step_mfma(physics, N, variant, a, s);
+  if (variant == kVariantElem) return launch_step_elem(physics, N, a, s);
   if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_impl<n, p>(a, s)
   if (physics == 0) {
@@ -658,6 +660,7 @@ int64_t tiles_for(int physics, int N, int variant, int64_t K) {
 int tile_elements(int physics, int N, int variant) {
   if (!variant_supported(physics, N, variant)) return -1;
   if (is_mfma(variant)) return physics == 1 ? mfma_elastic_tile_elements(N, variant) : mfma_packing(N, variant).E;
+  if (variant == kVariantElem) return elem_tile_elements();
 #define TE(n, p) Tile<n, p>::KT
   if (physics == 0) {
     switch (N) {
@@ -680,6 +683,7 @@ hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* ar
   if (is_mfma(variant))
     return physics == 1 ? launch_step_batch_mfma_elastic(N, variant, args, work, ntiles, phase, s)
                         : launch_step_batch_mfma(physics, N, variant, args, work, ntiles, phase, s);
+  if (variant == kVariantElem) return launch_step_batch_elem(physics, N, args, work, ntiles, phase, s);
   if (variant != kVariantValu) return hipErrorInvalidValue;
 #define CALL(n, p) step_batch_impl<n, p>(args, work, ntiles, phase, s)
   if (physics == 0) {

@@ -49,7 +49,8 @@ constexpr int kVariantValu = 0;      // node per thread, VALU contractions
 constexpr int kVariantMfma = 1;      // element tiles, FP32 MFMA contractions
 constexpr int kVariantMfmaBf16 = 2;  // BF16 MFMA, three split products, FP32 accumulation
 constexpr int kVariantMfmaF16 = 3;   // FP16 MFMA, three split products, FP32 accumulation
-constexpr int kNumVariants = 4;
+constexpr int kVariantElem = 4;      // element per thread (acoustic N = 1, 2; elastic N = 1)
+constexpr int kNumVariants = 5;
 bool variant_supported(int physics, int N, int variant);
 
 // Fragment packing of the MFMA variants: node blocks MB, padded volume K (KP)
@@ -60,6 +61,12 @@ struct MfmaPacking {
 int mfma_precision(int variant);  // 0 FP32, 1 BF16, 2 FP16, -1 not an MFMA variant
 MfmaPacking mfma_packing(int N, int variant);
 hipError_t launch_step_mfma(int physics, int N, int variant, const StepArgs& a, hipStream_t s);
+// Element-per-thread kernels (N = 1, 2).
+bool elem_supported(int physics, int N);
+int elem_tile_elements();
+hipError_t launch_step_elem(int physics, int N, const StepArgs& a, hipStream_t s);
+hipError_t launch_step_batch_elem(int physics, int N, const StepArgs* args, const int2* work, int64_t ntiles,
+                                  int phase, hipStream_t s);
 // Elastic MFMA kernels (512-thread workgroups).
 int mfma_elastic_tile_elements(int N, int variant);
 hipError_t launch_step_mfma_elastic(int N, int variant, const StepArgs& a, hipStream_t s);

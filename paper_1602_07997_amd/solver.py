@@ -176,6 +176,7 @@ class DGSolver:
         "mfma": nat.DG_VARIANT_MFMA,
         "mfma_bf16": nat.DG_VARIANT_MFMA_BF16,
         "mfma_f16": nat.DG_VARIANT_MFMA_F16,
+        "elem": nat.DG_VARIANT_ELEM,
     }
 
     @property

@@ -213,3 +213,37 @@ def test_unknown_variant_rejected():
     assert lib.dg_set_variant(c.solver._h, 9) == DG_E_UNSUPPORTED
     assert lib.dg_set_variant(c.solver._h, -1) == DG_E_UNSUPPORTED
     assert c.solver.variant == "valu"
+
+
+@pytest.mark.parametrize("physics,N", [("acoustic", 1), ("acoustic", 2), ("elastic", 1)])
+def test_elem_variant_parity(physics, N):
+    """Element-per-thread variant: one right-hand side and 20 AB3 steps
+    against the oracle (ragged last block of 256 elements, walls)."""
+    log(f"elem variant {physics} N={N}")
+    c = Case(physics, N, 0, jitter=0.1, seed=60 + N, coef_kind="random", init="smooth", dims=(5, 4, 3))
+    c.solver.variant = "elem"
+    assert c.solver.variant == "elem"
+    r = c.solver.rhs(c.to_gpu(c.q0_gpu))
+    torch.cuda.synchronize()
+    err_r, _ = c.rel_l2(c.to_host(r), c.oracle.rhs(c.q0))
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    c.solver.step(20, c.dt)
+    q = c.to_host(c.solver.get_fields())
+    err_q, _ = c.rel_l2(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt))
+    log(f"  rhs rel L2 {err_r:.3e}, 20 steps {err_q:.3e}")
+    assert err_r <= 2e-6 and err_q <= 1e-5
+
+
+def test_elem_variant_periodic_and_rejected_above_its_degrees():
+    from paper_1602_07997_amd._native import DG_E_UNSUPPORTED, DGError
+
+    c = Case("acoustic", 1, 3, jitter=0.0, coef_kind="random", init="smooth", periodic=True)
+    c.solver.variant = "elem"
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    c.solver.step(15, c.dt)
+    err, _ = c.rel_l2(c.to_host(c.solver.get_fields()), AB3Stepper(c.oracle, c.q0).step(15, c.dt))
+    assert err <= 1e-5
+    d = Case("elastic", 2, 1, jitter=0.0, coef_kind="random", init="smooth")
+    with pytest.raises(DGError) as ei:
+        d.solver.variant = "elem"
+    assert ei.value.status == DG_E_UNSUPPORTED
