@@ -163,9 +163,15 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
   float cf[CB];
   load_run<CB, 4>(a.cf + k * CB, cf);
   const bool use1 = step && (a.c1 != 0.0f), use2 = step && (a.c2 != 0.0f);
-  float h1[NQ], h2[NQ];
-  if (use1) load_run<NQ, AQ>(a.r1 + k * NQ, h1);
-  if (use2) load_run<NQ, AQ>(a.r2 + k * NQ, h2);
+  // The AB3 history is read with the other loads where the registers allow
+  // (acoustic: more bytes in flight pays), and only for the update where they
+  // do not (elastic: fewer registers, more waves).
+  constexpr bool kEarly = (PHYS == 0);
+  float h1[kEarly ? NQ : 1], h2[kEarly ? NQ : 1];
+  if constexpr (kEarly) {
+    if (use1) load_run<NQ, AQ>(a.r1 + k * NQ, h1);
+    if (use2) load_run<NQ, AQ>(a.r2 + k * NQ, h2);
+  }
 
   // ---- face constants and upwind penalties at the face nodes ----------------
   constexpr int NL = (PHYS == 0) ? 2 : 5;
@@ -342,12 +348,26 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
   // ---- update, writes, own traces -------------------------------------------
   store_run<NQ, AQ>(a.r_out + k * NQ, r);
   if (!step) return;
+  if constexpr (kEarly) {
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    float x = q[i] + a.c0 * r[i];
-    if (use1) x += a.c1 * h1[i];
-    if (use2) x += a.c2 * h2[i];
-    q[i] = x;
+    for (int i = 0; i < NQ; ++i) {
+      float x = q[i] + a.c0 * r[i];
+      if (use1) x += a.c1 * h1[i];
+      if (use2) x += a.c2 * h2[i];
+      q[i] = x;
+    }
+  } else {
+    constexpr int RUN = (AQ >= 4) ? 4 : AQ;
+#pragma unroll
+    for (int i0 = 0; i0 < NQ; i0 += RUN) {
+      float g1[RUN], g2[RUN];
+#pragma unroll
+      for (int t = 0; t < RUN; ++t) g1[t] = g2[t] = 0.0f;
+      if (use1) load_run<RUN, RUN>(a.r1 + k * NQ + i0, g1);
+      if (use2) load_run<RUN, RUN>(a.r2 + k * NQ + i0, g2);
+#pragma unroll
+      for (int t = 0; t < RUN; ++t) q[i0 + t] = q[i0 + t] + a.c0 * r[i0 + t] + a.c1 * g1[t] + a.c2 * g2[t];
+    }
   }
   store_run<NQ, AQ>(a.q_out + k * NQ, q);
 #pragma unroll
