@@ -14,7 +14,9 @@ boxes, N uniform in {2..6}, seed 2, per-mesh jitter and log-uniform
 coefficients), each member's kernel variant picked by the autotuner, all
 advanced together by the batch (one launch per degree/variant group, six-step
 HIP graph replays); the same meshes stepped one by one with the plain
-node-per-thread kernel are timed beside it.
+node-per-thread kernel are timed beside it.  ``--config adjoint`` times the
+misfit forward solve and the adjoint gradient at the elastic N=4 workload
+(14,196 tetrahedra, 200 steps, checkpoints every 20).
 
 Prints one JSON line with the throughput, a roofline object for the kernel
 that takes the largest share of the time (algorithmic bytes and flops per
@@ -310,6 +312,66 @@ def run_batched(steps, warmup, log, count=64, seed=2, candidates=FP32_VARIANTS):
     }
 
 
+def main_adjoint(args, log):
+    """Misfit and gradient at the elastic N=4 adjoint workload (14,196 tets,
+    200 steps, checkpoints every 20, Ricker source at the centre, 64
+    receivers): forward solve with data, then the adjoint gradient."""
+    import torch
+
+    from paper_1602_07997_amd import DGMisfit, DGSolver
+    from paper_1602_07997_amd.adjoint import ricker
+
+    N, steps = 4, 200
+    mesh = di.kuhn_box(13, 13, 14, jitter=0.1, seed=3)
+    coef = di.elastic_loguniform(mesh, 3).astype(np.float32)
+    dt = di.time_step(mesh, N, di.max_wave_speed(coef.astype(np.float64), "elastic"))
+    rec = np.random.default_rng(4).uniform(0.1, 0.9, (64, 3))
+    wav = ricker(np.arange(steps + 1) * dt, 5.0, 0.5 * steps * dt)
+    cen = di.element_centroids(mesh)
+    blob = 1.0 + 0.05 * np.exp(-np.sum((cen - np.array([0.35, 0.6, 0.5])) ** 2, 1) / (2 * 0.15 ** 2))
+    s = DGSolver("elastic", N, mesh.elem_xyz, mesh.elem_topo)
+    s.set_coefficients(torch.tensor(coef * blob[:, None].astype(np.float32), device="cuda"))
+    s.set_fields(torch.zeros(s.field_shape, device="cuda"))
+    chosen = s.autotune(2, dt, None if args.variant == "auto-mixed" else FP32_VARIANTS)
+    f = DGMisfit(s, steps, dt, [0.5, 0.5, 0.5], wav, rec, checkpoint_every=20)
+    data, _ = f.forward()
+    s.set_coefficients(torch.tensor(coef, device="cuda"))
+    for _ in range(max(1, args.warmup // 5)):
+        f.forward(data)
+        f.gradient()
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 10)
+    t_f = t_g = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, J = f.forward(data)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = f.gradient()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_f += t1 - t0
+        t_g += t2 - t1
+    t_f /= reps
+    t_g /= reps
+    nodes = mesh.K * s.Np
+    log(f"  adjoint workload: K={mesh.K}, variant {s.variant} ({chosen}); forward {t_f * 1e3:.2f} ms, "
+        f"gradient {t_g * 1e3:.2f} ms, J = {J:.4e}, |g|max = {float(g.abs().max()):.3e}")
+    out = {
+        "metric": METRIC, "value": nodes * steps / (t_f + t_g), "unit": "node-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": (t_f + t_g) / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype_of([s.variant]),
+        "data": "synthetic",
+        "config": {"workload": "elastic N=4 adjoint: 14,196 tets, 200 AB3 steps, checkpoints every 20, "
+                               "Ricker point source, 64 receivers; misfit forward then gradient",
+                   "variant": s.variant},
+        "roofline": None, "cpu_baseline": None,
+        "adjoint": {"forward_ms": t_f * 1e3, "gradient_ms": t_g * 1e3, "gradient_over_forward": t_g / t_f},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def dtype_of(variants) -> str:
     mixed = [v for v in variants if v in ("mfma_bf16", "mfma_f16")]
     if not mixed:
@@ -363,7 +425,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", choices=["acoustic", "elastic", "batched"], default="acoustic")
+    ap.add_argument("--config", choices=["acoustic", "elastic", "batched", "adjoint"], default="acoustic")
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument(
@@ -414,6 +476,8 @@ def main(argv=None):
         del src, dst
     if physics == "batched":
         return main_batched(args, log)
+    if physics == "adjoint":
+        return main_adjoint(args, log)
     log(f"bench: {physics} sweep N={degrees}, {args.steps} timed steps, {args.warmup} warm-up")
     cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log, args.variant)
 

@@ -126,8 +126,10 @@ dg_status dg_mesh_connectivity(int64_t K, const int64_t* elem_topo, int64_t* e2e
  * factor of eq. (3); face normals and Fscale = sJ/J, the surface factor) and
  * connectivity are built on the host in float64 and uploaded.  `stream` is a
  * hipStream_t (NULL = default stream) used by every later call.  Device
- * memory is allocated here and freed by dg_destroy.  Errors: DG_E_ARG,
- * DG_E_UNSUPPORTED, DG_E_MESH (J <= 0, inconsistent face pairing), DG_E_HIP. */
+ * memory is allocated here and freed by dg_destroy.  K must lie in
+ * [1, 2^26) (the per-face connectivity word packs the neighbour index in 26
+ * bits).  Errors: DG_E_ARG (K out of range, null arrays), DG_E_UNSUPPORTED,
+ * DG_E_MESH (J <= 0, inconsistent face pairing), DG_E_HIP.                    */
 dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz,
                     const int64_t* elem_topo, void* stream, dg_solver** out);
 

@@ -130,3 +130,39 @@ def test_create_rejects_bad_meshes_before_device_work():
     xyz[0] += 0.01 * np.array([[0, 0, 0], [0, 0, 0], [0, 0, 0], [0, 0, 1.0]])
     st, h = _create(0, 2, xyz, topo)
     assert st == nat.DG_E_MESH
+
+
+def test_empty_and_oversized_meshes_rejected():
+    """K = 0 and K >= 2^26 are rejected before any device work (the per-face
+    connectivity word packs the neighbour index in 26 bits)."""
+    empty_xyz = np.zeros((0, 4, 3))
+    empty_topo = np.zeros((0, 4), dtype=np.int64)
+    st, h = _create(0, 2, empty_xyz, empty_topo)
+    assert st == nat.DG_E_ARG and not h.value
+    e2e = np.zeros((1, 4), dtype=np.int64)
+    e2f = np.zeros((1, 4), dtype=np.int32)
+    assert nat.lib.dg_mesh_connectivity(
+        0, empty_topo.ctypes.data_as(C.POINTER(C.c_int64)), e2e.ctypes.data_as(C.POINTER(C.c_int64)),
+        e2f.ctypes.data_as(C.POINTER(C.c_int32)), e2f.ctypes.data_as(C.POINTER(C.c_int32)),
+    ) == nat.DG_E_ARG
+    one = di.kuhn_box(1)
+    h = C.c_void_p()
+    st = nat.lib.dg_create(
+        0, 2, 1 << 26, one.elem_xyz.ctypes.data_as(C.POINTER(C.c_double)),
+        one.elem_topo.ctypes.data_as(C.POINTER(C.c_int64)), None, C.byref(h),
+    )
+    assert st == nat.DG_E_ARG and not h.value
+
+
+def test_batch_and_misfit_entry_points_reject_null_arguments():
+    out = C.c_void_p()
+    assert nat.lib.dg_batch_create(None, 0, None, C.byref(out)) == nat.DG_E_ARG
+    assert nat.lib.dg_batch_step(None, 1, None) == nat.DG_E_ARG
+    assert nat.lib.dg_autotune(None, 1, 1.0, 0, None) == nat.DG_E_ARG
+    assert nat.lib.dg_misfit_create(None, 10, 0.1, 5, 0, None, None, 1, None, C.byref(out)) == nat.DG_E_ARG
+    assert nat.lib.dg_misfit_forward(None, None, None, None) == nat.DG_E_ARG
+    assert nat.lib.dg_misfit_gradient(None, None) == nat.DG_E_ARG
+    assert nat.lib.dg_misfit_channels(None) == -1
+    n = C.c_int(0)
+    assert nat.lib.dg_batch_groups(None, C.byref(n), None, None, None) == nat.DG_E_ARG
+    assert nat.lib.dg_locate_points(None, 1, None, None, None) == nat.DG_E_ARG
