@@ -112,22 +112,23 @@ def compute_floor(physics: str, N: int, variant: str) -> float:
 
 def measured_traffic(physics: str, N: int, variant: str):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary (profiles/dg_step_<physics>_sweep_traffic.md), or None when the
-    kernel source has changed since the counters were taken."""
+    summaries (profiles/dg_step_<physics>[_mixed]_sweep_traffic.md), or None
+    when the kernel source has changed since the counters were taken."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", f"dg_step_{physics}_sweep_traffic.md")
-    if not os.path.exists(path):
-        return None
     sha = hashlib.sha1(open(kernel_source(variant, physics), "rb").read()).hexdigest()[:12]
     pat = re.compile(
         rf"^traffic {physics} N={N} variant={variant} bytes_per_launch=(\d+) kernel_sha1=([0-9a-f]+)$"
     )
-    for line in open(path):
-        m = pat.match(line.strip())
-        if m and m.group(2) == sha:
-            return int(m.group(1))
+    for name in (f"dg_step_{physics}_sweep_traffic.md", f"dg_step_{physics}_mixed_sweep_traffic.md"):
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            continue
+        for line in open(path):
+            m = pat.match(line.strip())
+            if m and m.group(2) == sha:
+                return int(m.group(1))
     return None
 
 
@@ -149,7 +150,7 @@ def init_fields(physics, xyz):
     return np.ascontiguousarray(np.moveaxis(f, 0, 1)).astype(np.float32)
 
 
-def run_gpu(physics, degrees, steps, warmup, log, variant="valu"):
+def run_gpu(physics, degrees, steps, warmup, log, variant="valu", variant_map=None):
     import torch
 
     from paper_1602_07997_amd import DGSolver
@@ -164,7 +165,9 @@ def run_gpu(physics, degrees, steps, warmup, log, variant="valu"):
         dt = di.time_step(mesh, N, di.max_wave_speed(coef, physics))
         s.step(2, dt)  # Euler and two-step start-up
         tuned = None
-        if variant in ("auto", "auto-mixed"):
+        if variant_map and N in variant_map:
+            s.variant = variant_map[N]
+        elif variant in ("auto", "auto-mixed"):
             tuned = s.autotune(3, dt, FP32_VARIANTS if variant == "auto" else None)
         else:
             s.variant = variant
@@ -433,6 +436,11 @@ def main(argv=None):
         help="kernel variant for every degree; 'auto' lets the autotuner pick among the FP32 variants per "
         "degree, 'auto-mixed' also among the BF16/FP16 split-product variants",
     )
+    ap.add_argument(
+        "--variant-map", type=str, default="",
+        help="fixed variant per degree, e.g. '1:elem,2:valu,3:mfma' (overrides --variant for those degrees; "
+        "profiling runs use it so that the profiler's own timing does not change the autotuner's choice)",
+    )
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument(
@@ -479,7 +487,8 @@ def main(argv=None):
     if physics == "adjoint":
         return main_adjoint(args, log)
     log(f"bench: {physics} sweep N={degrees}, {args.steps} timed steps, {args.warmup} warm-up")
-    cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log, args.variant)
+    vmap = {int(k): v for k, v in (item.split(":") for item in args.variant_map.split(",") if item)}
+    cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log, args.variant, vmap)
 
     per = []
     for c in cases:
