@@ -115,188 +115,212 @@ dg_record_kernel(int nch, const float* __restrict__ q, const int64_t* __restrict
   out[ch] = acc;
 }
 
-// One wavefront per element.
+// One wavefront per element.  Every global load is issued up front (the
+// element's accumulators, chi from the three adjoint states, r, the own and
+// neighbour traces of all four faces); the mass products read r from LDS and
+// the faces are processed together, one face node per lane.
 template <int N, int PHYS>
 __global__ void __launch_bounds__(kWave)
 dg_grad_accum_kernel(const GradArgs a) {
   constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
-  constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT;
-  constexpr int NJ = (PHYS == 0) ? 2 : 6;  // jump vectors per face node
+  constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT, CB = Phys<PHYS>::CB;
+  constexpr int NJ = (PHYS == 0) ? 2 : 6;      // jump vectors per face node
+  constexpr int NACC = (PHYS == 0) ? 10 : 19;  // accumulators used
+  constexpr int NQ = (PHYS == 0) ? 2 : 4;      // face quantities: gm (P, S), gp (P, S)
+  constexpr int FIT = (4 * NFP + kWave - 1) / kWave;
   __shared__ float s_chi[NF * NP];
-  __shared__ float s_jump[NJ * NFP];
+  __shared__ float s_r[NF * NP];
+  __shared__ float s_jump[4 * NJ * NFP];
+  __shared__ double s_out[kGradAccStride];
   const int64_t k = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t base = k * NF * NP;
+  double* acc = a.gacc + k * kGradAccStride;
+  const double old = lane < NACC ? acc[lane] : 0.0;
   for (int i = lane; i < NF * NP; i += kWave) {
     float v = a.c0 * a.phi1[base + i];
     if (a.c1 != 0.0f) v += a.c1 * a.phi2[base + i];
     if (a.c2 != 0.0f) v += a.c2 * a.phi3[base + i];
     s_chi[i] = v;
+    s_r[i] = a.r[base + i];
   }
-  __syncthreads();
-  const double Jk = a.J[k];
-  double* acc = a.gacc + k * kGradAccStride;
-
-  // ---- mass-weighted products of chi and r = A q ---------------------------
-  {
-    const float* r = a.r + base;
-    float t0 = 0.f, t1 = 0.f, t2 = 0.f;
-    for (int n = lane; n < NP; n += kWave) {
-      const float* Mn = a.mass + n * NP;
-      if constexpr (PHYS == 0) {
-        float mr[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int m = 0; m < NP; ++m) {
-          const float w = Mn[m];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) mr[c] += w * r[c * NP + m];
-        }
-        t0 += s_chi[n] * mr[0];
-        t1 += s_chi[NP + n] * mr[1] + s_chi[2 * NP + n] * mr[2] + s_chi[3 * NP + n] * mr[3];
-      } else {
-        float mr[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) mr[c] = 0.f;
-        for (int m = 0; m < NP; ++m) {
-          const float w = Mn[m];
-#pragma unroll
-          for (int c = 0; c < 9; ++c) mr[c] += w * r[c * NP + m];
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) t0 += s_chi[c * NP + n] * mr[c];
-#pragma unroll
-        for (int c = 3; c < 9; ++c) t1 += (c < 6 ? 1.0f : 2.0f) * s_chi[c * NP + n] * mr[c];
-        t2 += (s_chi[3 * NP + n] + s_chi[4 * NP + n] + s_chi[5 * NP + n]) * (mr[3] + mr[4] + mr[5]);
-      }
-    }
-    t0 = wave_sum(t0);
-    t1 = wave_sum(t1);
-    t2 = wave_sum(t2);
-    if (lane == 0) {
-      acc[0] += Jk * t0;
-      acc[1] += Jk * t1;
-      if constexpr (PHYS == 1) acc[2] += Jk * t2;
-    }
-  }
-
-  // ---- face terms ------------------------------------------------------------
   float G[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) G[t] = a.geo[k * 9 + t];
-  const float* cf = a.cf + k * Phys<PHYS>::CB;
-  for (int f = 0; f < 4; ++f) {
-    float nrm[3], fs;
-    face_normal(G, f, nrm, fs);
+  const float* cf = a.cf + k * CB;
+  // jumps (halved differences, the step kernel's convention) of all faces
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = lane + t * kWave;
+    if (i >= 4 * NFP) continue;
+    const int f = i / NFP, j = i - f * NFP;
     const int word = a.conn[k * 4 + f];
     const bool wall = (word & 7) == 7;
     const float* own = a.tr + (k * 4 + f) * NT * NFP;
     const float* nbr = own;
     int jn = 0;
-    // jumps (halved differences, the step kernel's convention)
-    float jl[NJ];
-    if (lane < NFP) {
-      const int j = lane;
-      if (!wall) {
-        const int64_t kn = static_cast<int64_t>(word >> 5);
-        const int fnb = (word >> 3) & 3;
-        jn = a.perm[(word & 7) * NFP + j];
-        nbr = a.tr + (kn * 4 + fnb) * NT * NFP;
-      }
-      if constexpr (PHYS == 0) {
-        const float pM = own[j], vnM = own[NFP + j];
-        const float pP = wall ? pM : nbr[jn];
-        const float vnP = wall ? -vnM : -nbr[NFP + jn];
-        const float jp = 0.5f * (pP - pM), jv = 0.5f * (vnP - vnM);
-        const float ZP = cf[4 + f];
-        jl[0] = jp - ZP * jv;  // alpha
-        jl[1] = jv;
-      } else {
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          const float vM = own[ii * NFP + j], tM = own[(3 + ii) * NFP + j];
-          const float vP = wall ? vM : nbr[ii * NFP + jn];
-          const float tP = wall ? -tM : -nbr[(3 + ii) * NFP + jn];
-          jl[ii] = 0.5f * (vP - vM);
-          jl[3 + ii] = 0.5f * (tP - tM);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < NJ; ++c) s_jump[c * NFP + j] = jl[c];
+    if (!wall) {
+      const int64_t kn = static_cast<int64_t>(word >> 5);
+      const int fnb = (word >> 3) & 3;
+      jn = a.perm[(word & 7) * NFP + j];
+      nbr = a.tr + (kn * 4 + fnb) * NT * NFP;
     }
-    __syncthreads();
-    float gm0 = 0.f, gp0 = 0.f, gm1 = 0.f, gp1 = 0.f;
-    if (lane < NFP) {
-      const int j = lane;
-      // face-mass images of the jumps at this face node
-      float mj[NJ];
+    float* sj = s_jump + f * NJ * NFP;
+    if constexpr (PHYS == 0) {
+      const float pM = own[j], vnM = own[NFP + j];
+      const float pP = wall ? pM : nbr[jn];
+      const float vnP = wall ? -vnM : -nbr[NFP + jn];
+      const float jp = 0.5f * (pP - pM), jv = 0.5f * (vnP - vnM);
+      sj[j] = jp - cf[4 + f] * jv;  // alpha, Z+ of this face
+      sj[NFP + j] = jv;
+    } else {
 #pragma unroll
-      for (int c = 0; c < NJ; ++c) mj[c] = 0.f;
-      for (int jj = 0; jj < NFP; ++jj) {
-        const float w = a.face_mass[j * NFP + jj];
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) mj[c] += w * s_jump[c * NFP + jj];
-      }
-      const int vn = a.fmask[f * NFP + j];
-      if constexpr (PHYS == 0) {
-        const float ZM = cf[2], ZP = cf[4 + f];
-        const float kc = 2.0f / (ZM + ZP);
-        const float yp = s_chi[vn];
-        const float yvn = nrm[0] * s_chi[NP + vn] + nrm[1] * s_chi[2 * NP + vn] + nrm[2] * s_chi[3 * NP + vn];
-        const float at = mj[0], jvt = mj[1];
-        gm0 = 0.5f * kc * kc * (-yp + ZP * yvn) * at;
-        gp0 = -(yp + ZM * yvn) * (0.5f * kc * kc * at + kc * jvt);
-      } else {
-        const float ZpM = cf[3], ZsM = cf[4], ZpP = cf[8 + f], ZsP = cf[12 + f];
-        const float kp = 2.0f / (ZpM + ZpP), ks = 2.0f / (ZsM + ZsP);
-        float yv[3], Yn[3];
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) yv[ii] = s_chi[ii * NP + vn];
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii)
-          Yn[ii] = s_chi[(3 + voigt(ii, 0)) * NP + vn] * nrm[0] + s_chi[(3 + voigt(ii, 1)) * NP + vn] * nrm[1] +
-                   s_chi[(3 + voigt(ii, 2)) * NP + vn] * nrm[2];
-        const float yvn = yv[0] * nrm[0] + yv[1] * nrm[1] + yv[2] * nrm[2];
-        const float Ynn = Yn[0] * nrm[0] + Yn[1] * nrm[1] + Yn[2] * nrm[2];
-        // face-mass images: jv (mj[0..2]), jt (mj[3..5])
-        const float jvnt = mj[0] * nrm[0] + mj[1] * nrm[1] + mj[2] * nrm[2];
-        const float jsnnt = mj[3] * nrm[0] + mj[4] * nrm[1] + mj[5] * nrm[2];
-        const float apt = jsnnt + ZpP * jvnt, ast = jsnnt + ZsP * jvnt;
-        float asvt[3];
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) asvt[ii] = mj[3 + ii] + ZsP * mj[ii];
-        const float up = Ynn - ZpM * yvn, us = ZsM * yvn - Ynn;
-        float w[3];
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) w[ii] = Yn[ii] - ZsM * yv[ii];
-        const float wa = w[0] * asvt[0] + w[1] * asvt[1] + w[2] * asvt[2];
-        const float base_s = ast * us + wa;
-        const float yva = yv[0] * asvt[0] + yv[1] * asvt[1] + yv[2] * asvt[2];
-        const float wj = w[0] * mj[0] + w[1] * mj[1] + w[2] * mj[2];
-        gm0 = -0.5f * kp * kp * apt * up - kp * apt * yvn;
-        gp0 = -0.5f * kp * kp * apt * up + kp * jvnt * up;
-        gm1 = -0.5f * ks * ks * base_s + ks * (ast * yvn - yva);
-        gp1 = -0.5f * ks * ks * base_s + ks * (jvnt * us + wj);
+      for (int ii = 0; ii < 3; ++ii) {
+        const float vM = own[ii * NFP + j], tM = own[(3 + ii) * NFP + j];
+        const float vP = wall ? vM : nbr[ii * NFP + jn];
+        const float tP = wall ? -tM : -nbr[(3 + ii) * NFP + jn];
+        sj[ii * NFP + j] = 0.5f * (vP - vM);
+        sj[(3 + ii) * NFP + j] = 0.5f * (tP - tM);
       }
     }
-    gm0 = wave_sum(gm0);
-    gp0 = wave_sum(gp0);
-    if constexpr (PHYS == 1) {
-      gm1 = wave_sum(gm1);
-      gp1 = wave_sum(gp1);
-    }
-    if (lane == 0) {
-      const double sJ = Jk * static_cast<double>(fs);
-      if constexpr (PHYS == 0) {
-        acc[2 + f] += sJ * gm0;
-        acc[6 + f] += sJ * gp0;
-      } else {
-        acc[3 + f] += sJ * gm0;
-        acc[7 + f] += sJ * gm1;
-        acc[11 + f] += sJ * gp0;
-        acc[15 + f] += sJ * gp1;
-      }
-    }
-    __syncthreads();  // s_jump is rewritten for the next face
   }
+  __syncthreads();
+
+  // ---- mass-weighted products of chi and r = A q ---------------------------
+  float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+  for (int n = lane; n < NP; n += kWave) {
+    float mr[NF];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) mr[c] = 0.f;
+    // M is symmetric: column n of M, contiguous across the lanes
+    for (int m = 0; m < NP; ++m) {
+      const float w = a.mass[m * NP + n];
+#pragma unroll
+      for (int c = 0; c < NF; ++c) mr[c] += w * s_r[c * NP + m];
+    }
+    if constexpr (PHYS == 0) {
+      t0 += s_chi[n] * mr[0];
+      t1 += s_chi[NP + n] * mr[1] + s_chi[2 * NP + n] * mr[2] + s_chi[3 * NP + n] * mr[3];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t0 += s_chi[c * NP + n] * mr[c];
+#pragma unroll
+      for (int c = 3; c < 9; ++c) t1 += (c < 6 ? 1.0f : 2.0f) * s_chi[c * NP + n] * mr[c];
+      t2 += (s_chi[3 * NP + n] + s_chi[4 * NP + n] + s_chi[5 * NP + n]) * (mr[3] + mr[4] + mr[5]);
+    }
+  }
+
+  // ---- face terms, one face node per lane -----------------------------------
+  float nrm[4][3], fsc[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) face_normal(G, f, nrm[f], fsc[f]);
+  float part[4][NQ];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) part[f][q] = 0.f;
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = lane + t * kWave;
+    if (i >= 4 * NFP) continue;
+    const int f = i / NFP, j = i - f * NFP;
+    const float* sj = s_jump + f * NJ * NFP;
+    float mj[NJ];  // face-mass images of the jumps at this face node
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) mj[c] = 0.f;
+    for (int jj = 0; jj < NFP; ++jj) {
+      const float w = a.face_mass[jj * NFP + j];  // symmetric: contiguous across lanes
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) mj[c] += w * sj[c * NFP + jj];
+    }
+    const int vn = a.fmask[f * NFP + j];
+    // this item's face: select its normal with 0/1 weights (no dynamic register index)
+    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+#pragma unroll
+    for (int ff = 0; ff < 4; ++ff) {
+      const float s = static_cast<float>(f == ff);
+      n0 += s * nrm[ff][0];
+      n1 += s * nrm[ff][1];
+      n2 += s * nrm[ff][2];
+    }
+    float q[NQ];
+    if constexpr (PHYS == 0) {
+      const float ZM = cf[2], ZP = cf[4 + f];
+      const float kc = 2.0f / (ZM + ZP);
+      const float yp = s_chi[vn];
+      const float yvn = n0 * s_chi[NP + vn] + n1 * s_chi[2 * NP + vn] + n2 * s_chi[3 * NP + vn];
+      const float at = mj[0], jvt = mj[1];
+      q[0] = 0.5f * kc * kc * (-yp + ZP * yvn) * at;
+      q[1] = -(yp + ZM * yvn) * (0.5f * kc * kc * at + kc * jvt);
+    } else {
+      const float ZpM = cf[3], ZsM = cf[4], ZpP = cf[8 + f], ZsP = cf[12 + f];
+      const float kp = 2.0f / (ZpM + ZpP), ks = 2.0f / (ZsM + ZsP);
+      const float nn[3] = {n0, n1, n2};
+      float yv[3], Yn[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) yv[ii] = s_chi[ii * NP + vn];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii)
+        Yn[ii] = s_chi[(3 + voigt(ii, 0)) * NP + vn] * nn[0] + s_chi[(3 + voigt(ii, 1)) * NP + vn] * nn[1] +
+                 s_chi[(3 + voigt(ii, 2)) * NP + vn] * nn[2];
+      const float yvn = yv[0] * nn[0] + yv[1] * nn[1] + yv[2] * nn[2];
+      const float Ynn = Yn[0] * nn[0] + Yn[1] * nn[1] + Yn[2] * nn[2];
+      // face-mass images: jv (mj[0..2]), jt (mj[3..5])
+      const float jvnt = mj[0] * nn[0] + mj[1] * nn[1] + mj[2] * nn[2];
+      const float jsnnt = mj[3] * nn[0] + mj[4] * nn[1] + mj[5] * nn[2];
+      const float apt = jsnnt + ZpP * jvnt, ast = jsnnt + ZsP * jvnt;
+      float asvt[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) asvt[ii] = mj[3 + ii] + ZsP * mj[ii];
+      const float up = Ynn - ZpM * yvn, us = ZsM * yvn - Ynn;
+      float w[3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) w[ii] = Yn[ii] - ZsM * yv[ii];
+      const float wa = w[0] * asvt[0] + w[1] * asvt[1] + w[2] * asvt[2];
+      const float base_s = ast * us + wa;
+      const float yva = yv[0] * asvt[0] + yv[1] * asvt[1] + yv[2] * asvt[2];
+      const float wj = w[0] * mj[0] + w[1] * mj[1] + w[2] * mj[2];
+      q[0] = -0.5f * kp * kp * apt * up - kp * apt * yvn;        // gm, Zp
+      q[1] = -0.5f * ks * ks * base_s + ks * (ast * yvn - yva);  // gm, Zs
+      q[2] = -0.5f * kp * kp * apt * up + kp * jvnt * up;        // gp, Zp
+      q[3] = -0.5f * ks * ks * base_s + ks * (jvnt * us + wj);   // gp, Zs
+    }
+#pragma unroll
+    for (int ff = 0; ff < 4; ++ff) {
+      const float s = static_cast<float>(f == ff);
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) part[ff][c] += s * q[c];
+    }
+  }
+  // ---- reductions and the accumulator update ---------------------------------
+  t0 = wave_sum(t0);
+  t1 = wave_sum(t1);
+  if constexpr (PHYS == 1) t2 = wave_sum(t2);
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) part[f][c] = wave_sum(part[f][c]);
+  if (lane == 0) {
+    const double Jk = a.J[k];
+    s_out[0] = Jk * t0;
+    s_out[1] = Jk * t1;
+    if constexpr (PHYS == 1) s_out[2] = Jk * t2;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const double sJ = Jk * static_cast<double>(fsc[f]);
+      if constexpr (PHYS == 0) {
+        s_out[2 + f] = sJ * part[f][0];
+        s_out[6 + f] = sJ * part[f][1];
+      } else {
+        s_out[3 + f] = sJ * part[f][0];
+        s_out[7 + f] = sJ * part[f][1];
+        s_out[11 + f] = sJ * part[f][2];
+        s_out[15 + f] = sJ * part[f][3];
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < NACC) acc[lane] = old + s_out[lane];
 }
 
 template <int PHYS>
