@@ -44,6 +44,9 @@ namespace {
 using namespace dev;
 using namespace mfma;
 
+// k-steps of operator prefetch in the FP32 products
+constexpr int kPrefetch = 4;
+
 template <int N, int PREC>
 struct MShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
@@ -56,6 +59,11 @@ struct MShape {
   static constexpr int E = 16 * NBLK;            // elements per tile
   static constexpr int PAIRS = MB * NBLK;
   static constexpr int REGION = 4 * KMAX * E;    // 4-byte words of B operands
+  // register budget: as many waves per SIMD as the LDS footprint allows
+  // (one wavefront of each workgroup per SIMD), at most 4
+  static constexpr int LDS_BYTES = 4 * (REGION + E * 9 + E * 8 + E * 4 * 8 + 4 * 16 * 17);
+  static constexpr int BY_LDS = (160 * 1024) / LDS_BYTES;
+  static constexpr int WAVES = BY_LDS < 1 ? 1 : (BY_LDS > 4 ? 4 : BY_LDS);
 };
 
 // B operand region: set s (0..3), row k, column e.
@@ -104,51 +112,122 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   const bool step = (a.mode == kStepMode);
   const BRegion<N, PREC> breg{s_B};
 
-  // ---- A1: constants, face records, neighbour traces ----------------------
-  for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
-  for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
-  for (int i = tid; i < ne * 4; i += kThreads) {
-    const int e = i >> 2, f = i & 3;
-    face_record<0>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
+  // ---- A1: every global read of the tile's inputs, issued together --------
+  // Each load is unconditional at a clamped, in-range address and unused
+  // values are dropped by selects, so that no load waits behind a branch or
+  // behind another item's load: the phase costs one memory round trip.
+  constexpr int GIT = (E * 9 + kThreads - 1) / kThreads;
+  constexpr int CIT = (E * CB + kThreads - 1) / kThreads;
+  constexpr int PIT = (6 * NFP + kThreads - 1) / kThreads;
+  static_assert(6 * NFP <= 4 * SCR, "the permutation table borrows the transpose scratch");
+  static_assert(E * 4 <= kThreads, "one face record per thread");
+  int* s_perm = reinterpret_cast<int*>(s_scr);  // free until the epilogue
+  float gv[GIT], cv[CIT];
+  int pv[PIT];
+#pragma unroll
+  for (int t = 0; t < GIT; ++t) {
+    const int i = tid + t * kThreads;
+    gv[t] = a.geo[e0 * 9 + (i < ne * 9 ? i : ne * 9 - 1)];
   }
-  // face-slot items: i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP
-  float pP[FIT], vnP[FIT];
-  bool wall[FIT];
+#pragma unroll
+  for (int t = 0; t < CIT; ++t) {
+    const int i = tid + t * kThreads;
+    cv[t] = a.cf[e0 * CB + (i < ne * CB ? i : ne * CB - 1)];
+  }
+#pragma unroll
+  for (int t = 0; t < PIT; ++t) {
+    const int i = tid + t * kThreads;
+    pv[t] = a.perm[i < 6 * NFP ? i : 6 * NFP - 1];
+  }
+  // connectivity word of this thread's face record (e, f) = (tid / 4, tid % 4)
+  const int rec_e = tid >> 2, rec_f = tid & 3;
+  const int rec_word = a.conn[(e0 + (rec_e < ne ? rec_e : ne - 1)) * 4 + rec_f];
+  // face-slot items i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP:
+  // connectivity word and own trace (p, v.n of the fields read this step)
+  int cw[FIT];
+  float pM[FIT], vnM[FIT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kThreads;
-    pP[t] = vnP[t] = 0.0f;
-    wall[t] = true;
     const int e = i / KL, slot = i - e * KL;
-    if (e < ne && slot < 4 * NFP) {
-      const int f = slot / NFP, j = slot - f * NFP;
-      const int w = a.conn[(e0 + e) * 4 + f];
-      wall[t] = (w & 7) == 7;
-      if (!wall[t]) {
-        const int64_t kn = static_cast<int64_t>(w >> 5);
-        const int fnb = (w >> 3) & 3;
-        const int jn = a.perm[(w & 7) * NFP + j];
-        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
-        pP[t] = tr[0];
-        vnP[t] = -tr[NFP];  // the neighbour stored v.n with its own normal
-      }
-    }
+    const bool ok = e < ne && slot < 4 * NFP;
+    const int ec = ok ? e : 0, sc = ok ? slot : 0;
+    const int f = sc / NFP, j = sc - f * NFP;
+    cw[t] = a.conn[(e0 + ec) * 4 + f];
+    const float* own = a.qf_in + ((e0 + ec) * 4 + f) * NT * NFP + j;
+    pM[t] = own[0];
+    vnM[t] = own[NFP];
+  }
+  // node items i = e*KP + n (n < KP, so that the zero padding is written
+  // too): the fields of the first NIT1 items now, the rest with the
+  // neighbour traces (register budget)
+  constexpr int NIT1 = NIT < 6 ? NIT : 6;
+  float qv[NIT][NF];
+  auto load_node = [&](int t) {
+    const int i = tid + t * kThreads;
+    const int e = i / KP, n = i - e * KP;
+    const bool ok = i < E * KP && e < ne && n < NP;
+    const float* qe = a.q_in + (e0 + (ok ? e : 0)) * NF * NP + (ok ? n : 0);
+#pragma unroll
+    for (int c = 0; c < NF; ++c) qv[t][c] = qe[c * NP];
+  };
+#pragma unroll
+  for (int t = 0; t < NIT1; ++t) load_node(t);
+#pragma unroll
+  for (int t = 0; t < GIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i < ne * 9) s_g[i] = gv[t];
+  }
+#pragma unroll
+  for (int t = 0; t < CIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i < ne * CB) s_cf[i] = cv[t];
+  }
+#pragma unroll
+  for (int t = 0; t < PIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i < 6 * NFP) s_perm[i] = pv[t];
   }
   __syncthreads();
 
-  // ---- A2: volume operands p, U_j; upwind alpha at the face slots ---------
+  // ---- A2: neighbour traces; face records; volume operands p, U_j ---------
+#pragma unroll
+  for (int t = NIT1; t < NIT; ++t) load_node(t);
+  // upwind alpha at the face slots from the own and neighbour traces
+  // (rigid wall: mirror state p+ = p-, v.n+ = -v.n-; Z+ = Z- there)
+  float alpha[FIT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    const int e = i / KL, slot = i - e * KL;
+    const bool ok = e < ne && slot < 4 * NFP;
+    const int ec = ok ? e : 0, sc = ok ? slot : 0;
+    const int f = sc / NFP, j = sc - f * NFP;
+    const int w = cw[t];
+    const bool wall = (w & 7) == 7;
+    // a wall reads its own trace (in range, value unused)
+    const int64_t kn = wall ? e0 + ec : static_cast<int64_t>(w >> 5);
+    const int fnb = wall ? f : (w >> 3) & 3;
+    const int jn = wall ? j : s_perm[(w & 7) * NFP + j];
+    const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
+    const float pP = tr[0];
+    const float vnP = -tr[NFP];  // the neighbour stored v.n with its own normal
+    const float ZP = wall ? s_cf[ec * CB + 2] : s_cf[ec * CB + 4 + f];
+    const float pp = wall ? pM[t] : pP;
+    const float vp = wall ? -vnM[t] : vnP;
+    alpha[t] = ok ? 0.5f * (pp - pM[t]) - ZP * 0.5f * (vp - vnM[t]) : 0.0f;
+  }
+  if (rec_e < ne) face_record<0>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
 #pragma unroll
   for (int t = 0; t < NIT; ++t) {
     const int i = tid + t * kThreads;
     if (i >= E * KP) continue;
-    // items over (e, n) with n < KP so that the zero padding is written too
     const int e = i / KP, n = i - e * KP;
     float p = 0.f, u0 = 0.f, u1 = 0.f, u2 = 0.f;
     if (e < ne && n < NP) {
-      const float* qe = a.q_in + (e0 + e) * NF * NP;
-      p = qe[n];
-      const float v0 = qe[NP + n], v1 = qe[2 * NP + n], v2 = qe[3 * NP + n];
       const float* G = s_g + 9 * e;
+      const float v0 = qv[t][1], v1 = qv[t][2], v2 = qv[t][3];
+      p = qv[t][0];
       u0 = G[0] * v0 + G[3] * v1 + G[6] * v2;
       u1 = G[1] * v0 + G[4] * v1 + G[7] * v2;
       u2 = G[2] * v0 + G[5] * v1 + G[8] * v2;
@@ -157,25 +236,6 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     breg.put(1, n, e, u0);
     breg.put(2, n, e, u1);
     breg.put(3, n, e, u2);
-  }
-  float alpha[FIT];
-#pragma unroll
-  for (int t = 0; t < FIT; ++t) {
-    const int i = tid + t * kThreads;
-    alpha[t] = 0.0f;
-    const int e = i / KL, slot = i - e * KL;
-    if (e < ne && slot < 4 * NFP) {
-      const int f = slot / NFP, j = slot - f * NFP;
-      const float* rec = s_face + (e * 4 + f) * FW;
-      const int vn = a.fmask[f * NFP + j];
-      const float* qe = a.q_in + (e0 + e) * NF * NP;
-      const float pM = qe[vn];
-      const float vnM = rec[0] * qe[NP + vn] + rec[1] * qe[2 * NP + vn] + rec[2] * qe[3 * NP + vn];
-      // rigid wall: mirror state p+ = p-, v.n+ = -v.n-
-      const float pp = wall[t] ? pM : pP[t];
-      const float vp = wall[t] ? -vnM : vnP[t];
-      alpha[t] = 0.5f * (pp - pM) - rec[3] * 0.5f * (vp - vnM);
-    }
   }
   __syncthreads();
 
@@ -192,21 +252,57 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     if constexpr (PREC == 0) {
       const float* Dp = a.Dpack + static_cast<int64_t>(mb) * (KP / 4) * 64 + lane;
       constexpr int JS = MB * (KP / 4) * 64;
-#pragma unroll 4
-      for (int kk = 0; kk < KP / 4; ++kk) {
-        const int k = kk * 4 + kq;
-        const int c = swz<E>(k, col);
-        const float bp = s_B[(0 * KMAX + k) * E + c];
-        const float b0 = s_B[(1 * KMAX + k) * E + c];
-        const float b1 = s_B[(2 * KMAX + k) * E + c];
-        const float b2 = s_B[(3 * KMAX + k) * E + c];
-        const float a0 = Dp[kk * 64], a1 = Dp[JS + kk * 64], a2 = Dp[2 * JS + kk * 64];
-        T0[q] = mfma_f32(a0, bp, T0[q]);
-        T1[q] = mfma_f32(a1, bp, T1[q]);
-        T2[q] = mfma_f32(a2, bp, T2[q]);
-        DV[q] = mfma_f32(a0, b0, DV[q]);
-        DV[q] = mfma_f32(a1, b1, DV[q]);
-        DV[q] = mfma_f32(a2, b2, DV[q]);
+      // Operator fragments stream from L2 through two register sets: the
+      // loads of the next group of PD k-steps are issued before the products
+      // of the current group (the scheduling barrier keeps them there), so
+      // their latency overlaps PD k-steps of products.
+      constexpr int NK = KP / 4, PD = NK < kPrefetch ? NK : kPrefetch;
+      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
+      float ra[PD][3], rb[PD][3];
+      auto load = [&](float (&r)[PD][3], int g) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          const int kk = g * PD + i < NK ? g * PD + i : NK - 1;  // clamped; the extra reads are unused
+          r[i][0] = Dp[kk * 64];
+          r[i][1] = Dp[JS + kk * 64];
+          r[i][2] = Dp[2 * JS + kk * 64];
+        }
+      };
+      auto compute = [&](const float (&r)[PD][3], int g, int cnt) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int k = (g * PD + i) * 4 + kq;
+          const int c = swz<E>(k, col);
+          const float bp = s_B[(0 * KMAX + k) * E + c];
+          const float b0 = s_B[(1 * KMAX + k) * E + c];
+          const float b1 = s_B[(2 * KMAX + k) * E + c];
+          const float b2 = s_B[(3 * KMAX + k) * E + c];
+          T0[q] = mfma_f32(r[i][0], bp, T0[q]);
+          T1[q] = mfma_f32(r[i][1], bp, T1[q]);
+          T2[q] = mfma_f32(r[i][2], bp, T2[q]);
+          DV[q] = mfma_f32(r[i][0], b0, DV[q]);
+          DV[q] = mfma_f32(r[i][1], b1, DV[q]);
+          DV[q] = mfma_f32(r[i][2], b2, DV[q]);
+        }
+      };
+      load(ra, 0);
+#pragma unroll 1
+      for (int g = 0; g + 2 < NGT; g += 2) {
+        load(rb, g + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, g, PD);
+        load(ra, g + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(rb, g + 1, PD);
+      }
+      if constexpr (NGT % 2 == 1) {
+        compute(ra, NGT - 1, LAST);
+      } else {
+        load(rb, NGT - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, NGT - 2, PD);
+        compute(rb, NGT - 1, LAST);
       }
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
@@ -275,15 +371,42 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     floatx4 lp = {0, 0, 0, 0}, l0 = lp, l1 = lp, l2 = lp;
     if constexpr (PREC == 0) {
       const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
-#pragma unroll 4
-      for (int kk = 0; kk < KL / 4; ++kk) {
-        const int k = kk * 4 + kq;
-        const int c = swz<E>(k, col);
-        const float al = Lp[kk * 64];
-        lp = mfma_f32(al, s_B[(0 * KMAX + k) * E + c], lp);
-        l0 = mfma_f32(al, s_B[(1 * KMAX + k) * E + c], l0);
-        l1 = mfma_f32(al, s_B[(2 * KMAX + k) * E + c], l1);
-        l2 = mfma_f32(al, s_B[(3 * KMAX + k) * E + c], l2);
+      constexpr int NK = KL / 4, PD = NK < 2 * kPrefetch ? NK : 2 * kPrefetch;
+      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
+      float ra[PD], rb[PD];
+      auto load = [&](float (&r)[PD], int g) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) r[i] = Lp[(g * PD + i < NK ? g * PD + i : NK - 1) * 64];
+      };
+      auto compute = [&](const float (&r)[PD], int g, int cnt) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int k = (g * PD + i) * 4 + kq;
+          const int c = swz<E>(k, col);
+          lp = mfma_f32(r[i], s_B[(0 * KMAX + k) * E + c], lp);
+          l0 = mfma_f32(r[i], s_B[(1 * KMAX + k) * E + c], l0);
+          l1 = mfma_f32(r[i], s_B[(2 * KMAX + k) * E + c], l1);
+          l2 = mfma_f32(r[i], s_B[(3 * KMAX + k) * E + c], l2);
+        }
+      };
+      load(ra, 0);
+#pragma unroll 1
+      for (int g = 0; g + 2 < NGT; g += 2) {
+        load(rb, g + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, g, PD);
+        load(ra, g + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(rb, g + 1, PD);
+      }
+      if constexpr (NGT % 2 == 1) {
+        compute(ra, NGT - 1, LAST);
+      } else {
+        load(rb, NGT - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, NGT - 2, PD);
+        compute(rb, NGT - 1, LAST);
       }
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
@@ -309,6 +432,8 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
         l2 = mfma_split<PREC>(al, b, l2);
       }
     }
+    const int n = mb * 16 + nl;
+    const int ncl = n < NP ? n : NP - 1;
     // right-hand sides in the accumulator layout: row 4*kq + r, column nl
     float rr[4][4];
     {
@@ -325,7 +450,6 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     }
     // transpose field by field through the wave's scratch:
     // lane -> (node mb*16 + nl, element nb*16 + eg + 4 it)
-    const int n = mb * 16 + nl;
     float rt[4][4];  // [field][it]
 #pragma unroll
     for (int c = 0; c < NF; ++c) {
@@ -338,26 +462,38 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
+    // AB3 update: fields and history read in two halves (register budget),
+    // each half's reads issued together at clamped addresses
     float qn[4][4];
+    int nfs[3] = {-1, -1, -1};
     if (step) {
-      float qo[4][4], h1[4][4], h2[4][4];
-      const bool use1 = a.c1 != 0.0f, use2 = a.c2 != 0.0f;
+      const float* p1 = a.c1 != 0.0f ? a.r1 : a.q_in;  // history read only where it is used
+      const float* p2 = a.c2 != 0.0f ? a.r2 : a.q_in;
+      const float w1 = a.c1 != 0.0f ? 1.0f : 0.0f, w2 = a.c2 != 0.0f ? 1.0f : 0.0f;
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int e = nb * 16 + eg + 4 * it;
-        const bool ok = e < ne && n < NP;
-        const int64_t base = (e0 + e) * NF * NP + n;
+      for (int s = 0; s < 3; ++s) nfs[s] = a.nodeface[ncl * 3 + s];
 #pragma unroll
-        for (int c = 0; c < NF; ++c) {
-          qo[c][it] = ok ? a.q_in[base + c * NP] : 0.0f;
-          h1[c][it] = (ok && use1) ? a.r1[base + c * NP] : 0.0f;
-          h2[c][it] = (ok && use2) ? a.r2[base + c * NP] : 0.0f;
+      for (int half = 0; half < 2; ++half) {
+        float qo[4][2], h1[4][2], h2[4][2];
+#pragma unroll
+        for (int ih = 0; ih < 2; ++ih) {
+          const int e = nb * 16 + eg + 4 * (2 * half + ih);
+          const int64_t base = (e0 + (e < ne ? e : ne - 1)) * NF * NP + ncl;
+#pragma unroll
+          for (int c = 0; c < NF; ++c) {
+            qo[c][ih] = a.q_in[base + c * NP];
+            h1[c][ih] = p1[base + c * NP];
+            h2[c][ih] = p2[base + c * NP];
+          }
         }
+#pragma unroll
+        for (int ih = 0; ih < 2; ++ih)
+#pragma unroll
+          for (int c = 0; c < NF; ++c) {
+            const int it = 2 * half + ih;
+            qn[c][it] = qo[c][ih] + a.c0 * rt[c][it] + a.c1 * (w1 * h1[c][ih]) + a.c2 * (w2 * h2[c][ih]);
+          }
       }
-#pragma unroll
-      for (int it = 0; it < 4; ++it)
-#pragma unroll
-        for (int c = 0; c < NF; ++c) qn[c][it] = qo[c][it] + a.c0 * rt[c][it] + a.c1 * h1[c][it] + a.c2 * h2[c][it];
     }
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
@@ -372,7 +508,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       const float* fr = s_face + e * 4 * FW;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        const int fj = a.nodeface[n * 3 + s];
+        const int fj = nfs[s];
         if (fj < 0) break;
         const int f = fj / NFP, j = fj - f * NFP;
         float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP + j;
