@@ -81,68 +81,151 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
   const bool step = (a.mode == kStepMode);
 
   // ---- phase A: issue every global load before the first barrier ----------
-  // neighbour traces of this thread's face-node items, straight from the
-  // connectivity word (no LDS round trip)
+  // Loads are unconditional at clamped (in-range) addresses and unused values
+  // are dropped by selects, so that no load waits behind a branch or behind
+  // another item's load.  Three dependent rounds: (1) everything indexed by
+  // the tile alone, (2) the face-node permutation of each face item, (3) the
+  // neighbour traces.
+  constexpr int QV = (KT * NF * NP + 4 * kThreads - 1) / (4 * kThreads);  // float4 per thread
+  constexpr int GIT = (KT * 9 + kThreads - 1) / kThreads;
+  constexpr int CIT = (KT * CB + kThreads - 1) / kThreads;
+  static_assert(KT * 4 <= kThreads, "one face record per thread");
+  // (1) connectivity words of the face-node items
   int word[FIT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    const bool ok = i < ne * NFN;
+    const int e = ok ? i / NFN : 0, f = ok ? (i - e * NFN) / NFP : 0;
+    word[t] = a.conn[(e0 + e) * 4 + f];
+  }
+  // (1) AB3 history of this thread's node items (read only where it is used)
+  float h1[NIT][NF], h2[NIT][NF];
+  {
+    const bool use1 = step && (a.c1 != 0.0f), use2 = step && (a.c2 != 0.0f);
+    const float* p1 = use1 ? a.r1 : a.q_in;
+    const float* p2 = use2 ? a.r2 : a.q_in;
+#pragma unroll
+    for (int t = 0; t < NIT; ++t) {
+      const int i = tid + t * kThreads;
+      const int ic = i < ne * NP ? i : 0;
+      const int e = ic / NP, n = ic - e * NP;
+      const int64_t base = (e0 + e) * NF * NP + n;
+#pragma unroll
+      for (int c = 0; c < NF; ++c) {
+        const float x1 = p1[base + c * NP], x2 = p2[base + c * NP];
+        h1[t][c] = use1 ? x1 : 0.0f;
+        h2[t][c] = use2 ? x2 : 0.0f;
+      }
+    }
+  }
+  // (1) the tile's fields, inverse Jacobians, coefficients and face-record words
+  const int cnt = ne * NF * NP;
+  const bool vec4 = ((e0 * NF * NP) & 3) == 0;
+  const int nfull = vec4 ? cnt >> 2 : 0;  // whole float4 of the aligned copy
+  float4 qv[QV];
+  float qtail;
+  {
+    const float* src = a.q_in + e0 * NF * NP;
+    // the aligned copy's last cnt % 4 values, one per thread
+    qtail = src[4 * nfull + tid < cnt ? 4 * nfull + tid : 0];
+#pragma unroll
+    for (int t = 0; t < QV; ++t) {
+      const int i4 = tid + t * kThreads;
+      if (vec4) {
+        qv[t] = reinterpret_cast<const float4*>(src)[i4 < nfull ? i4 : 0];
+      } else {
+        float x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ii = 4 * i4 + u;
+          x[u] = src[ii < cnt ? ii : 0];
+        }
+        qv[t] = make_float4(x[0], x[1], x[2], x[3]);
+      }
+    }
+  }
+  float gv[GIT], cv[CIT];
+#pragma unroll
+  for (int t = 0; t < GIT; ++t) {
+    const int i = tid + t * kThreads;
+    gv[t] = a.geo[e0 * 9 + (i < ne * 9 ? i : 0)];
+  }
+#pragma unroll
+  for (int t = 0; t < CIT; ++t) {
+    const int i = tid + t * kThreads;
+    cv[t] = a.cf[e0 * CB + (i < ne * CB ? i : 0)];
+  }
+  const int rec_e = tid >> 2, rec_f = tid & 3;
+  const int rec_word = a.conn[(e0 + (rec_e < ne ? rec_e : 0)) * 4 + rec_f];
+  // volume node of each face-node item; face slots of each node item
+  int vnode[FIT], nfs[NIT][3];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    const bool ok = i < ne * NFN;
+    const int e = ok ? i / NFN : 0, fn = ok ? i - e * NFN : 0;
+    vnode[t] = a.fmask[fn];
+  }
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = tid + t * kThreads;
+    const int ic = i < ne * NP ? i : 0;
+    const int n = ic - (ic / NP) * NP;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) nfs[t][s] = a.nodeface[n * 3 + s];
+  }
+  // (2) permuted face node on the neighbour's side
+  int jn[FIT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    const bool ok = i < ne * NFN;
+    const int e = ok ? i / NFN : 0, fn = ok ? i - e * NFN : 0;
+    const int j = fn - (fn / NFP) * NFP;
+    const int o = (word[t] & 7) == 7 ? 0 : (word[t] & 7);
+    jn[t] = a.perm[o * NFP + j];
+  }
+  // (3) neighbour traces (a wall reads its own, in range and unused)
   float nbt[FIT][NT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kThreads;
-    word[t] = 7;
+    const bool ok = i < ne * NFN;
+    const int e = ok ? i / NFN : 0, fn = ok ? i - e * NFN : 0;
+    const int f = fn / NFP, j = fn - f * NFP;
+    const int w = word[t];
+    const bool wall = (w & 7) == 7;
+    const int64_t kn = wall ? e0 + e : static_cast<int64_t>(w >> 5);
+    const int fnb = wall ? f : (w >> 3) & 3;
+    const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + (wall ? j : jn[t]);
 #pragma unroll
-    for (int c = 0; c < NT; ++c) nbt[t][c] = 0.0f;
-    if (i < ne * NFN) {
-      const int e = i / NFN, fn = i - e * NFN;
-      const int f = fn / NFP, j = fn - f * NFP;
-      const int w = a.conn[(e0 + e) * 4 + f];
-      word[t] = w;
-      if ((w & 7) != 7) {
-        const int64_t kn = static_cast<int64_t>(w >> 5);
-        const int fnb = (w >> 3) & 3;
-        const int jn = a.perm[(w & 7) * NFP + j];
-        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) nbt[t][c] = tr[c * NFP];
-      }
-    }
+    for (int c = 0; c < NT; ++c) nbt[t][c] = tr[c * NFP];
   }
-  // AB3 history of this thread's node items
-  float h1[NIT][NF], h2[NIT][NF];
-  const bool use1 = step && (a.c1 != 0.0f), use2 = step && (a.c2 != 0.0f);
+  // stage the tile into LDS
 #pragma unroll
-  for (int t = 0; t < NIT; ++t) {
+  for (int t = 0; t < QV; ++t) {
+    const int i4 = tid + t * kThreads;
+    const float x[4] = {qv[t].x, qv[t].y, qv[t].z, qv[t].w};
+    const int lim = vec4 ? 4 * nfull : cnt;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * i4 + u < lim) s_q[4 * i4 + u] = x[u];
+  }
+  if (vec4 && 4 * nfull + tid < cnt) s_q[4 * nfull + tid] = qtail;
+#pragma unroll
+  for (int t = 0; t < GIT; ++t) {
     const int i = tid + t * kThreads;
-    if (i < ne * NP) {
-      const int e = i / NP, n = i - e * NP;
-      const int64_t base = (e0 + e) * NF * NP + n;
-#pragma unroll
-      for (int c = 0; c < NF; ++c) {
-        h1[t][c] = use1 ? a.r1[base + c * NP] : 0.0f;
-        h2[t][c] = use2 ? a.r2[base + c * NP] : 0.0f;
-      }
-    }
+    if (i < ne * 9) s_g[i] = gv[t];
   }
-  // the tile's fields, inverse Jacobians and coefficients into LDS
-  {
-    const float* src = a.q_in + e0 * NF * NP;
-    const int cnt = ne * NF * NP;
-    if (((e0 * NF * NP) & 3) == 0) {
-      const float4* src4 = reinterpret_cast<const float4*>(src);
-      float4* dst4 = reinterpret_cast<float4*>(s_q);
-      for (int i = tid; i < cnt / 4; i += kThreads) dst4[i] = src4[i];
-      for (int i = (cnt / 4) * 4 + tid; i < cnt; i += kThreads) s_q[i] = src[i];
-    } else {
-      for (int i = tid; i < cnt; i += kThreads) s_q[i] = src[i];
-    }
-    for (int i = tid; i < ne * 9; i += kThreads) s_g[i] = a.geo[e0 * 9 + i];
-    for (int i = tid; i < ne * CB; i += kThreads) s_cf[i] = a.cf[e0 * CB + i];
-    // per-face constants, once per face (read straight from global memory)
-    for (int i = tid; i < ne * 4; i += kThreads) {
-      const int e = i >> 2, f = i & 3;
-      face_record<PHYS>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
-    }
+#pragma unroll
+  for (int t = 0; t < CIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i < ne * CB) s_cf[i] = cv[t];
   }
   __syncthreads();
+  // per-face constants, once per face
+  if (rec_e < ne) face_record<PHYS>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
 
   // ---- phase B: volume combinations and upwind penalties -----------------
   for (int i = tid; i < ne * NP; i += kThreads) {
@@ -166,15 +249,16 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
       }
     }
   }
+  __syncthreads();  // face records
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kThreads;
     if (i >= ne * NFN) continue;
     const int e = i / NFN, fn = i - e * NFN;
-    const int f = fn / NFP, j = fn - f * NFP;
+    const int f = fn / NFP;
     const float* rec = s_face + (e * 4 + f) * FW;
     const float nrm[3] = {rec[0], rec[1], rec[2]};
-    const int vn = a.fmask[f * NFP + j];
+    const int vn = vnode[t];
     const float* qe = s_q + e * NF * NP;
     const bool wall = (word[t] & 7) == 7;
     float* lf = s_lift + e * NL * NFN + fn;
@@ -348,7 +432,7 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
     // own traces of the updated fields at every face this node lies on
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      const int fj = a.nodeface[n * 3 + s];
+      const int fj = nfs[t][s];
       if (fj < 0) break;
       const int f = fj / NFP, j = fj - f * NFP;
       const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
