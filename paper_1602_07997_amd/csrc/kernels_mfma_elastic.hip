@@ -127,16 +127,89 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   const bool step = (a.mode == kStepMode);
   const ERegion<N, PREC> reg{s_B};
 
-  // ---- A1 -------------------------------------------------------------------
-  for (int i = tid; i < ne * 9; i += kEThreads) s_g[i] = a.geo[e0 * 9 + i];
-  for (int i = tid; i < ne * CB; i += kEThreads) s_cf[i] = a.cf[e0 * CB + i];
-  for (int i = tid; i < ne * 4; i += kEThreads) {
-    const int e = i >> 2, f = i & 3;
-    face_record<1>(a.geo + (e0 + e) * 9, a.cf + (e0 + e) * CB, f, a.conn[(e0 + e) * 4 + f], s_face + i * FW);
+  // ---- A1: every global read indexed by the tile alone, issued together ----
+  // Loads are unconditional at clamped (in-range) addresses and unused values
+  // are dropped by selects, so that none waits behind a branch or behind
+  // another item's load.
+  constexpr int GIT = (E * 9 + kEThreads - 1) / kEThreads;
+  constexpr int CIT = (E * CB + kEThreads - 1) / kEThreads;
+  constexpr int PIT = (6 * NFP + kEThreads - 1) / kEThreads;
+  static_assert(6 * NFP <= NW * SCR, "the permutation table borrows the transpose scratch");
+  static_assert(E * 4 <= kEThreads, "one face record per thread");
+  int* s_perm = reinterpret_cast<int*>(s_scr);  // free until the epilogue
+  float gv[GIT], cv[CIT];
+  int pv[PIT];
+#pragma unroll
+  for (int t = 0; t < GIT; ++t) {
+    const int i = tid + t * kEThreads;
+    gv[t] = a.geo[e0 * 9 + (i < ne * 9 ? i : 0)];
+  }
+#pragma unroll
+  for (int t = 0; t < CIT; ++t) {
+    const int i = tid + t * kEThreads;
+    cv[t] = a.cf[e0 * CB + (i < ne * CB ? i : 0)];
+  }
+#pragma unroll
+  for (int t = 0; t < PIT; ++t) {
+    const int i = tid + t * kEThreads;
+    pv[t] = a.perm[i < 6 * NFP ? i : 0];
+  }
+  const int rec_e = tid >> 2, rec_f = tid & 3;
+  const int rec_word = a.conn[(e0 + (rec_e < ne ? rec_e : 0)) * 4 + rec_f];
+  // face-slot items i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP:
+  // connectivity word and own trace (v and s n of the fields read this step)
+  int cw[FIT];
+  float ot[FIT][NT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kEThreads;
+    const int e = i / KL, slot = i - e * KL;
+    const bool ok = e < ne && slot < 4 * NFP;
+    const int ec = ok ? e : 0, sc = ok ? slot : 0;
+    const int f = sc / NFP, j = sc - f * NFP;
+    cw[t] = a.conn[(e0 + ec) * 4 + f];
+    const float* own = a.qf_in + ((e0 + ec) * 4 + f) * NT * NFP + j;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) ot[t][c] = own[c * NFP];
+  }
+#pragma unroll
+  for (int t = 0; t < GIT; ++t) {
+    const int i = tid + t * kEThreads;
+    if (i < ne * 9) s_g[i] = gv[t];
+  }
+#pragma unroll
+  for (int t = 0; t < CIT; ++t) {
+    const int i = tid + t * kEThreads;
+    if (i < ne * CB) s_cf[i] = cv[t];
+  }
+#pragma unroll
+  for (int t = 0; t < PIT; ++t) {
+    const int i = tid + t * kEThreads;
+    if (i < 6 * NFP) s_perm[i] = pv[t];
   }
   __syncthreads();
 
-  // ---- A2: LIFT operands at every face slot ---------------------------------
+  // ---- A2: neighbour traces; face records; LIFT operands at every face slot --
+  float nt[FIT][NT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kEThreads;
+    const int e = i / KL, slot = i - e * KL;
+    const bool ok = e < ne && slot < 4 * NFP;
+    const int ec = ok ? e : 0, sc = ok ? slot : 0;
+    const int f = sc / NFP, j = sc - f * NFP;
+    const int w = cw[t];
+    const bool wall = (w & 7) == 7;
+    // a wall reads its own trace (in range, value unused)
+    const int64_t kn = wall ? e0 + ec : static_cast<int64_t>(w >> 5);
+    const int fnb = wall ? f : (w >> 3) & 3;
+    const int jn = wall ? j : s_perm[(w & 7) * NFP + j];
+    const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) nt[t][c] = tr[c * NFP];
+  }
+  if (rec_e < ne) face_record<1>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
+  __syncthreads();
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kEThreads;
@@ -146,37 +219,20 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 #pragma unroll
     for (int c = 0; c < 9; ++c) b[c] = 0.0f;
     if (e < ne && slot < 4 * NFP) {
-      const int f = slot / NFP, j = slot - f * NFP;
+      const int f = slot / NFP;
       const float* rec = s_face + (e * 4 + f) * FW;
       const float n0 = rec[0], n1 = rec[1], n2 = rec[2];
       const float nn[3] = {n0, n1, n2};
-      const int vn = a.fmask[f * NFP + j];
-      const float* qe = a.q_in + (e0 + e) * NF * NP;
+      const bool wall = (cw[t] & 7) == 7;
       float vM[3], tM[3], vP[3], tP[3];
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) vM[ii] = qe[ii * NP + vn];
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii)
-        tM[ii] = qe[(3 + voigt(ii, 0)) * NP + vn] * n0 + qe[(3 + voigt(ii, 1)) * NP + vn] * n1 +
-                 qe[(3 + voigt(ii, 2)) * NP + vn] * n2;
-      const int w = a.conn[(e0 + e) * 4 + f];
-      if ((w & 7) == 7) {
-        // traction-free wall: mirror state v+ = v-, (s n)+ = -(s n)-
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          vP[ii] = vM[ii];
-          tP[ii] = -tM[ii];
-        }
-      } else {
-        const int64_t kn = static_cast<int64_t>(w >> 5);
-        const int fnb = (w >> 3) & 3;
-        const int jn = a.perm[(w & 7) * NFP + j];
-        const float* tr = a.qf_in + (kn * 4 + fnb) * NT * NFP + jn;
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          vP[ii] = tr[ii * NFP];
-          tP[ii] = -tr[(3 + ii) * NFP];  // the neighbour stored s n with its own normal
-        }
+      for (int ii = 0; ii < 3; ++ii) {
+        vM[ii] = ot[t][ii];
+        tM[ii] = ot[t][3 + ii];
+        // traction-free wall: mirror state v+ = v-, (s n)+ = -(s n)-;
+        // otherwise the neighbour stored s n with its own normal
+        vP[ii] = wall ? vM[ii] : nt[t][ii];
+        tP[ii] = wall ? -tM[ii] : -nt[t][3 + ii];
       }
       float jv[3], jt[3];
 #pragma unroll
@@ -253,15 +309,29 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   __syncthreads();
 
   // ---- B1: the nine fields (FP32) -------------------------------------------
+  // reads in batches of up to three node items, at clamped addresses
+  constexpr int BB = 3;
 #pragma unroll
-  for (int t = 0; t < NIT; ++t) {
-    const int i = tid + t * kEThreads;
-    if (i >= E * KP) continue;
-    const int e = i / KP, n = i - e * KP;
-    const bool ok = e < ne && n < NP;
-    const float* qe = a.q_in + (e0 + e) * NF * NP;
+  for (int t0 = 0; t0 < NIT; t0 += BB) {
+    float x[BB][9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) reg.put_f32(c, n, e, ok ? qe[c * NP + n] : 0.0f);
+    for (int u = 0; u < BB; ++u) {
+      const int i = tid + (t0 + u) * kEThreads;
+      const int e = i / KP, n = i - e * KP;
+      const bool ok = t0 + u < NIT && i < E * KP && e < ne && n < NP;
+      const float* qe = a.q_in + (e0 + (ok ? e : 0)) * NF * NP + (ok ? n : 0);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) x[u][c] = qe[c * NP];
+    }
+#pragma unroll
+    for (int u = 0; u < BB; ++u) {
+      const int i = tid + (t0 + u) * kEThreads;
+      if (t0 + u >= NIT || i >= E * KP) continue;
+      const int e = i / KP, n = i - e * KP;
+      const bool ok = e < ne && n < NP;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) reg.put_f32(c, n, e, ok ? x[u][c] : 0.0f);
+    }
   }
   __syncthreads();
 
@@ -359,33 +429,57 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
         rr[3 + v][r] = x;
       }
     }
-    // transpose, update and write field by field; lane -> (node mb*16 + nl, element nb*16 + kq + 4 it)
+    // transpose, update and write field by field; lane -> (node mb*16 + nl,
+    // element nb*16 + kq + 4 it); the fields and history are read three
+    // fields at a time, each batch issued together at clamped addresses
     const int n = mb * 16 + nl;
-    const bool use1 = step && a.c1 != 0.0f, use2 = step && a.c2 != 0.0f;
+    const int ncl = n < NP ? n : NP - 1;
+    int nfs[3] = {-1, -1, -1};
+    if (step) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) nfs[s] = a.nodeface[ncl * 3 + s];
+    }
+    const float* p1 = a.c1 != 0.0f ? a.r1 : a.q_in;  // history read only where it is used
+    const float* p2 = a.c2 != 0.0f ? a.r2 : a.q_in;
+    const float w1 = a.c1 != 0.0f ? 1.0f : 0.0f, w2 = a.c2 != 0.0f ? 1.0f : 0.0f;
     float qn[9][4];
 #pragma unroll
-    for (int c = 0; c < NF; ++c) {
+    for (int c0 = 0; c0 < NF; c0 += 3) {
+      float qo[3][4], h1[3][4], h2[3][4];
+      if (step) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) scr[nl * 17 + 4 * kq + r] = rr[c][r];
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      float rt[4];
+        for (int it = 0; it < 4; ++it) {
+          const int e = nb * 16 + kq + 4 * it;
+          const int64_t base = (e0 + (e < ne ? e : ne - 1)) * NF * NP + ncl;
 #pragma unroll
-      for (int it = 0; it < 4; ++it) rt[it] = scr[(kq + 4 * it) * 17 + nl];
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+          for (int u = 0; u < 3; ++u) {
+            qo[u][it] = a.q_in[base + (c0 + u) * NP];
+            h1[u][it] = p1[base + (c0 + u) * NP];
+            h2[u][it] = p2[base + (c0 + u) * NP];
+          }
+        }
+      }
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
-        const int e = nb * 16 + kq + 4 * it;
-        qn[c][it] = 0.0f;
-        if (e >= ne || n >= NP) continue;
-        const int64_t base = (e0 + e) * NF * NP + c * NP + n;
-        a.r_out[base] = rt[it];
-        if (!step) continue;
-        const float h1 = use1 ? a.r1[base] : 0.0f;
-        const float h2 = use2 ? a.r2[base] : 0.0f;
-        qn[c][it] = a.q_in[base] + a.c0 * rt[it] + a.c1 * h1 + a.c2 * h2;
-        a.q_out[base] = qn[c][it];
+      for (int u = 0; u < 3; ++u) {
+        const int c = c0 + u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) scr[nl * 17 + 4 * kq + r] = rr[c][r];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        float rt[4];
+#pragma unroll
+        for (int it = 0; it < 4; ++it) rt[it] = scr[(kq + 4 * it) * 17 + nl];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int e = nb * 16 + kq + 4 * it;
+          qn[c][it] = step ? qo[u][it] + a.c0 * rt[it] + a.c1 * (w1 * h1[u][it]) + a.c2 * (w2 * h2[u][it]) : 0.0f;
+          if (e >= ne || n >= NP) continue;
+          const int64_t base = (e0 + e) * NF * NP + c * NP + n;
+          a.r_out[base] = rt[it];
+          if (step) a.q_out[base] = qn[c][it];
+        }
       }
     }
     if (!step) continue;
@@ -396,7 +490,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
       const float* fr = s_face + e * 4 * FW;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
-        const int fj = a.nodeface[n * 3 + s];
+        const int fj = nfs[s];
         if (fj < 0) break;
         const int f = fj / NFP, j = fj - f * NFP;
         const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
