@@ -111,6 +111,10 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   const int lane = tid & 63, wave = tid >> 6;
   const bool step = (a.mode == kStepMode);
   const BRegion<N, PREC> breg{s_B};
+  // tile-local arrays: uniform 64-bit bases, 32-bit offsets within the tile
+  const float* tq = a.q_in + e0 * NF * NP;
+  const float* ttr = a.qf_in + e0 * 4 * NT * NFP;
+  const int32_t* tconn = a.conn + e0 * 4;
 
   // ---- A1: every global read of the tile's inputs, issued together --------
   // Each load is unconditional at a clamped, in-range address and unused
@@ -127,12 +131,12 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
     const int i = tid + t * kThreads;
-    gv[t] = a.geo[e0 * 9 + (i < ne * 9 ? i : ne * 9 - 1)];
+    gv[t] = (a.geo + e0 * 9)[i < ne * 9 ? i : ne * 9 - 1];
   }
 #pragma unroll
   for (int t = 0; t < CIT; ++t) {
     const int i = tid + t * kThreads;
-    cv[t] = a.cf[e0 * CB + (i < ne * CB ? i : ne * CB - 1)];
+    cv[t] = (a.cf + e0 * CB)[i < ne * CB ? i : ne * CB - 1];
   }
 #pragma unroll
   for (int t = 0; t < PIT; ++t) {
@@ -141,38 +145,62 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   }
   // connectivity word of this thread's face record (e, f) = (tid / 4, tid % 4)
   const int rec_e = tid >> 2, rec_f = tid & 3;
-  const int rec_word = a.conn[(e0 + (rec_e < ne ? rec_e : ne - 1)) * 4 + rec_f];
+  const int rec_word = tconn[(rec_e < ne ? rec_e : ne - 1) * 4 + rec_f];
   // face-slot items i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP:
-  // connectivity word and own trace (p, v.n of the fields read this step)
+  // connectivity word and own trace (p, v.n of the fields read this step);
+  // the own trace waits for the neighbour's round at the highest degrees
+  // (register budget)
+  constexpr bool LATE_OWN = N >= 7;
   int cw[FIT];
   float pM[FIT], vnM[FIT];
-#pragma unroll
-  for (int t = 0; t < FIT; ++t) {
+  auto load_own = [&](int t) {
     const int i = tid + t * kThreads;
     const int e = i / KL, slot = i - e * KL;
     const bool ok = e < ne && slot < 4 * NFP;
     const int ec = ok ? e : 0, sc = ok ? slot : 0;
     const int f = sc / NFP, j = sc - f * NFP;
-    cw[t] = a.conn[(e0 + ec) * 4 + f];
-    const float* own = a.qf_in + ((e0 + ec) * 4 + f) * NT * NFP + j;
+    const float* own = ttr + (ec * 4 + f) * NT * NFP + j;
     pM[t] = own[0];
     vnM[t] = own[NFP];
+  };
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = tid + t * kThreads;
+    const int e = i / KL, slot = i - e * KL;
+    const bool ok = e < ne && slot < 4 * NFP;
+    cw[t] = tconn[(ok ? e : 0) * 4 + (ok ? slot : 0) / NFP];
+    if (!LATE_OWN) load_own(t);
   }
   // node items i = e*KP + n (n < KP, so that the zero padding is written
   // too): the fields of the first NIT1 items now, the rest with the
   // neighbour traces (register budget)
-  constexpr int NIT1 = NIT < 6 ? NIT : 6;
+  constexpr int NIT1 = (PREC == 0 && N >= 7) ? NIT : (NIT < 6 ? NIT : 6);
   float qv[NIT][NF];
   auto load_node = [&](int t) {
     const int i = tid + t * kThreads;
     const int e = i / KP, n = i - e * KP;
     const bool ok = i < E * KP && e < ne && n < NP;
-    const float* qe = a.q_in + (e0 + (ok ? e : 0)) * NF * NP + (ok ? n : 0);
+    const float* qe = tq + ((ok ? e : 0) * NF * NP + (ok ? n : 0));
 #pragma unroll
     for (int c = 0; c < NF; ++c) qv[t][c] = qe[c * NP];
   };
 #pragma unroll
   for (int t = 0; t < NIT1; ++t) load_node(t);
+  // FP32 at the highest degrees (register budget): the first items' raw
+  // fields go straight into the operand region (p final, v converted to U_j
+  // after the barrier by the same thread)
+  constexpr bool RAW = PREC == 0 && N >= 7;
+  if constexpr (RAW) {
+#pragma unroll
+    for (int t = 0; t < NIT1; ++t) {
+      const int i = tid + t * kThreads;
+      if (i >= E * KP) continue;
+      const int e = i / KP, n = i - e * KP;
+      const bool ok = e < ne && n < NP;
+#pragma unroll
+      for (int c = 0; c < NF; ++c) breg.put(c, n, e, ok ? qv[t][c] : 0.0f);
+    }
+  }
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
     const int i = tid + t * kThreads;
@@ -196,8 +224,14 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   // upwind alpha at the face slots from the own and neighbour traces
   // (rigid wall: mirror state p+ = p-, v.n+ = -v.n-; Z+ = Z- there)
   float alpha[FIT];
+  constexpr int FCH = LATE_OWN ? (FIT + 1) / 2 : FIT;  // items per round (register budget)
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
+    if (LATE_OWN && t % FCH == 0) {
+      if (t > 0) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = t; u < t + FCH && u < FIT; ++u) load_own(u);
+    }
     const int i = tid + t * kThreads;
     const int e = i / KL, slot = i - e * KL;
     const bool ok = e < ne && slot < 4 * NFP;
@@ -217,22 +251,36 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     const float vp = wall ? -vnM[t] : vnP;
     alpha[t] = ok ? 0.5f * (pp - pM[t]) - ZP * 0.5f * (vp - vnM[t]) : 0.0f;
   }
+  // materialise alpha here: otherwise the compiler sinks its arithmetic to
+  // the penalty phase and keeps the four trace values per item live across
+  // the volume products
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) __asm__ volatile("" : "+v"(alpha[t]));
   if (rec_e < ne) face_record<0>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
 #pragma unroll
   for (int t = 0; t < NIT; ++t) {
     const int i = tid + t * kThreads;
     if (i >= E * KP) continue;
     const int e = i / KP, n = i - e * KP;
+    float v0, v1, v2;
+    if (RAW && t < NIT1) {  // raw fields staged before the barrier (p is in place)
+      v0 = s_B[(1 * KMAX + n) * E + swz<E>(n, e)];
+      v1 = s_B[(2 * KMAX + n) * E + swz<E>(n, e)];
+      v2 = s_B[(3 * KMAX + n) * E + swz<E>(n, e)];
+    } else {
+      v0 = qv[t][1];
+      v1 = qv[t][2];
+      v2 = qv[t][3];
+    }
     float p = 0.f, u0 = 0.f, u1 = 0.f, u2 = 0.f;
     if (e < ne && n < NP) {
       const float* G = s_g + 9 * e;
-      const float v0 = qv[t][1], v1 = qv[t][2], v2 = qv[t][3];
       p = qv[t][0];
       u0 = G[0] * v0 + G[3] * v1 + G[6] * v2;
       u1 = G[1] * v0 + G[4] * v1 + G[7] * v2;
       u2 = G[2] * v0 + G[5] * v1 + G[8] * v2;
     }
-    breg.put(0, n, e, p);
+    if (!(RAW && t < NIT1)) breg.put(0, n, e, p);
     breg.put(1, n, e, u0);
     breg.put(2, n, e, u1);
     breg.put(3, n, e, u2);
@@ -467,8 +515,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     float qn[4][4];
     int nfs[3] = {-1, -1, -1};
     if (step) {
-      const float* p1 = a.c1 != 0.0f ? a.r1 : a.q_in;  // history read only where it is used
-      const float* p2 = a.c2 != 0.0f ? a.r2 : a.q_in;
+      // history read only where it is used
+      const float* t1 = (a.c1 != 0.0f ? a.r1 : a.q_in) + e0 * NF * NP;
+      const float* t2 = (a.c2 != 0.0f ? a.r2 : a.q_in) + e0 * NF * NP;
       const float w1 = a.c1 != 0.0f ? 1.0f : 0.0f, w2 = a.c2 != 0.0f ? 1.0f : 0.0f;
 #pragma unroll
       for (int s = 0; s < 3; ++s) nfs[s] = a.nodeface[ncl * 3 + s];
@@ -478,12 +527,12 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
         for (int ih = 0; ih < 2; ++ih) {
           const int e = nb * 16 + eg + 4 * (2 * half + ih);
-          const int64_t base = (e0 + (e < ne ? e : ne - 1)) * NF * NP + ncl;
+          const int off = (e < ne ? e : ne - 1) * NF * NP + ncl;
 #pragma unroll
           for (int c = 0; c < NF; ++c) {
-            qo[c][ih] = a.q_in[base + c * NP];
-            h1[c][ih] = p1[base + c * NP];
-            h2[c][ih] = p2[base + c * NP];
+            qo[c][ih] = tq[off + c * NP];
+            h1[c][ih] = t1[off + c * NP];
+            h2[c][ih] = t2[off + c * NP];
           }
         }
 #pragma unroll
@@ -499,19 +548,19 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     for (int it = 0; it < 4; ++it) {
       const int e = nb * 16 + eg + 4 * it;
       if (e >= ne || n >= NP) continue;
-      const int64_t base = (e0 + e) * NF * NP + n;
+      const int off = e * NF * NP + n;
 #pragma unroll
-      for (int c = 0; c < NF; ++c) a.r_out[base + c * NP] = rt[c][it];
+      for (int c = 0; c < NF; ++c) (a.r_out + e0 * NF * NP)[off + c * NP] = rt[c][it];
       if (!step) continue;
 #pragma unroll
-      for (int c = 0; c < NF; ++c) a.q_out[base + c * NP] = qn[c][it];
+      for (int c = 0; c < NF; ++c) (a.q_out + e0 * NF * NP)[off + c * NP] = qn[c][it];
       const float* fr = s_face + e * 4 * FW;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const int fj = nfs[s];
         if (fj < 0) break;
         const int f = fj / NFP, j = fj - f * NFP;
-        float* tr = a.qf_out + ((e0 + e) * 4 + f) * NT * NFP + j;
+        float* tr = a.qf_out + e0 * 4 * NT * NFP + ((e * 4 + f) * NT * NFP + j);
         tr[0] = qn[0][it];
         tr[NFP] = fr[f * FW + 0] * qn[1][it] + fr[f * FW + 1] * qn[2][it] + fr[f * FW + 2] * qn[3][it];
       }
