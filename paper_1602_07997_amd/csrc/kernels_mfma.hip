@@ -44,8 +44,9 @@ namespace {
 using namespace dev;
 using namespace mfma;
 
-// k-steps of operator prefetch in the FP32 products
+// k-steps of operator prefetch in the FP32 and the 16-bit products
 constexpr int kPrefetch = 4;
+constexpr int kPrefetch16 = 1;
 
 template <int N, int PREC>
 struct MShape {
@@ -358,27 +359,58 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       constexpr int JS = MB * (KP / 16) * 64;  // fragments between D_0, D_1, D_2
       const shortx4* Dh = reinterpret_cast<const shortx4*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
       const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
-#pragma unroll 2
-      for (int kk = 0; kk < KP / 16; ++kk) {
-        const int off = ((kk * 4 + kq) * E + col) * 4;
-        Frag16 bp, b0, b1, b2;
-        bp.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
-        bp.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
-        b0.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
-        b0.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
-        b1.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
-        b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
-        b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
-        b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
-        const Frag16 a0{Dh[kk * 64], Dl[kk * 64]};
-        const Frag16 a1{Dh[JS + kk * 64], Dl[JS + kk * 64]};
-        const Frag16 a2{Dh[2 * JS + kk * 64], Dl[2 * JS + kk * 64]};
-        T0[q] = mfma_split<PREC>(a0, bp, T0[q]);
-        T1[q] = mfma_split<PREC>(a1, bp, T1[q]);
-        T2[q] = mfma_split<PREC>(a2, bp, T2[q]);
-        DV[q] = mfma_split<PREC>(a0, b0, DV[q]);
-        DV[q] = mfma_split<PREC>(a1, b1, DV[q]);
-        DV[q] = mfma_split<PREC>(a2, b2, DV[q]);
+      // operator fragments through two register sets, as in the FP32 path
+      constexpr int NK = KP / 16, PD = NK < kPrefetch16 ? NK : kPrefetch16;
+      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
+      Frag16 ra[PD][3], rb[PD][3];
+      auto load = [&](Frag16 (&r)[PD][3], int g) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          const int kk = g * PD + i < NK ? g * PD + i : NK - 1;  // clamped; the extra reads are unused
+#pragma unroll
+          for (int j = 0; j < 3; ++j) r[i][j] = Frag16{Dh[j * JS + kk * 64], Dl[j * JS + kk * 64]};
+        }
+      };
+      auto compute = [&](const Frag16 (&r)[PD][3], int g, int cnt) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int kk = g * PD + i;
+          const int off = ((kk * 4 + kq) * E + col) * 4;
+          Frag16 bp, b0, b1, b2;
+          bp.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
+          bp.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
+          b0.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
+          b0.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
+          b1.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
+          b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
+          b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
+          b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
+          T0[q] = mfma_split<PREC>(r[i][0], bp, T0[q]);
+          T1[q] = mfma_split<PREC>(r[i][1], bp, T1[q]);
+          T2[q] = mfma_split<PREC>(r[i][2], bp, T2[q]);
+          DV[q] = mfma_split<PREC>(r[i][0], b0, DV[q]);
+          DV[q] = mfma_split<PREC>(r[i][1], b1, DV[q]);
+          DV[q] = mfma_split<PREC>(r[i][2], b2, DV[q]);
+        }
+      };
+      load(ra, 0);
+#pragma unroll 1
+      for (int g = 0; g + 2 < NGT; g += 2) {
+        load(rb, g + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, g, PD);
+        load(ra, g + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(rb, g + 1, PD);
+      }
+      if constexpr (NGT % 2 == 1) {
+        compute(ra, NGT - 1, LAST);
+      } else {
+        load(rb, NGT - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, NGT - 2, PD);
+        compute(rb, NGT - 1, LAST);
       }
     }
   }
@@ -461,23 +493,53 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       constexpr int LO = 4 * KMAX * E;
       const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
-#pragma unroll 2
-      for (int kk = 0; kk < KL / 16; ++kk) {
-        const int off = ((kk * 4 + kq) * E + col) * 4;
-        const Frag16 al{Lh[kk * 64], Ll[kk * 64]};
-        Frag16 b;
-        b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
-        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
-        lp = mfma_split<PREC>(al, b, lp);
-        b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
-        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
-        l0 = mfma_split<PREC>(al, b, l0);
-        b.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
-        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
-        l1 = mfma_split<PREC>(al, b, l1);
-        b.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
-        b.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
-        l2 = mfma_split<PREC>(al, b, l2);
+      constexpr int NK = KL / 16, PD = NK < 2 * kPrefetch16 ? NK : 2 * kPrefetch16;
+      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
+      Frag16 ra[PD], rb[PD];
+      auto load = [&](Frag16 (&r)[PD], int g) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          const int kk = g * PD + i < NK ? g * PD + i : NK - 1;
+          r[i] = Frag16{Lh[kk * 64], Ll[kk * 64]};
+        }
+      };
+      auto compute = [&](const Frag16 (&r)[PD], int g, int cnt) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int off = (((g * PD + i) * 4 + kq) * E + col) * 4;
+          Frag16 b;
+          b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
+          lp = mfma_split<PREC>(r[i], b, lp);
+          b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
+          l0 = mfma_split<PREC>(r[i], b, l0);
+          b.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
+          l1 = mfma_split<PREC>(r[i], b, l1);
+          b.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
+          l2 = mfma_split<PREC>(r[i], b, l2);
+        }
+      };
+      load(ra, 0);
+#pragma unroll 1
+      for (int g = 0; g + 2 < NGT; g += 2) {
+        load(rb, g + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, g, PD);
+        load(ra, g + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(rb, g + 1, PD);
+      }
+      if constexpr (NGT % 2 == 1) {
+        compute(ra, NGT - 1, LAST);
+      } else {
+        load(rb, NGT - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra, NGT - 2, PD);
+        compute(rb, NGT - 1, LAST);
       }
     }
     const int n = mb * 16 + nl;
