@@ -306,18 +306,17 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       // of the current group (the scheduling barrier keeps them there), so
       // their latency overlaps PD k-steps of products.
       constexpr int NK = KP / 4, PD = NK < kPrefetch ? NK : kPrefetch;
-      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
-      float ra[PD][3], rb[PD][3];
-      auto load = [&](float (&r)[PD][3], int g) {
+      using R = Ring<float, PD, 3>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           const int kk = g * PD + i < NK ? g * PD + i : NK - 1;  // clamped; the extra reads are unused
-          r[i][0] = Dp[kk * 64];
-          r[i][1] = Dp[JS + kk * 64];
-          r[i][2] = Dp[2 * JS + kk * 64];
+          r.v[i][0] = Dp[kk * 64];
+          r.v[i][1] = Dp[JS + kk * 64];
+          r.v[i][2] = Dp[2 * JS + kk * 64];
         }
       };
-      auto compute = [&](const float (&r)[PD][3], int g, int cnt) {
+      auto compute = [&](const R& r, int g, int cnt) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
@@ -327,32 +326,15 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
           const float b0 = s_B[(1 * KMAX + k) * E + c];
           const float b1 = s_B[(2 * KMAX + k) * E + c];
           const float b2 = s_B[(3 * KMAX + k) * E + c];
-          T0[q] = mfma_f32(r[i][0], bp, T0[q]);
-          T1[q] = mfma_f32(r[i][1], bp, T1[q]);
-          T2[q] = mfma_f32(r[i][2], bp, T2[q]);
-          DV[q] = mfma_f32(r[i][0], b0, DV[q]);
-          DV[q] = mfma_f32(r[i][1], b1, DV[q]);
-          DV[q] = mfma_f32(r[i][2], b2, DV[q]);
+          T0[q] = mfma_f32(r.v[i][0], bp, T0[q]);
+          T1[q] = mfma_f32(r.v[i][1], bp, T1[q]);
+          T2[q] = mfma_f32(r.v[i][2], bp, T2[q]);
+          DV[q] = mfma_f32(r.v[i][0], b0, DV[q]);
+          DV[q] = mfma_f32(r.v[i][1], b1, DV[q]);
+          DV[q] = mfma_f32(r.v[i][2], b2, DV[q]);
         }
       };
-      load(ra, 0);
-#pragma unroll 1
-      for (int g = 0; g + 2 < NGT; g += 2) {
-        load(rb, g + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, g, PD);
-        load(ra, g + 2);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(rb, g + 1, PD);
-      }
-      if constexpr (NGT % 2 == 1) {
-        compute(ra, NGT - 1, LAST);
-      } else {
-        load(rb, NGT - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, NGT - 2, PD);
-        compute(rb, NGT - 1, LAST);
-      }
+      pipelined<NK, PD, R>(load, compute);
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
       constexpr int LO = 4 * KMAX * E;
@@ -361,17 +343,16 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
       // operator fragments through two register sets, as in the FP32 path
       constexpr int NK = KP / 16, PD = NK < kPrefetch16 ? NK : kPrefetch16;
-      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
-      Frag16 ra[PD][3], rb[PD][3];
-      auto load = [&](Frag16 (&r)[PD][3], int g) {
+      using R = Ring<Frag16, PD, 3>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           const int kk = g * PD + i < NK ? g * PD + i : NK - 1;  // clamped; the extra reads are unused
 #pragma unroll
-          for (int j = 0; j < 3; ++j) r[i][j] = Frag16{Dh[j * JS + kk * 64], Dl[j * JS + kk * 64]};
+          for (int j = 0; j < 3; ++j) r.v[i][j] = Frag16{Dh[j * JS + kk * 64], Dl[j * JS + kk * 64]};
         }
       };
-      auto compute = [&](const Frag16 (&r)[PD][3], int g, int cnt) {
+      auto compute = [&](const R& r, int g, int cnt) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
@@ -386,32 +367,15 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
           b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
           b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
           b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
-          T0[q] = mfma_split<PREC>(r[i][0], bp, T0[q]);
-          T1[q] = mfma_split<PREC>(r[i][1], bp, T1[q]);
-          T2[q] = mfma_split<PREC>(r[i][2], bp, T2[q]);
-          DV[q] = mfma_split<PREC>(r[i][0], b0, DV[q]);
-          DV[q] = mfma_split<PREC>(r[i][1], b1, DV[q]);
-          DV[q] = mfma_split<PREC>(r[i][2], b2, DV[q]);
+          T0[q] = mfma_split<PREC>(r.v[i][0], bp, T0[q]);
+          T1[q] = mfma_split<PREC>(r.v[i][1], bp, T1[q]);
+          T2[q] = mfma_split<PREC>(r.v[i][2], bp, T2[q]);
+          DV[q] = mfma_split<PREC>(r.v[i][0], b0, DV[q]);
+          DV[q] = mfma_split<PREC>(r.v[i][1], b1, DV[q]);
+          DV[q] = mfma_split<PREC>(r.v[i][2], b2, DV[q]);
         }
       };
-      load(ra, 0);
-#pragma unroll 1
-      for (int g = 0; g + 2 < NGT; g += 2) {
-        load(rb, g + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, g, PD);
-        load(ra, g + 2);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(rb, g + 1, PD);
-      }
-      if constexpr (NGT % 2 == 1) {
-        compute(ra, NGT - 1, LAST);
-      } else {
-        load(rb, NGT - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, NGT - 2, PD);
-        compute(rb, NGT - 1, LAST);
-      }
+      pipelined<NK, PD, R>(load, compute);
     }
   }
   __syncthreads();
@@ -452,58 +416,39 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     if constexpr (PREC == 0) {
       const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
       constexpr int NK = KL / 4, PD = NK < 2 * kPrefetch ? NK : 2 * kPrefetch;
-      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
-      float ra[PD], rb[PD];
-      auto load = [&](float (&r)[PD], int g) {
+      using R = Ring<float, PD, 1>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
-        for (int i = 0; i < PD; ++i) r[i] = Lp[(g * PD + i < NK ? g * PD + i : NK - 1) * 64];
+        for (int i = 0; i < PD; ++i) r.v[i][0] = Lp[(g * PD + i < NK ? g * PD + i : NK - 1) * 64];
       };
-      auto compute = [&](const float (&r)[PD], int g, int cnt) {
+      auto compute = [&](const R& r, int g, int cnt) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
           const int k = (g * PD + i) * 4 + kq;
           const int c = swz<E>(k, col);
-          lp = mfma_f32(r[i], s_B[(0 * KMAX + k) * E + c], lp);
-          l0 = mfma_f32(r[i], s_B[(1 * KMAX + k) * E + c], l0);
-          l1 = mfma_f32(r[i], s_B[(2 * KMAX + k) * E + c], l1);
-          l2 = mfma_f32(r[i], s_B[(3 * KMAX + k) * E + c], l2);
+          lp = mfma_f32(r.v[i][0], s_B[(0 * KMAX + k) * E + c], lp);
+          l0 = mfma_f32(r.v[i][0], s_B[(1 * KMAX + k) * E + c], l0);
+          l1 = mfma_f32(r.v[i][0], s_B[(2 * KMAX + k) * E + c], l1);
+          l2 = mfma_f32(r.v[i][0], s_B[(3 * KMAX + k) * E + c], l2);
         }
       };
-      load(ra, 0);
-#pragma unroll 1
-      for (int g = 0; g + 2 < NGT; g += 2) {
-        load(rb, g + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, g, PD);
-        load(ra, g + 2);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(rb, g + 1, PD);
-      }
-      if constexpr (NGT % 2 == 1) {
-        compute(ra, NGT - 1, LAST);
-      } else {
-        load(rb, NGT - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, NGT - 2, PD);
-        compute(rb, NGT - 1, LAST);
-      }
+      pipelined<NK, PD, R>(load, compute);
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
       constexpr int LO = 4 * KMAX * E;
       const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       constexpr int NK = KL / 16, PD = NK < 2 * kPrefetch16 ? NK : 2 * kPrefetch16;
-      constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
-      Frag16 ra[PD], rb[PD];
-      auto load = [&](Frag16 (&r)[PD], int g) {
+      using R = Ring<Frag16, PD, 1>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           const int kk = g * PD + i < NK ? g * PD + i : NK - 1;
-          r[i] = Frag16{Lh[kk * 64], Ll[kk * 64]};
+          r.v[i][0] = Frag16{Lh[kk * 64], Ll[kk * 64]};
         }
       };
-      auto compute = [&](const Frag16 (&r)[PD], int g, int cnt) {
+      auto compute = [&](const R& r, int g, int cnt) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
@@ -511,36 +456,19 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
           Frag16 b;
           b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
           b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
-          lp = mfma_split<PREC>(r[i], b, lp);
+          lp = mfma_split<PREC>(r.v[i][0], b, lp);
           b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
           b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
-          l0 = mfma_split<PREC>(r[i], b, l0);
+          l0 = mfma_split<PREC>(r.v[i][0], b, l0);
           b.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
           b.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
-          l1 = mfma_split<PREC>(r[i], b, l1);
+          l1 = mfma_split<PREC>(r.v[i][0], b, l1);
           b.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
           b.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
-          l2 = mfma_split<PREC>(r[i], b, l2);
+          l2 = mfma_split<PREC>(r.v[i][0], b, l2);
         }
       };
-      load(ra, 0);
-#pragma unroll 1
-      for (int g = 0; g + 2 < NGT; g += 2) {
-        load(rb, g + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, g, PD);
-        load(ra, g + 2);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(rb, g + 1, PD);
-      }
-      if constexpr (NGT % 2 == 1) {
-        compute(ra, NGT - 1, LAST);
-      } else {
-        load(rb, NGT - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(ra, NGT - 2, PD);
-        compute(rb, NGT - 1, LAST);
-      }
+      pipelined<NK, PD, R>(load, compute);
     }
     const int n = mb * 16 + nl;
     const int ncl = n < NP ? n : NP - 1;

@@ -279,31 +279,54 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     if (p >= S::PAIRS) continue;
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + nl;
+    // operator fragments stream through two register sets (pipelined)
     if constexpr (PREC == 0) {
       const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
-#pragma unroll 2
-      for (int kk = 0; kk < KL / 4; ++kk) {
-        const int k = kk * 4 + kq;
-        const float al = Lp[kk * 64];
+      constexpr int NK = KL / 4, PD = NK < 8 ? NK : 8;
+      using R = Ring<float, PD, 1>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) LL[q][c] = mfma_f32(al, s_B[reg.f32_word(c, k, col)], LL[q][c]);
-      }
+        for (int i = 0; i < PD; ++i) r.v[i][0] = Lp[(g * PD + i < NK ? g * PD + i : NK - 1) * 64];
+      };
+      auto compute = [&](const R& r, int g, int cnt) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int k = (g * PD + i) * 4 + kq;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) LL[q][c] = mfma_f32(r.v[i][0], s_B[reg.f32_word(c, k, col)], LL[q][c]);
+        }
+      };
+      pipelined<NK, PD, R>(load, compute);
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
       constexpr int LO = S::NSET * KMAX * E;
       const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
-      for (int kk = 0; kk < KL / 16; ++kk) {
-        const int off = ((kk * 4 + kq) * E + col) * 4;
-        const Frag16 al{Lh[kk * 64], Ll[kk * 64]};
+      constexpr int NK = KL / 16, PD = NK < 2 ? NK : 2;
+      using R = Ring<Frag16, PD, 1>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          Frag16 b;
-          b.hi = *reinterpret_cast<const shortx4*>(u + c * KMAX * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + c * KMAX * E + off);
-          LL[q][c] = mfma_split<PREC>(al, b, LL[q][c]);
+        for (int i = 0; i < PD; ++i) {
+          const int kk = g * PD + i < NK ? g * PD + i : NK - 1;
+          r.v[i][0] = Frag16{Lh[kk * 64], Ll[kk * 64]};
         }
-      }
+      };
+      auto compute = [&](const R& r, int g, int cnt) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int off = (((g * PD + i) * 4 + kq) * E + col) * 4;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            Frag16 b;
+            b.hi = *reinterpret_cast<const shortx4*>(u + c * KMAX * E + off);
+            b.lo = *reinterpret_cast<const shortx4*>(u + LO + c * KMAX * E + off);
+            LL[q][c] = mfma_split<PREC>(r.v[i][0], b, LL[q][c]);
+          }
+        }
+      };
+      pipelined<NK, PD, R>(load, compute);
     }
   }
   __syncthreads();
@@ -357,35 +380,52 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     if constexpr (PREC == 0) {
       const float* Dp = a.Dpack + static_cast<int64_t>(mb) * (KP / 4) * 64 + lane;
       constexpr int JS = MB * (KP / 4) * 64;
-#pragma unroll 2
-      for (int kk = 0; kk < KP / 4; ++kk) {
-        const int k = kk * 4 + kq;
-        float x[9];
+      constexpr int NK = KP / 4, PD = NK < 4 ? NK : 4;
+      using R = Ring<float, PD, 3>;
+      auto load = [&](R& r, int g) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) x[c] = s_B[reg.f32_word(c, k, col)];
-        const float d[3] = {Dp[kk * 64], Dp[JS + kk * 64], Dp[2 * JS + kk * 64]};
+        for (int i = 0; i < PD; ++i) {
+          const int kk = g * PD + i < NK ? g * PD + i : NK - 1;
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          const float si0 = x[3 + voigt(ii, 0)], si1 = x[3 + voigt(ii, 1)], si2 = x[3 + voigt(ii, 2)];
+          for (int l = 0; l < 3; ++l) r.v[i][l] = Dp[l * JS + kk * 64];
+        }
+      };
+      auto compute = [&](const R& r, int g, int cnt) {
 #pragma unroll
-          for (int l = 0; l < 3; ++l) {
-            Dv[ii][l] = mfma_f32(d[l], x[ii], Dv[ii][l]);
-            const float ax = G[0 * 3 + l] * si0 + G[1 * 3 + l] * si1 + G[2 * 3 + l] * si2;
-            dS[ii] = mfma_f32(d[l], ax, dS[ii]);
+        for (int i = 0; i < PD; ++i) {
+          if (i >= cnt) break;
+          const int k = (g * PD + i) * 4 + kq;
+          float x[9];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) x[c] = s_B[reg.f32_word(c, k, col)];
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) {
+            const float si0 = x[3 + voigt(ii, 0)], si1 = x[3 + voigt(ii, 1)], si2 = x[3 + voigt(ii, 2)];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+              Dv[ii][l] = mfma_f32(r.v[i][l], x[ii], Dv[ii][l]);
+              const float ax = G[0 * 3 + l] * si0 + G[1 * 3 + l] * si1 + G[2 * 3 + l] * si2;
+              dS[ii] = mfma_f32(r.v[i][l], ax, dS[ii]);
+            }
           }
         }
-      }
+      };
+      pipelined<NK, PD, R>(load, compute);
     } else {
       constexpr int JS = MB * (KP / 16) * 64;
       const shortx4* Dh = reinterpret_cast<const shortx4*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
       const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
-      for (int kk = 0; kk < KP / 16; ++kk) {
+      constexpr int NK = KP / 16, PD = 1;
+      using R = Ring<Frag16, PD, 3>;
+      auto load = [&](R& r, int g) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) r.v[0][l] = Frag16{Dh[l * JS + g * 64], Dl[l * JS + g * 64]};
+      };
+      auto compute = [&](const R& r, int kk, int) {
         float4 x[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) x[c] = *reinterpret_cast<const float4*>(s_B + reg.f32_word(c, kk * 16 + 4 * kq, col));
-        Frag16 d[3];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) d[l] = Frag16{Dh[l * JS + kk * 64], Dl[l * JS + kk * 64]};
+        const Frag16* d = r.v[0];
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
           const Frag16 vb = split4<PREC>(x[ii]);
@@ -402,7 +442,8 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
             dS[ii] = mfma_split<PREC>(d[l], split4<PREC>(ax), dS[ii]);
           }
         }
-      }
+      };
+      pipelined<NK, PD, R>(load, compute);
     }
     // right-hand sides in the accumulator layout (rows 4 kq + r, column nl)
     const float* cf = s_cf + ec * CB;

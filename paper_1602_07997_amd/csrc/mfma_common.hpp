@@ -74,6 +74,41 @@ __device__ __forceinline__ floatx4 mfma_split(const Frag16& a, const Frag16& b, 
   return mfma16<PREC>(a.hi, b.hi, c);
 }
 
+// Register sets of a software-pipelined operator stream.
+template <class T, int A, int B>
+struct Ring {
+  T v[A][B];
+};
+
+// Software pipeline over NK k-steps in groups of PD: the operator fragments
+// of the next group are read into the other of two register sets before the
+// products of the current group (the scheduling barriers keep that order),
+// so that their latency overlaps PD k-steps of products.  load(r, g) fills r
+// with group g (clamping past the end), compute(r, g, cnt) runs the first cnt
+// k-steps of group g.
+template <int NK, int PD, class R, class Load, class Compute>
+__device__ __forceinline__ void pipelined(Load&& load, Compute&& compute) {
+  constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
+  R ra, rb;
+  load(ra, 0);
+#pragma unroll 1
+  for (int g = 0; g + 2 < NGT; g += 2) {
+    load(rb, g + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(ra, g, PD);
+    load(ra, g + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(rb, g + 1, PD);
+  }
+  if constexpr (NGT % 2 == 1) {
+    compute(ra, NGT - 1, LAST);
+  } else {
+    load(rb, NGT - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(ra, NGT - 2, PD);
+    compute(rb, NGT - 1, LAST);
+  }
+}
 
 }  // namespace mfma
 }  // namespace dgw
