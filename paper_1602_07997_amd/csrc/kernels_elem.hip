@@ -141,20 +141,11 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
   const bool step = (a.mode == kStepMode);
 
   // ---- every global load of the element --------------------------------------
+  // the element's own data first (independent of the connectivity), then the
+  // neighbour trace blocks, which wait for the connectivity word; a wall reads
+  // its own block (in range, value unused) so that no load sits in a branch
   const int4 w4 = reinterpret_cast<const int4*>(a.conn)[k];
   const int word[4] = {w4.x, w4.y, w4.z, w4.w};
-  float nbv[4][NTR];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    if ((word[f] & 7) != 7) {
-      const int64_t kn = static_cast<int64_t>(word[f] >> 5);
-      const int fnb = (word[f] >> 3) & 3;
-      load_run<NTR, AT>(a.qf_in + (kn * 4 + fnb) * NTR, nbv[f]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NTR; ++i) nbv[f][i] = 0.0f;
-    }
-  }
   float q[NQ];
   load_run<NQ, AQ>(a.q_in + k * NQ, q);
   float G[9];
@@ -171,6 +162,15 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
   if constexpr (kEarly) {
     if (use1) load_run<NQ, AQ>(a.r1 + k * NQ, h1);
     if (use2) load_run<NQ, AQ>(a.r2 + k * NQ, h2);
+  }
+
+  float nbv[4][NTR];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const bool wall = (word[f] & 7) == 7;
+    const int64_t kn = wall ? k : static_cast<int64_t>(word[f] >> 5);
+    const int fnb = wall ? f : (word[f] >> 3) & 3;
+    load_run<NTR, AT>(a.qf_in + (kn * 4 + fnb) * NTR, nbv[f]);
   }
 
   // ---- face constants and upwind penalties at the face nodes ----------------
