@@ -275,16 +275,19 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
   std::vector<float> Dpack, Lpack;
   std::vector<uint16_t> D16[2][2], L16[2][2];  // [bf16, f16][hi, lo]
   {
-    const dgw::MfmaPacking p32 = dgw::mfma_packing(order, dgw::kVariantMfma);
+    const dgw::MfmaPacking p32 = dgw::mfma_packing(physics, order, dgw::kVariantMfma);
+    const dgw::ColMap c32 = dgw::face_block_columns(Nfp, p32.KF);
     for (int j = 0; j < 3; ++j) dgw::pack_fp32(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p32.MB, p32.KP, Dpack);
-    dgw::pack_fp32(ref->lift.data(), Np, 4 * Nfp, p32.MB, p32.KL, Lpack);
+    dgw::pack_fp32(ref->lift.data(), Np, 4 * Nfp, p32.MB, p32.KL, Lpack, p32.KF > 0 ? &c32 : nullptr);
     const int vars[2] = {dgw::kVariantMfmaBf16, dgw::kVariantMfmaF16};
     for (int v = 0; v < 2; ++v) {
-      const dgw::MfmaPacking p16 = dgw::mfma_packing(order, vars[v]);
+      const dgw::MfmaPacking p16 = dgw::mfma_packing(physics, order, vars[v]);
+      const dgw::ColMap c16 = dgw::face_block_columns(Nfp, p16.KF);
       for (int j = 0; j < 3; ++j)
         dgw::pack_split16(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p16.MB, p16.KP, v == 0,
                           D16[v][0], D16[v][1]);
-      dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, v == 0, L16[v][0], L16[v][1]);
+      dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, v == 0, L16[v][0], L16[v][1],
+                        p16.KF > 0 ? &c16 : nullptr);
     }
   }
 

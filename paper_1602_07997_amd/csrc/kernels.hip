@@ -743,7 +743,7 @@ int64_t tiles_for(int physics, int N, int variant, int64_t K) {
 
 int tile_elements(int physics, int N, int variant) {
   if (!variant_supported(physics, N, variant)) return -1;
-  if (is_mfma(variant)) return physics == 1 ? mfma_elastic_tile_elements(N, variant) : mfma_packing(N, variant).E;
+  if (is_mfma(variant)) return mfma_packing(physics, N, variant).E;
   if (variant == kVariantElem) return elem_tile_elements();
 #define TE(n, p) Tile<n, p>::KT
   if (physics == 0) {

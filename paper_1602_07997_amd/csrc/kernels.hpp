@@ -26,10 +26,10 @@ struct StepArgs {
   const int32_t* perm;   // [6][NFP]
   const int32_t* nodeface;  // [NP][3] face slots f*NFP+j containing node n, -1 padded
   const float* Dpack;    // FP32 MFMA: D_j in 16x4 fragment order [3][MB][KP/4][64]
-  const float* Lpack;    // FP32 MFMA: merged LIFT [MB][KL/4][64]
+  const float* Lpack;    // FP32 MFMA: LIFT [MB][KL/4][64] (acoustic per face, elastic merged)
   const uint16_t* D16h;  // 16-bit MFMA: D_j split hi / lo, 16x16 fragments [3][MB][KP/16][64][4]
   const uint16_t* D16l;
-  const uint16_t* L16h;  // 16-bit MFMA: merged LIFT split hi / lo [MB][KL/16][64][4]
+  const uint16_t* L16h;  // 16-bit MFMA: LIFT split hi / lo [MB][KL/16][64][4], K as in Lpack
   const uint16_t* L16l;
   float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
   int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))
@@ -55,11 +55,14 @@ bool variant_supported(int physics, int N, int variant);
 
 // Fragment packing of the MFMA variants: node blocks MB, padded volume K (KP)
 // and LIFT K (KL), k per instruction KS, elements per tile E.
+// KF > 0: the LIFT is packed per face, face f's columns at K = f*KF .. (the
+// acoustic kernel); KF = 0: merged faces, K = 4 Nfp padded (the elastic kernel).
 struct MfmaPacking {
-  int MB = 0, KP = 0, KL = 0, KS = 0, E = 0;
+  int MB = 0, KP = 0, KL = 0, KS = 0, E = 0, KF = 0;
 };
 int mfma_precision(int variant);  // 0 FP32, 1 BF16, 2 FP16, -1 not an MFMA variant
-MfmaPacking mfma_packing(int N, int variant);
+MfmaPacking mfma_packing(int physics, int N, int variant);
+MfmaPacking mfma_elastic_packing(int N, int variant);
 hipError_t launch_step_mfma(int physics, int N, int variant, const StepArgs& a, hipStream_t s);
 // Element-per-thread kernels (N = 1, 2).
 bool elem_supported(int physics, int N);

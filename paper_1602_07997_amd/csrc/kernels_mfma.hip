@@ -2,33 +2,37 @@
 //
 // The volume and LIFT products of eqs. (5)-(6) become small GEMMs with the
 // element as the column index.  For a tile of E = 16 NBLK elements:
-//   T_j = D_j p,   dv = sum_j D_j U_j  (U_j = sum_i g_ij v_i)    K = Np
-//   lp  = L Pp,    lv_i = L (Pv n_i)   (L the merged LIFT)       K = 4 Nfp
-// with Pp = Fscale rho c^2 k_c alpha and Pv = -Fscale c k_c alpha the
-// upwind penalties of Sec. 2.1 at every face node.  Three precisions:
+//   T_j = D_j p,   dv = sum_j D_j U_j  (U_j = sum_i g_ij v_i)        K = Np
+//   lp  = sum_f L_f Pp_f,   lv_i = sum_f n_f,i L_f Pv_f              K = Nfp per face
+// with L_f the face-f block of the lift matrix (Np x Nfp), and Pp = Fscale
+// rho c^2 k_c alpha, Pv = -Fscale c k_c alpha the upwind penalties of
+// Sec. 2.1 at face f's nodes.  The face normal is constant on an affine
+// face, so it multiplies the lifted scalar Pv after the product: two lifted
+// operands instead of four.  Three precisions:
 //   PREC 0  FP32 v_mfma_f32_16x16x4_f32;
 //   PREC 1  BF16 v_mfma_f32_16x16x16_bf16 with FP32 accumulation and the
 //           split x = x_hi + x_lo of both operands, D x ~ D_hi x_hi +
 //           D_hi x_lo + D_lo x_hi (the dropped D_lo x_lo is ~2^-16 |D||x|);
 //   PREC 2  FP16 v_mfma_f32_16x16x16_f16 with the same three products
 //           (~2^-22 |D||x| dropped).
-// Operators are split and packed on the host in fragment order; the
-// right-hand operands (p, U_j, the penalties) are formed and split once per
-// tile in LDS.  Fields, r and the update stay FP32.
+// Operators are split and packed on the host in fragment order (the LIFT in
+// face blocks of KF columns); the right-hand operands (p, U_j, the
+// penalties) are formed and split once per tile in LDS.  Fields, r and the
+// update stay FP32.
 //
 // Phases of one workgroup (4 wavefronts):
-//   A1  per-element constants and face records into LDS; connectivity words
-//       and neighbour traces of the tile's face nodes into registers;
-//   A2  p and U_j of every node into LDS (B operands); upwind alpha of every
-//       face node into registers;
+//   A1  every global read indexed by the tile alone (constants, connectivity
+//       words, own traces, fields), issued together; constants into LDS;
+//   A2  neighbour traces and the upwind alpha of every face node (kept in
+//       registers); face records; p and U_j of every node into LDS;
 //   C1  volume products, one (16-node block, 16-element block) pair per
 //       wavefront in turn;
-//   B2  penalty operands into the same LDS region;
-//   C2  LIFT products, then the epilogue: the pair's right-hand sides are
-//       combined in the accumulator layout, transposed through a per-wave LDS
-//       scratch so that every global access is a run of 16 consecutive
-//       nodes, and the AB3 update, q / r writes and own-trace emission
-//       follow.
+//   B2  the two penalty operands into the same LDS region;
+//   C2  LIFT products per face, then the epilogue: the pair's right-hand
+//       sides are combined in the accumulator layout, transposed through a
+//       per-wave LDS scratch so that every global access is a run of 16
+//       consecutive nodes, and the AB3 update, q / r writes and own-trace
+//       emission follow.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -54,36 +58,34 @@ struct MShape {
   static constexpr int KS = PREC == 0 ? 4 : 16;  // k per instruction
   static constexpr int MB = (NP + 15) / 16;      // 16-row node blocks
   static constexpr int KP = rup(NP, KS);         // volume K, zero padded
-  static constexpr int KL = rup(4 * NFP, KS);    // LIFT K (merged faces), zero padded
-  static constexpr int KMAX = KP > KL ? KP : KL;
+  static constexpr int KF = rup(NFP, KS);        // LIFT K of one face, zero padded
+  static constexpr int KL = 4 * KF;              // LIFT K, face blocks of KF
   static constexpr int NBLK = (N <= 2) ? 4 : (N == 3 ? 2 : 1);
   static constexpr int E = 16 * NBLK;            // elements per tile
   static constexpr int PAIRS = MB * NBLK;
-  static constexpr int REGION = 4 * KMAX * E;    // 4-byte words of B operands
-  // register budget: as many waves per SIMD as the LDS footprint allows
-  // (one wavefront of each workgroup per SIMD), at most 4
-  static constexpr int LDS_BYTES = 4 * (REGION + E * 9 + E * 8 + E * 4 * 8 + 4 * 16 * 17);
-  static constexpr int BY_LDS = (160 * 1024) / LDS_BYTES;
-  static constexpr int WAVES = BY_LDS < 1 ? 1 : (BY_LDS > 4 ? 4 : BY_LDS);
+  // 4-byte words of B operands: four volume sets of KP rows, then (reused)
+  // two penalty sets of KL rows
+  static constexpr int REGION = (4 * KP > 2 * KL ? 4 * KP : 2 * KL) * E;
 };
 
-// B operand region: set s (0..3), row k, column e.
-//   FP32:   word s*KMAX*E + k*E + swz(k, e)
-//   16-bit: hi at unit s*KMAX*E + ((k/4)*E + e)*4 + k%4, lo 4*KMAX*E units later
-template <int N, int PREC>
+// B operand region, sets of STRIDE rows (KP for the volume operands, KL for
+// the penalties): set s, row k, column e.
+//   FP32:   word (s*STRIDE + k)*E + swz(k, e)
+//   16-bit: hi at unit s*STRIDE*E + ((k/4)*E + e)*4 + k%4, lo REGION units later
+template <int N, int PREC, int STRIDE>
 struct BRegion {
   using S = MShape<N, PREC>;
   float* w;
   __device__ __forceinline__ void put(int s, int k, int e, float x) const {
     if constexpr (PREC == 0) {
-      w[(s * S::KMAX + k) * S::E + swz<S::E>(k, e)] = x;
+      w[(s * STRIDE + k) * S::E + swz<S::E>(k, e)] = x;
     } else {
       uint16_t* u = reinterpret_cast<uint16_t*>(w);
       uint16_t hi, lo;
       split16<PREC>(x, hi, lo);
-      const int idx = s * S::KMAX * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+      const int idx = s * STRIDE * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
       u[idx] = hi;
-      u[4 * S::KMAX * S::E + idx] = lo;
+      u[S::REGION + idx] = lo;
     }
   }
 };
@@ -91,7 +93,7 @@ struct BRegion {
 template <int N, int PREC>
 __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) {
   using S = MShape<N, PREC>;
-  constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KMAX = S::KMAX, E = S::E;
+  constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
   constexpr int NF = 4, NT = 2, CB = 8;
   constexpr int FW = FaceRec<0>::W;
   constexpr int NIT = (E * KP + kThreads - 1) / kThreads;  // node items (incl. padding) per thread
@@ -111,7 +113,8 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const bool step = (a.mode == kStepMode);
-  const BRegion<N, PREC> breg{s_B};
+  const BRegion<N, PREC, KP> breg{s_B};   // volume operands
+  const BRegion<N, PREC, KL> lreg{s_B};   // penalty operands (after the volume products)
   // tile-local arrays: uniform 64-bit bases, 32-bit offsets within the tile
   const float* tq = a.q_in + e0 * NF * NP;
   const float* ttr = a.qf_in + e0 * 4 * NT * NFP;
@@ -147,7 +150,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   // connectivity word of this thread's face record (e, f) = (tid / 4, tid % 4)
   const int rec_e = tid >> 2, rec_f = tid & 3;
   const int rec_word = tconn[(rec_e < ne ? rec_e : ne - 1) * 4 + rec_f];
-  // face-slot items i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP:
+  // face-slot items i = e*KL + slot, slot = f*KF + j, a face node while j < NFP:
   // connectivity word and own trace (p, v.n of the fields read this step);
   // the own trace waits for the neighbour's round at the highest degrees
   // (register budget)
@@ -157,9 +160,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   auto load_own = [&](int t) {
     const int i = tid + t * kThreads;
     const int e = i / KL, slot = i - e * KL;
-    const bool ok = e < ne && slot < 4 * NFP;
-    const int ec = ok ? e : 0, sc = ok ? slot : 0;
-    const int f = sc / NFP, j = sc - f * NFP;
+    const int fs = slot / KF, js = slot - fs * KF;
+    const bool ok = e < ne && js < NFP;
+    const int ec = ok ? e : 0, f = ok ? fs : 0, j = ok ? js : 0;
     const float* own = ttr + (ec * 4 + f) * NT * NFP + j;
     pM[t] = own[0];
     vnM[t] = own[NFP];
@@ -168,8 +171,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kThreads;
     const int e = i / KL, slot = i - e * KL;
-    const bool ok = e < ne && slot < 4 * NFP;
-    cw[t] = tconn[(ok ? e : 0) * 4 + (ok ? slot : 0) / NFP];
+    const int fs = slot / KF;
+    const bool ok = e < ne && slot - fs * KF < NFP;
+    cw[t] = tconn[(ok ? e : 0) * 4 + (ok ? fs : 0)];
     if (!LATE_OWN) load_own(t);
   }
   // node items i = e*KP + n (n < KP, so that the zero padding is written
@@ -235,9 +239,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     }
     const int i = tid + t * kThreads;
     const int e = i / KL, slot = i - e * KL;
-    const bool ok = e < ne && slot < 4 * NFP;
-    const int ec = ok ? e : 0, sc = ok ? slot : 0;
-    const int f = sc / NFP, j = sc - f * NFP;
+    const int fs = slot / KF, js = slot - fs * KF;
+    const bool ok = e < ne && js < NFP;
+    const int ec = ok ? e : 0, f = ok ? fs : 0, j = ok ? js : 0;
     const int w = cw[t];
     const bool wall = (w & 7) == 7;
     // a wall reads its own trace (in range, value unused)
@@ -265,9 +269,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     const int e = i / KP, n = i - e * KP;
     float v0, v1, v2;
     if (RAW && t < NIT1) {  // raw fields staged before the barrier (p is in place)
-      v0 = s_B[(1 * KMAX + n) * E + swz<E>(n, e)];
-      v1 = s_B[(2 * KMAX + n) * E + swz<E>(n, e)];
-      v2 = s_B[(3 * KMAX + n) * E + swz<E>(n, e)];
+      v0 = s_B[(1 * KP + n) * E + swz<E>(n, e)];
+      v1 = s_B[(2 * KP + n) * E + swz<E>(n, e)];
+      v2 = s_B[(3 * KP + n) * E + swz<E>(n, e)];
     } else {
       v0 = qv[t][1];
       v1 = qv[t][2];
@@ -322,10 +326,10 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
           if (i >= cnt) break;
           const int k = (g * PD + i) * 4 + kq;
           const int c = swz<E>(k, col);
-          const float bp = s_B[(0 * KMAX + k) * E + c];
-          const float b0 = s_B[(1 * KMAX + k) * E + c];
-          const float b1 = s_B[(2 * KMAX + k) * E + c];
-          const float b2 = s_B[(3 * KMAX + k) * E + c];
+          const float bp = s_B[(0 * KP + k) * E + c];
+          const float b0 = s_B[(1 * KP + k) * E + c];
+          const float b1 = s_B[(2 * KP + k) * E + c];
+          const float b2 = s_B[(3 * KP + k) * E + c];
           T0[q] = mfma_f32(r.v[i][0], bp, T0[q]);
           T1[q] = mfma_f32(r.v[i][1], bp, T1[q]);
           T2[q] = mfma_f32(r.v[i][2], bp, T2[q]);
@@ -337,7 +341,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       pipelined<NK, PD, R>(load, compute);
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
-      constexpr int LO = 4 * KMAX * E;
+      constexpr int LO = S::REGION;  // 16-bit units
       constexpr int JS = MB * (KP / 16) * 64;  // fragments between D_0, D_1, D_2
       const shortx4* Dh = reinterpret_cast<const shortx4*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
       const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
@@ -359,14 +363,14 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
           const int kk = g * PD + i;
           const int off = ((kk * 4 + kq) * E + col) * 4;
           Frag16 bp, b0, b1, b2;
-          bp.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
-          bp.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
-          b0.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
-          b0.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
-          b1.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
-          b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
-          b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
-          b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
+          bp.hi = *reinterpret_cast<const shortx4*>(u + 0 * KP * E + off);
+          bp.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KP * E + off);
+          b0.hi = *reinterpret_cast<const shortx4*>(u + 1 * KP * E + off);
+          b0.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KP * E + off);
+          b1.hi = *reinterpret_cast<const shortx4*>(u + 2 * KP * E + off);
+          b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KP * E + off);
+          b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KP * E + off);
+          b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KP * E + off);
           T0[q] = mfma_split<PREC>(r.v[i][0], bp, T0[q]);
           T1[q] = mfma_split<PREC>(r.v[i][1], bp, T1[q]);
           T2[q] = mfma_split<PREC>(r.v[i][2], bp, T2[q]);
@@ -386,20 +390,15 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     const int i = tid + t * kThreads;
     if (i >= E * KL) continue;
     const int e = i / KL, slot = i - e * KL;
-    float fp = 0.f, f0 = 0.f, f1 = 0.f, f2 = 0.f;
-    if (e < ne && slot < 4 * NFP) {
-      const int f = slot / NFP;
+    float fp = 0.f, fv = 0.f;
+    const int f = slot / KF;
+    if (e < ne && slot - f * KF < NFP) {
       const float* rec = s_face + (e * 4 + f) * FW;
       fp = rec[4] * alpha[t];
-      const float fv = rec[5] * alpha[t];
-      f0 = fv * rec[0];
-      f1 = fv * rec[1];
-      f2 = fv * rec[2];
+      fv = rec[5] * alpha[t];
     }
-    breg.put(0, slot, e, fp);
-    breg.put(1, slot, e, f0);
-    breg.put(2, slot, e, f1);
-    breg.put(3, slot, e, f2);
+    lreg.put(0, slot, e, fp);
+    lreg.put(1, slot, e, fv);
   }
   __syncthreads();
 
@@ -412,7 +411,12 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     if (p >= S::PAIRS) continue;
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + nl;
-    floatx4 lp = {0, 0, 0, 0}, l0 = lp, l1 = lp, l2 = lp;
+    // per-face LIFT of the two penalty scalars; k-steps never straddle a
+    // face block (KF is a multiple of the instruction's K), and the fully
+    // unrolled stream resolves each k-step's face at compile time
+    floatx4 lp = {0, 0, 0, 0}, LV[4];  // p penalty summed over faces; v penalty per face
+#pragma unroll
+    for (int f = 0; f < 4; ++f) LV[f] = floatx4{0, 0, 0, 0};
     if constexpr (PREC == 0) {
       const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
       constexpr int NK = KL / 4, PD = NK < 2 * kPrefetch ? NK : 2 * kPrefetch;
@@ -425,18 +429,17 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
-          const int k = (g * PD + i) * 4 + kq;
+          const int kk = g * PD + i, f = kk / (KF / 4);
+          const int k = kk * 4 + kq;
           const int c = swz<E>(k, col);
-          lp = mfma_f32(r.v[i][0], s_B[(0 * KMAX + k) * E + c], lp);
-          l0 = mfma_f32(r.v[i][0], s_B[(1 * KMAX + k) * E + c], l0);
-          l1 = mfma_f32(r.v[i][0], s_B[(2 * KMAX + k) * E + c], l1);
-          l2 = mfma_f32(r.v[i][0], s_B[(3 * KMAX + k) * E + c], l2);
+          lp = mfma_f32(r.v[i][0], s_B[(0 * KL + k) * E + c], lp);
+          LV[f] = mfma_f32(r.v[i][0], s_B[(1 * KL + k) * E + c], LV[f]);
         }
       };
-      pipelined<NK, PD, R>(load, compute);
+      pipelined<NK, PD, R, true>(load, compute);
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
-      constexpr int LO = 4 * KMAX * E;
+      constexpr int LO = S::REGION;  // 16-bit units
       const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       constexpr int NK = KL / 16, PD = NK < 2 * kPrefetch16 ? NK : 2 * kPrefetch16;
@@ -452,23 +455,18 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
-          const int off = (((g * PD + i) * 4 + kq) * E + col) * 4;
+          const int kk = g * PD + i, f = kk / (KF / 16);
+          const int off = ((kk * 4 + kq) * E + col) * 4;
           Frag16 b;
-          b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KMAX * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KMAX * E + off);
+          b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KL * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KL * E + off);
           lp = mfma_split<PREC>(r.v[i][0], b, lp);
-          b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KMAX * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KMAX * E + off);
-          l0 = mfma_split<PREC>(r.v[i][0], b, l0);
-          b.hi = *reinterpret_cast<const shortx4*>(u + 2 * KMAX * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KMAX * E + off);
-          l1 = mfma_split<PREC>(r.v[i][0], b, l1);
-          b.hi = *reinterpret_cast<const shortx4*>(u + 3 * KMAX * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KMAX * E + off);
-          l2 = mfma_split<PREC>(r.v[i][0], b, l2);
+          b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KL * E + off);
+          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KL * E + off);
+          LV[f] = mfma_split<PREC>(r.v[i][0], b, LV[f]);
         }
       };
-      pipelined<NK, PD, R>(load, compute);
+      pipelined<NK, PD, R, true>(load, compute);
     }
     const int n = mb * 16 + nl;
     const int ncl = n < NP ? n : NP - 1;
@@ -478,12 +476,18 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       const int ec = col < ne ? col : 0;
       const float* G = s_g + 9 * ec;
       const float rc2 = s_cf[ec * CB + 0], irho = s_cf[ec * CB + 1];
+      const float* fr = s_face + ec * 4 * FW;  // the element's face normals
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        float lv[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          lv[i] = fr[0 * FW + i] * LV[0][r] + fr[1 * FW + i] * LV[1][r] + fr[2 * FW + i] * LV[2][r] +
+                  fr[3 * FW + i] * LV[3][r];
         rr[0][r] = -rc2 * DV[q][r] + lp[r];
-        rr[1][r] = -irho * (G[0] * T0[q][r] + G[1] * T1[q][r] + G[2] * T2[q][r]) + l0[r];
-        rr[2][r] = -irho * (G[3] * T0[q][r] + G[4] * T1[q][r] + G[5] * T2[q][r]) + l1[r];
-        rr[3][r] = -irho * (G[6] * T0[q][r] + G[7] * T1[q][r] + G[8] * T2[q][r]) + l2[r];
+        rr[1][r] = -irho * (G[0] * T0[q][r] + G[1] * T1[q][r] + G[2] * T2[q][r]) + lv[0];
+        rr[2][r] = -irho * (G[3] * T0[q][r] + G[4] * T1[q][r] + G[5] * T2[q][r]) + lv[1];
+        rr[3][r] = -irho * (G[6] * T0[q][r] + G[7] * T1[q][r] + G[8] * T2[q][r]) + lv[2];
       }
     }
     // transpose field by field through the wave's scratch:
@@ -595,7 +599,7 @@ hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
 template <int N, int PREC>
 MfmaPacking packing_of() {
   using S = MShape<N, PREC>;
-  return MfmaPacking{S::MB, S::KP, S::KL, S::KS, S::E};
+  return MfmaPacking{S::MB, S::KP, S::KL, S::KS, S::E, S::KF};
 }
 
 }  // namespace
@@ -629,7 +633,8 @@ int mfma_precision(int variant) {
       break;                                                                             \
   }
 
-MfmaPacking mfma_packing(int N, int variant) {
+MfmaPacking mfma_packing(int physics, int N, int variant) {
+  if (physics != 0) return mfma_elastic_packing(N, variant);
 #define CALL(n, p) packing_of<n, p>()
   DGW_MFMA_DISPATCH(CALL)
 #undef CALL

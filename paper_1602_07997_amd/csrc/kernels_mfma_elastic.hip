@@ -616,6 +616,13 @@ int mfma_elastic_tile_elements(int N, int variant) {
   return -1;
 }
 
+MfmaPacking mfma_elastic_packing(int N, int variant) {
+#define CALL(n, p) MfmaPacking{EShape<n, p>::MB, EShape<n, p>::KP, EShape<n, p>::KL, EShape<n, p>::KS, EShape<n, p>::E, 0}
+  DGW_EMFMA_DISPATCH(CALL)
+#undef CALL
+  return MfmaPacking{};
+}
+
 hipError_t launch_step_mfma_elastic(int N, int variant, const StepArgs& a, hipStream_t s) {
 #define CALL(n, p) emfma_impl<n, p>(a, s)
   DGW_EMFMA_DISPATCH(CALL)

@@ -86,19 +86,27 @@ struct Ring {
 // so that their latency overlaps PD k-steps of products.  load(r, g) fills r
 // with group g (clamping past the end), compute(r, g, cnt) runs the first cnt
 // k-steps of group g.
-template <int NK, int PD, class R, class Load, class Compute>
+// UNROLL unrolls the group loop completely (group indices then fold to
+// constants, e.g. to pick an accumulator per face).
+template <int NK, int PD, class R, bool UNROLL = false, class Load, class Compute>
 __device__ __forceinline__ void pipelined(Load&& load, Compute&& compute) {
   constexpr int NGT = (NK + PD - 1) / PD, LAST = NK - (NGT - 1) * PD;
   R ra, rb;
   load(ra, 0);
-#pragma unroll 1
-  for (int g = 0; g + 2 < NGT; g += 2) {
+  auto two = [&](int g) {
     load(rb, g + 1);
     __builtin_amdgcn_sched_barrier(0);
     compute(ra, g, PD);
     load(ra, g + 2);
     __builtin_amdgcn_sched_barrier(0);
     compute(rb, g + 1, PD);
+  };
+  if constexpr (UNROLL) {
+#pragma unroll
+    for (int g = 0; g + 2 < NGT; g += 2) two(g);
+  } else {
+#pragma unroll 1
+    for (int g = 0; g + 2 < NGT; g += 2) two(g);
   }
   if constexpr (NGT % 2 == 1) {
     compute(ra, NGT - 1, LAST);

@@ -71,21 +71,34 @@ float f16_float(uint16_t h) {
   return x;
 }
 
-void pack_fp32(const double* A, int rows, int cols, int MB, int KP, std::vector<float>& out) {
+static int source_column(const ColMap* colmap, int col) {
+  if (!colmap) return col;
+  return col < static_cast<int>(colmap->size()) ? (*colmap)[col] : -1;
+}
+
+ColMap face_block_columns(int Nfp, int KF) {
+  if (KF < Nfp) return ColMap();  // no face blocks (merged layout)
+  ColMap m(static_cast<size_t>(4) * KF, -1);
+  for (int f = 0; f < 4; ++f)
+    for (int j = 0; j < Nfp; ++j) m[static_cast<size_t>(f) * KF + j] = f * Nfp + j;
+  return m;
+}
+
+void pack_fp32(const double* A, int rows, int cols, int MB, int KP, std::vector<float>& out, const ColMap* colmap) {
   const size_t base = out.size();
   out.resize(base + static_cast<size_t>(MB) * (KP / 4) * 64, 0.0f);
   for (int mb = 0; mb < MB; ++mb)
     for (int kk = 0; kk < KP / 4; ++kk)
       for (int l = 0; l < 64; ++l) {
-        const int row = mb * 16 + l % 16, col = kk * 4 + l / 16;
-        if (row < rows && col < cols)
+        const int row = mb * 16 + l % 16, col = source_column(colmap, kk * 4 + l / 16);
+        if (row < rows && col >= 0 && col < cols)
           out[base + (static_cast<size_t>(mb) * (KP / 4) + kk) * 64 + l] =
               static_cast<float>(A[static_cast<size_t>(row) * cols + col]);
       }
 }
 
 void pack_split16(const double* A, int rows, int cols, int MB, int K16, bool bf16, std::vector<uint16_t>& hi,
-                  std::vector<uint16_t>& lo) {
+                  std::vector<uint16_t>& lo, const ColMap* colmap) {
   const size_t base = hi.size();
   const size_t n = static_cast<size_t>(MB) * (K16 / 16) * 64 * 4;
   hi.resize(base + n, 0);
@@ -94,8 +107,8 @@ void pack_split16(const double* A, int rows, int cols, int MB, int K16, bool bf1
     for (int kk = 0; kk < K16 / 16; ++kk)
       for (int l = 0; l < 64; ++l)
         for (int t = 0; t < 4; ++t) {
-          const int row = mb * 16 + l % 16, col = kk * 16 + 4 * (l / 16) + t;
-          if (row >= rows || col >= cols) continue;
+          const int row = mb * 16 + l % 16, col = source_column(colmap, kk * 16 + 4 * (l / 16) + t);
+          if (row >= rows || col < 0 || col >= cols) continue;
           const double x = A[static_cast<size_t>(row) * cols + col];
           const size_t idx = base + ((static_cast<size_t>(mb) * (K16 / 16) + kk) * 64 + l) * 4 + t;
           if (bf16) {
