@@ -283,10 +283,11 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
     for (int v = 0; v < 2; ++v) {
       const dgw::MfmaPacking p16 = dgw::mfma_packing(physics, order, vars[v]);
       const dgw::ColMap c16 = dgw::face_block_columns(Nfp, p16.KF);
+      const int kw = p16.KS / 4;  // k per lane group: 4 (16x16x16) or 8 (16x16x32)
       for (int j = 0; j < 3; ++j)
-        dgw::pack_split16(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p16.MB, p16.KP, v == 0,
+        dgw::pack_split16(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p16.MB, p16.KP, kw, v == 0,
                           D16[v][0], D16[v][1]);
-      dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, v == 0, L16[v][0], L16[v][1],
+      dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, kw, v == 0, L16[v][0], L16[v][1],
                         p16.KF > 0 ? &c16 : nullptr);
     }
   }

@@ -27,9 +27,9 @@ struct StepArgs {
   const int32_t* nodeface;  // [NP][3] face slots f*NFP+j containing node n, -1 padded
   const float* Dpack;    // FP32 MFMA: D_j in 16x4 fragment order [3][MB][KP/4][64]
   const float* Lpack;    // FP32 MFMA: LIFT [MB][KL/4][64] (acoustic per face, elastic merged)
-  const uint16_t* D16h;  // 16-bit MFMA: D_j split hi / lo, 16x16 fragments [3][MB][KP/16][64][4]
+  const uint16_t* D16h;  // 16-bit MFMA: D_j split hi / lo, [3][MB][KP/KS][64][KS/4] (KS = 32 acoustic, 16 elastic)
   const uint16_t* D16l;
-  const uint16_t* L16h;  // 16-bit MFMA: LIFT split hi / lo [MB][KL/16][64][4], K as in Lpack
+  const uint16_t* L16h;  // 16-bit MFMA: LIFT split hi / lo [MB][KL/KS][64][KS/4], K as in Lpack
   const uint16_t* L16l;
   float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
   int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))

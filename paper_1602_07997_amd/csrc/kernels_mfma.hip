@@ -10,10 +10,10 @@
 // face, so it multiplies the lifted scalar Pv after the product: two lifted
 // operands instead of four.  Three precisions:
 //   PREC 0  FP32 v_mfma_f32_16x16x4_f32;
-//   PREC 1  BF16 v_mfma_f32_16x16x16_bf16 with FP32 accumulation and the
-//           split x = x_hi + x_lo of both operands, D x ~ D_hi x_hi +
+//   PREC 1  BF16 v_mfma_f32_16x16x32_bf16 (gfx950) with FP32 accumulation
+//           and the split x = x_hi + x_lo of both operands, D x ~ D_hi x_hi +
 //           D_hi x_lo + D_lo x_hi (the dropped D_lo x_lo is ~2^-16 |D||x|);
-//   PREC 2  FP16 v_mfma_f32_16x16x16_f16 with the same three products
+//   PREC 2  FP16 v_mfma_f32_16x16x32_f16 with the same three products
 //           (~2^-22 |D||x| dropped).
 // Operators are split and packed on the host in fragment order (the LIFT in
 // face blocks of KF columns); the right-hand operands (p, U_j, the
@@ -55,7 +55,7 @@ constexpr int kPrefetch16 = 1;
 template <int N, int PREC>
 struct MShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
-  static constexpr int KS = PREC == 0 ? 4 : 16;  // k per instruction
+  static constexpr int KS = PREC == 0 ? 4 : 32;  // k per instruction
   static constexpr int MB = (NP + 15) / 16;      // 16-row node blocks
   static constexpr int KP = rup(NP, KS);         // volume K, zero padded
   static constexpr int KF = rup(NFP, KS);        // LIFT K of one face, zero padded
@@ -71,7 +71,7 @@ struct MShape {
 // B operand region, sets of STRIDE rows (KP for the volume operands, KL for
 // the penalties): set s, row k, column e.
 //   FP32:   word (s*STRIDE + k)*E + swz(k, e)
-//   16-bit: hi at unit s*STRIDE*E + ((k/4)*E + e)*4 + k%4, lo REGION units later
+//   16-bit: hi at unit s*STRIDE*E + ((k/8)*E + e)*8 + k%8, lo REGION units later
 template <int N, int PREC, int STRIDE>
 struct BRegion {
   using S = MShape<N, PREC>;
@@ -83,7 +83,7 @@ struct BRegion {
       uint16_t* u = reinterpret_cast<uint16_t*>(w);
       uint16_t hi, lo;
       split16<PREC>(x, hi, lo);
-      const int idx = s * STRIDE * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+      const int idx = s * STRIDE * S::E + ((k >> 3) * S::E + e) * 8 + (k & 7);
       u[idx] = hi;
       u[S::REGION + idx] = lo;
     }
@@ -101,7 +101,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   constexpr int SCR = 16 * 17;                             // per-wave transpose scratch
   constexpr int PPW = (S::PAIRS + 3) / 4;                  // pairs per wavefront (at most)
 
-  __shared__ float s_B[S::REGION];
+  __shared__ __attribute__((aligned(16))) float s_B[S::REGION];
   __shared__ float s_g[E * 9];
   __shared__ float s_cf[E * CB];
   __shared__ float s_face[E * 4 * FW];
@@ -342,18 +342,18 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
       constexpr int LO = S::REGION;  // 16-bit units
-      constexpr int JS = MB * (KP / 16) * 64;  // fragments between D_0, D_1, D_2
-      const shortx4* Dh = reinterpret_cast<const shortx4*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
-      const shortx4* Dl = reinterpret_cast<const shortx4*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 16) * 64 + lane;
+      constexpr int JS = MB * (KP / 32) * 64;  // fragments between D_0, D_1, D_2
+      const shortx8* Dh = reinterpret_cast<const shortx8*>(a.D16h) + static_cast<int64_t>(mb) * (KP / 32) * 64 + lane;
+      const shortx8* Dl = reinterpret_cast<const shortx8*>(a.D16l) + static_cast<int64_t>(mb) * (KP / 32) * 64 + lane;
       // operator fragments through two register sets, as in the FP32 path
-      constexpr int NK = KP / 16, PD = NK < kPrefetch16 ? NK : kPrefetch16;
-      using R = Ring<Frag16, PD, 3>;
+      constexpr int NK = KP / 32, PD = NK < kPrefetch16 ? NK : kPrefetch16;
+      using R = Ring<Frag32, PD, 3>;
       auto load = [&](R& r, int g) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           const int kk = g * PD + i < NK ? g * PD + i : NK - 1;  // clamped; the extra reads are unused
 #pragma unroll
-          for (int j = 0; j < 3; ++j) r.v[i][j] = Frag16{Dh[j * JS + kk * 64], Dl[j * JS + kk * 64]};
+          for (int j = 0; j < 3; ++j) r.v[i][j] = Frag32{Dh[j * JS + kk * 64], Dl[j * JS + kk * 64]};
         }
       };
       auto compute = [&](const R& r, int g, int cnt) {
@@ -361,16 +361,16 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
           const int kk = g * PD + i;
-          const int off = ((kk * 4 + kq) * E + col) * 4;
-          Frag16 bp, b0, b1, b2;
-          bp.hi = *reinterpret_cast<const shortx4*>(u + 0 * KP * E + off);
-          bp.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KP * E + off);
-          b0.hi = *reinterpret_cast<const shortx4*>(u + 1 * KP * E + off);
-          b0.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KP * E + off);
-          b1.hi = *reinterpret_cast<const shortx4*>(u + 2 * KP * E + off);
-          b1.lo = *reinterpret_cast<const shortx4*>(u + LO + 2 * KP * E + off);
-          b2.hi = *reinterpret_cast<const shortx4*>(u + 3 * KP * E + off);
-          b2.lo = *reinterpret_cast<const shortx4*>(u + LO + 3 * KP * E + off);
+          const int off = ((kk * 4 + kq) * E + col) * 8;
+          Frag32 bp, b0, b1, b2;
+          bp.hi = *reinterpret_cast<const shortx8*>(u + 0 * KP * E + off);
+          bp.lo = *reinterpret_cast<const shortx8*>(u + LO + 0 * KP * E + off);
+          b0.hi = *reinterpret_cast<const shortx8*>(u + 1 * KP * E + off);
+          b0.lo = *reinterpret_cast<const shortx8*>(u + LO + 1 * KP * E + off);
+          b1.hi = *reinterpret_cast<const shortx8*>(u + 2 * KP * E + off);
+          b1.lo = *reinterpret_cast<const shortx8*>(u + LO + 2 * KP * E + off);
+          b2.hi = *reinterpret_cast<const shortx8*>(u + 3 * KP * E + off);
+          b2.lo = *reinterpret_cast<const shortx8*>(u + LO + 3 * KP * E + off);
           T0[q] = mfma_split<PREC>(r.v[i][0], bp, T0[q]);
           T1[q] = mfma_split<PREC>(r.v[i][1], bp, T1[q]);
           T2[q] = mfma_split<PREC>(r.v[i][2], bp, T2[q]);
@@ -440,29 +440,29 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
       constexpr int LO = S::REGION;  // 16-bit units
-      const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
-      const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
-      constexpr int NK = KL / 16, PD = NK < 2 * kPrefetch16 ? NK : 2 * kPrefetch16;
-      using R = Ring<Frag16, PD, 1>;
+      const shortx8* Lh = reinterpret_cast<const shortx8*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 32) * 64 + lane;
+      const shortx8* Ll = reinterpret_cast<const shortx8*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 32) * 64 + lane;
+      constexpr int NK = KL / 32, PD = NK < 2 * kPrefetch16 ? NK : 2 * kPrefetch16;
+      using R = Ring<Frag32, PD, 1>;
       auto load = [&](R& r, int g) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           const int kk = g * PD + i < NK ? g * PD + i : NK - 1;
-          r.v[i][0] = Frag16{Lh[kk * 64], Ll[kk * 64]};
+          r.v[i][0] = Frag32{Lh[kk * 64], Ll[kk * 64]};
         }
       };
       auto compute = [&](const R& r, int g, int cnt) {
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
-          const int kk = g * PD + i, f = kk / (KF / 16);
-          const int off = ((kk * 4 + kq) * E + col) * 4;
-          Frag16 b;
-          b.hi = *reinterpret_cast<const shortx4*>(u + 0 * KL * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 0 * KL * E + off);
+          const int kk = g * PD + i, f = kk / (KF / 32);
+          const int off = ((kk * 4 + kq) * E + col) * 8;
+          Frag32 b;
+          b.hi = *reinterpret_cast<const shortx8*>(u + 0 * KL * E + off);
+          b.lo = *reinterpret_cast<const shortx8*>(u + LO + 0 * KL * E + off);
           lp = mfma_split<PREC>(r.v[i][0], b, lp);
-          b.hi = *reinterpret_cast<const shortx4*>(u + 1 * KL * E + off);
-          b.lo = *reinterpret_cast<const shortx4*>(u + LO + 1 * KL * E + off);
+          b.hi = *reinterpret_cast<const shortx8*>(u + 1 * KL * E + off);
+          b.lo = *reinterpret_cast<const shortx8*>(u + LO + 1 * KL * E + off);
           LV[f] = mfma_split<PREC>(r.v[i][0], b, LV[f]);
         }
       };

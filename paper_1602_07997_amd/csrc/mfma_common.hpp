@@ -11,7 +11,10 @@ namespace mfma {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int rup(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -72,6 +75,31 @@ __device__ __forceinline__ floatx4 mfma_split(const Frag16& a, const Frag16& b, 
   c = mfma16<PREC>(a.lo, b.hi, c);
   c = mfma16<PREC>(a.hi, b.lo, c);
   return mfma16<PREC>(a.hi, b.hi, c);
+}
+
+// gfx950 16x16x32 products: lane l holds row (A) / column (B) l%16 at
+// k = 8 (l/16) + t, t = 0..7; the accumulator layout is that of 16x16x16.
+// Twice the work of a 16x16x16 instruction at the same issue cost.
+struct Frag32 {
+  shortx8 hi, lo;
+};
+
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma32(shortx8 a, shortx8 b, floatx4 c) {
+  if constexpr (PREC == 1) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8, a), __builtin_bit_cast(halfx8, b), c,
+                                                  0, 0, 0);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ floatx4 mfma_split(const Frag32& a, const Frag32& b, floatx4 c) {
+  c = mfma32<PREC>(a.lo, b.hi, c);
+  c = mfma32<PREC>(a.hi, b.lo, c);
+  return mfma32<PREC>(a.hi, b.hi, c);
 }
 
 // Register sets of a software-pipelined operator stream.

@@ -97,20 +97,21 @@ void pack_fp32(const double* A, int rows, int cols, int MB, int KP, std::vector<
       }
 }
 
-void pack_split16(const double* A, int rows, int cols, int MB, int K16, bool bf16, std::vector<uint16_t>& hi,
+void pack_split16(const double* A, int rows, int cols, int MB, int K, int KW, bool bf16, std::vector<uint16_t>& hi,
                   std::vector<uint16_t>& lo, const ColMap* colmap) {
+  const int KB = 4 * KW;  // k per fragment
   const size_t base = hi.size();
-  const size_t n = static_cast<size_t>(MB) * (K16 / 16) * 64 * 4;
+  const size_t n = static_cast<size_t>(MB) * (K / KB) * 64 * KW;
   hi.resize(base + n, 0);
   lo.resize(base + n, 0);
   for (int mb = 0; mb < MB; ++mb)
-    for (int kk = 0; kk < K16 / 16; ++kk)
+    for (int kk = 0; kk < K / KB; ++kk)
       for (int l = 0; l < 64; ++l)
-        for (int t = 0; t < 4; ++t) {
-          const int row = mb * 16 + l % 16, col = source_column(colmap, kk * 16 + 4 * (l / 16) + t);
+        for (int t = 0; t < KW; ++t) {
+          const int row = mb * 16 + l % 16, col = source_column(colmap, kk * KB + KW * (l / 16) + t);
           if (row >= rows || col < 0 || col >= cols) continue;
           const double x = A[static_cast<size_t>(row) * cols + col];
-          const size_t idx = base + ((static_cast<size_t>(mb) * (K16 / 16) + kk) * 64 + l) * 4 + t;
+          const size_t idx = base + ((static_cast<size_t>(mb) * (K / KB) + kk) * 64 + l) * KW + t;
           if (bf16) {
             const uint16_t h = bf16_round(static_cast<float>(x));
             hi[idx] = h;

@@ -21,10 +21,11 @@ using ColMap = std::vector<int>;
 void pack_fp32(const double* A, int rows, int cols, int MB, int KP, std::vector<float>& out,
                const ColMap* colmap = nullptr);
 
-// A as 16x16 fragments of 16-bit pairs x = hi + lo, lane l holding
-// A[mb*16 + l%16][c(16 kk + 4 (l/16) + t)], t = 0..3; appended as
-// [MB][K16/16][64][4] to hi and lo.
-void pack_split16(const double* A, int rows, int cols, int MB, int K16, bool bf16, std::vector<uint16_t>& hi,
+// A as 16 x (4 KW) fragments of 16-bit pairs x = hi + lo (KW = 4: the
+// 16x16x16 instructions, KW = 8: 16x16x32), lane l holding
+// A[mb*16 + l%16][c(4 KW kk + KW (l/16) + t)], t < KW; appended as
+// [MB][K/(4 KW)][64][KW] to hi and lo.
+void pack_split16(const double* A, int rows, int cols, int MB, int K, int KW, bool bf16, std::vector<uint16_t>& hi,
                   std::vector<uint16_t>& lo, const ColMap* colmap = nullptr);
 
 // Column map of the per-face LIFT: face f's Nfp columns start at K = f*KF
