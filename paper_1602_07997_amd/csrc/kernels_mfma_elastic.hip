@@ -4,23 +4,27 @@
 // With the element as the GEMM column, for a tile of E = 16 NBLK elements:
 //   Dv_il = D_l v_i                 (9 products, K = Np)
 //   dS_i  = sum_l D_l S_il,  S_il = sum_a g_al s_ia   (K = Np, S formed per k-step)
-//   Lv_i, Ls_v = L B_c              (9 products over the merged 4 Nfp face nodes)
-// where the LIFT operands B are the upwind penalties of Sec. 2.1 already
-// combined with the element's coefficients and the face normal:
-//   Bv_i = n_i (c_p A1 - c_s A2) + k_s c_s A3_i
-//   Bs_ij = 2 mu (A1 - A2) n_i n_j + mu k_s (n_i A3_j + A3_i n_j) + delta_ij lambda A1
-//   A1 = Fs k_p (s_nn + Zp+ v_n), A2 = Fs k_s (s_nn + Zs+ v_n), A3 = Fs (s n + Zs+ v)
-// (jumps halved).  The right-hand side is then
+//   a_c   = L_f A_c                 (5 products per face, K = Nfp, L_f the
+//                                    face-f block of the lift matrix)
+// with the penalty scalars of Sec. 2.1 at face f's nodes (jumps halved)
+//   A1 = Fs k_p (s_nn + Zp+ v_n), A2 = Fs k_s (s_nn + Zs+ v_n), A3 = Fs (s n + Zs+ v).
+// The face normal, k_s and the element's coefficients are constant over an
+// affine face, so they are applied after the product:
+//   Lv_i  = sum_f n_i (c_p a1 - c_s a2) + k_s c_s a3_i
+//   Ls_ij = sum_f 2 mu (a1 - a2) n_i n_j + mu k_s (n_i a3_j + a3_i n_j) + delta_ij lambda a1
+// and the right-hand side is
 //   r_v_i = (1/rho) dS_i + Lv_i,
 //   r_s_ij = mu (dv_i/dx_j + dv_j/dx_i) + delta_ij lambda div v + Ls_ij,
 //   dv_i/dx_j = sum_l g_jl Dv_il.
 // Precisions as in the acoustic kernel: FP32 16x16x4, or BF16 / FP16
 // 16x16x16 with both operands split hi + lo and three products accumulated in
 // FP32.  Workgroups of 8 wavefronts; phases:
-//   A1  constants and face records into LDS;
-//   A2  LIFT operands of every face node into LDS (neighbour traces gathered
-//       here);
-//   C2  LIFT products, kept in registers;
+//   A1  every global read indexed by the tile alone, issued together;
+//       constants into LDS;
+//   A2  neighbour traces; face records; the five LIFT operands of every face
+//       node into LDS;
+//   C2  LIFT products per face, combined into the nine contributions and
+//       kept in registers;
 //   B1  the tile's nine fields into the same LDS region;
 //   C1  volume products and the epilogue (transpose through a per-wave LDS
 //       scratch, AB3 update, q / r writes, own traces), pair by pair.
@@ -47,30 +51,33 @@ struct EShape {
   static constexpr int KS = PREC == 0 ? 4 : 16;
   static constexpr int MB = (NP + 15) / 16;
   static constexpr int KP = rup(NP, KS);
-  static constexpr int KL = rup(4 * NFP, KS);
-  static constexpr int KMAX = KP > KL ? KP : KL;
+  static constexpr int KF = rup(NFP, KS);  // LIFT K of one face, zero padded
+  static constexpr int KL = 4 * KF;        // LIFT K, face blocks of KF
   static constexpr int NBLK = (N == 1) ? 4 : (N <= 3 ? 2 : 1);
   static constexpr int E = 16 * NBLK;
   static constexpr int PAIRS = MB * NBLK;
-  static constexpr int NSET = 9;
-  static constexpr int REGION = NSET * KMAX * E;  // 4-byte words
+  static constexpr int NSV = 9;  // volume operand sets (the fields)
+  static constexpr int NSL = 5;  // LIFT operand sets (the lifted penalty scalars)
+  // 4-byte words: the LIFT sets, then (reused) the volume sets
+  static constexpr int REGION = (NSV * KP > NSL * KL ? NSV * KP : NSL * KL) * E;
 };
 
-// Operand region, set s, row k, column e.
+// Operand region, sets of STRIDE rows (KL for the LIFT operands, KP for the
+// fields): set s, row k, column e.
 //   FP32 sets (PREC 0, and the volume sets of every precision):
-//     PREC 0:  word (s*KMAX + k)*E + swz(k, e)
-//     else:    word s*KMAX*E + ((k/4)*E + e)*4 + k%4   (4 consecutive k contiguous)
+//     PREC 0:  word (s*STRIDE + k)*E + swz(k, e)
+//     else:    word s*STRIDE*E + ((k/4)*E + e)*4 + k%4   (4 consecutive k contiguous)
 //   16-bit split sets (LIFT operands of PREC 1, 2): hi at unit
-//     s*KMAX*E + ((k/4)*E + e)*4 + k%4, lo NSET*KMAX*E units later.
-template <int N, int PREC>
+//     s*STRIDE*E + ((k/4)*E + e)*4 + k%4, lo REGION units later.
+template <int N, int PREC, int STRIDE>
 struct ERegion {
   using S = EShape<N, PREC>;
   float* w;
   __device__ __forceinline__ int f32_word(int s, int k, int e) const {
     if constexpr (PREC == 0)
-      return (s * S::KMAX + k) * S::E + swz<S::E>(k, e);
+      return (s * STRIDE + k) * S::E + swz<S::E>(k, e);
     else
-      return s * S::KMAX * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+      return s * STRIDE * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
   }
   __device__ __forceinline__ void put_f32(int s, int k, int e, float x) const { w[f32_word(s, k, e)] = x; }
   __device__ __forceinline__ void put_split(int s, int k, int e, float x) const {
@@ -80,9 +87,9 @@ struct ERegion {
       uint16_t* u = reinterpret_cast<uint16_t*>(w);
       uint16_t hi, lo;
       split16<PREC>(x, hi, lo);
-      const int idx = s * S::KMAX * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
+      const int idx = s * STRIDE * S::E + ((k >> 2) * S::E + e) * 4 + (k & 3);
       u[idx] = hi;
-      u[S::NSET * S::KMAX * S::E + idx] = lo;
+      u[S::REGION + idx] = lo;
     }
   }
 };
@@ -103,7 +110,7 @@ __device__ __forceinline__ Frag16 split4(const float4& x) {
 template <int N, int PREC>
 __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_t tile) {
   using S = EShape<N, PREC>;
-  constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KMAX = S::KMAX, E = S::E;
+  constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
   constexpr int NF = 9, NT = 6, CB = 16;
   constexpr int FW = FaceRec<1>::W;
   constexpr int NW = kEThreads / 64;
@@ -112,7 +119,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   constexpr int SCR = 16 * 17;
   constexpr int PPW = (S::PAIRS + NW - 1) / NW;
 
-  __shared__ float s_B[S::REGION];
+  __shared__ __attribute__((aligned(16))) float s_B[S::REGION];
   __shared__ float s_g[E * 9];
   __shared__ float s_cf[E * CB];
   __shared__ float s_face[E * 4 * FW];
@@ -125,7 +132,8 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   const int lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, nl = lane & 15;
   const bool step = (a.mode == kStepMode);
-  const ERegion<N, PREC> reg{s_B};
+  const ERegion<N, PREC, KL> lreg{s_B};  // LIFT operands
+  const ERegion<N, PREC, KP> vreg{s_B};  // fields (after the LIFT products)
 
   // ---- A1: every global read indexed by the tile alone, issued together ----
   // Loads are unconditional at clamped (in-range) addresses and unused values
@@ -156,7 +164,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   }
   const int rec_e = tid >> 2, rec_f = tid & 3;
   const int rec_word = a.conn[(e0 + (rec_e < ne ? rec_e : 0)) * 4 + rec_f];
-  // face-slot items i = e*KL + slot, slot = f*NFP + j while slot < 4 NFP:
+  // face-slot items i = e*KL + slot, slot = f*KF + j, a face node while j < NFP:
   // connectivity word and own trace (v and s n of the fields read this step)
   int cw[FIT];
   float ot[FIT][NT];
@@ -164,9 +172,9 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kEThreads;
     const int e = i / KL, slot = i - e * KL;
-    const bool ok = e < ne && slot < 4 * NFP;
-    const int ec = ok ? e : 0, sc = ok ? slot : 0;
-    const int f = sc / NFP, j = sc - f * NFP;
+    const int fs = slot / KF, js = slot - fs * KF;
+    const bool ok = e < ne && js < NFP;
+    const int ec = ok ? e : 0, f = ok ? fs : 0, j = ok ? js : 0;
     cw[t] = a.conn[(e0 + ec) * 4 + f];
     const float* own = a.qf_in + ((e0 + ec) * 4 + f) * NT * NFP + j;
 #pragma unroll
@@ -195,9 +203,9 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   for (int t = 0; t < FIT; ++t) {
     const int i = tid + t * kEThreads;
     const int e = i / KL, slot = i - e * KL;
-    const bool ok = e < ne && slot < 4 * NFP;
-    const int ec = ok ? e : 0, sc = ok ? slot : 0;
-    const int f = sc / NFP, j = sc - f * NFP;
+    const int fs = slot / KF, js = slot - fs * KF;
+    const bool ok = e < ne && js < NFP;
+    const int ec = ok ? e : 0, f = ok ? fs : 0, j = ok ? js : 0;
     const int w = cw[t];
     const bool wall = (w & 7) == 7;
     // a wall reads its own trace (in range, value unused)
@@ -215,14 +223,17 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     const int i = tid + t * kEThreads;
     if (i >= E * KL) continue;
     const int e = i / KL, slot = i - e * KL;
-    float b[9];
+    // the five lifted scalars of Sec. 2.1's elastic penalty (jumps halved):
+    // A1 = Fs k_p (s_nn + Zp+ v_n), A2 = Fs k_s (s_nn + Zs+ v_n),
+    // A3 = Fs (s n + Zs+ v); the normal and the coefficients are applied
+    // after the per-face LIFT products
+    float b[5];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) b[c] = 0.0f;
-    if (e < ne && slot < 4 * NFP) {
-      const int f = slot / NFP;
+    for (int c = 0; c < 5; ++c) b[c] = 0.0f;
+    const int f = slot / KF;
+    if (e < ne && slot - f * KF < NFP) {
       const float* rec = s_face + (e * 4 + f) * FW;
       const float n0 = rec[0], n1 = rec[1], n2 = rec[2];
-      const float nn[3] = {n0, n1, n2};
       const bool wall = (cw[t] & 7) == 7;
       float vM[3], tM[3], vP[3], tP[3];
 #pragma unroll
@@ -243,33 +254,22 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
       const float jvn = jv[0] * n0 + jv[1] * n1 + jv[2] * n2;
       const float jsnn = jt[0] * n0 + jt[1] * n1 + jt[2] * n2;
       const float ZpP = rec[3], ZsP = rec[4], fs = rec[5], kp = rec[6], ks = rec[7];
-      const float A1 = fs * kp * (jsnn + ZpP * jvn);
-      const float A2 = fs * ks * (jsnn + ZsP * jvn);
-      float A3[3];
+      b[0] = fs * kp * (jsnn + ZpP * jvn);
+      b[1] = fs * ks * (jsnn + ZsP * jvn);
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) A3[ii] = fs * (jt[ii] + ZsP * jv[ii]);
-      const float* cf = s_cf + e * CB;
-      const float lam = cf[0], mu = cf[1], cp = cf[5], cs = cf[6];
-      const float a1 = cp * A1 - cs * A2;
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) b[ii] = nn[ii] * a1 + ks * cs * A3[ii];
-      const float b2 = 2.0f * mu * (A1 - A2), c3 = mu * ks;
-      const int vi[6] = {0, 1, 2, 1, 0, 0};
-      const int vj[6] = {0, 1, 2, 2, 2, 1};
-#pragma unroll
-      for (int v = 0; v < 6; ++v) {
-        const int ii = vi[v], jj = vj[v];
-        float x = b2 * nn[ii] * nn[jj] + c3 * (nn[ii] * A3[jj] + A3[ii] * nn[jj]);
-        if (ii == jj) x += lam * A1;
-        b[3 + v] = x;
-      }
+      for (int ii = 0; ii < 3; ++ii) b[2 + ii] = fs * (jt[ii] + ZsP * jv[ii]);
     }
 #pragma unroll
-    for (int c = 0; c < 9; ++c) reg.put_split(c, slot, e, b[c]);
+    for (int c = 0; c < 5; ++c) lreg.put_split(c, slot, e, b[c]);
   }
   __syncthreads();
 
-  // ---- C2: LIFT products (kept) ---------------------------------------------
+  // ---- C2: LIFT products per face, combined into the nine right-hand-side
+  // contributions (kept in registers) ------------------------------------------
+  // For face f with normal n and the element's lambda, mu, c_p, c_s and the
+  // face's k_s, the lifted scalars a1 = L_f A1, a2 = L_f A2, a3 = L_f A3 give
+  //   velocity  n (c_p a1 - c_s a2) + k_s c_s a3
+  //   stress    2 mu (a1 - a2) n n^T + mu k_s (n a3^T + a3 n^T) + lambda a1 I.
   floatx4 LL[PPW][9];
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
@@ -279,10 +279,42 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     if (p >= S::PAIRS) continue;
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + nl;
-    // operator fragments stream through two register sets (pipelined)
+    const int ecol = col < ne ? col : 0;
+    floatx4 LA[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) LA[c] = floatx4{0, 0, 0, 0};
+    auto combine = [&](int f) {
+      const float* rec = s_face + (ecol * 4 + f) * FW;
+      const float* cf = s_cf + ecol * CB;
+      const float nn[3] = {rec[0], rec[1], rec[2]};
+      const float ks = rec[7];
+      const float lam = cf[0], mu = cf[1], cp = cf[5], cs = cf[6];
+      const int vi[6] = {0, 1, 2, 1, 0, 0};
+      const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float a1 = LA[0][r], a2 = LA[1][r];
+        const float a3[3] = {LA[2][r], LA[3][r], LA[4][r]};
+        const float t = cp * a1 - cs * a2;
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) LL[q][ii][r] += nn[ii] * t + ks * cs * a3[ii];
+        const float b2 = 2.0f * mu * (a1 - a2), c3 = mu * ks;
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+          const int ii = vi[v], jj = vj[v];
+          float x = b2 * nn[ii] * nn[jj] + c3 * (nn[ii] * a3[jj] + a3[ii] * nn[jj]);
+          if (ii == jj) x += lam * a1;
+          LL[q][3 + v][r] += x;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 5; ++c) LA[c] = floatx4{0, 0, 0, 0};
+    };
+    // operator fragments stream through two register sets (pipelined, fully
+    // unrolled so that each k-step's face is known at compile time)
     if constexpr (PREC == 0) {
       const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
-      constexpr int NK = KL / 4, PD = NK < 8 ? NK : 8;
+      constexpr int NK = KL / 4, NKF = KF / 4, PD = NK < 8 ? NK : 8;
       using R = Ring<float, PD, 1>;
       auto load = [&](R& r, int g) {
 #pragma unroll
@@ -292,18 +324,20 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
-          const int k = (g * PD + i) * 4 + kq;
+          const int kk = g * PD + i;
+          const int k = kk * 4 + kq;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) LL[q][c] = mfma_f32(r.v[i][0], s_B[reg.f32_word(c, k, col)], LL[q][c]);
+          for (int c = 0; c < 5; ++c) LA[c] = mfma_f32(r.v[i][0], s_B[lreg.f32_word(c, k, col)], LA[c]);
+          if (kk % NKF == NKF - 1) combine(kk / NKF);
         }
       };
-      pipelined<NK, PD, R>(load, compute);
+      pipelined<NK, PD, R, true>(load, compute);
     } else {
       const uint16_t* u = reinterpret_cast<const uint16_t*>(s_B);
-      constexpr int LO = S::NSET * KMAX * E;
+      constexpr int LO = S::REGION;  // 16-bit units
       const shortx4* Lh = reinterpret_cast<const shortx4*>(a.L16h) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
       const shortx4* Ll = reinterpret_cast<const shortx4*>(a.L16l) + static_cast<int64_t>(mb) * (KL / 16) * 64 + lane;
-      constexpr int NK = KL / 16, PD = NK < 2 ? NK : 2;
+      constexpr int NK = KL / 16, NKF = KF / 16, PD = NK < 2 ? NK : 2;
       using R = Ring<Frag16, PD, 1>;
       auto load = [&](R& r, int g) {
 #pragma unroll
@@ -316,17 +350,19 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 #pragma unroll
         for (int i = 0; i < PD; ++i) {
           if (i >= cnt) break;
-          const int off = (((g * PD + i) * 4 + kq) * E + col) * 4;
+          const int kk = g * PD + i;
+          const int off = ((kk * 4 + kq) * E + col) * 4;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) {
+          for (int c = 0; c < 5; ++c) {
             Frag16 b;
-            b.hi = *reinterpret_cast<const shortx4*>(u + c * KMAX * E + off);
-            b.lo = *reinterpret_cast<const shortx4*>(u + LO + c * KMAX * E + off);
-            LL[q][c] = mfma_split<PREC>(r.v[i][0], b, LL[q][c]);
+            b.hi = *reinterpret_cast<const shortx4*>(u + c * KL * E + off);
+            b.lo = *reinterpret_cast<const shortx4*>(u + LO + c * KL * E + off);
+            LA[c] = mfma_split<PREC>(r.v[i][0], b, LA[c]);
           }
+          if (kk % NKF == NKF - 1) combine(kk / NKF);
         }
       };
-      pipelined<NK, PD, R>(load, compute);
+      pipelined<NK, PD, R, true>(load, compute);
     }
   }
   __syncthreads();
@@ -353,7 +389,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
       const int e = i / KP, n = i - e * KP;
       const bool ok = e < ne && n < NP;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) reg.put_f32(c, n, e, ok ? x[u][c] : 0.0f);
+      for (int c = 0; c < 9; ++c) vreg.put_f32(c, n, e, ok ? x[u][c] : 0.0f);
     }
   }
   __syncthreads();
@@ -397,7 +433,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
           const int k = (g * PD + i) * 4 + kq;
           float x[9];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) x[c] = s_B[reg.f32_word(c, k, col)];
+          for (int c = 0; c < 9; ++c) x[c] = s_B[vreg.f32_word(c, k, col)];
 #pragma unroll
           for (int ii = 0; ii < 3; ++ii) {
             const float si0 = x[3 + voigt(ii, 0)], si1 = x[3 + voigt(ii, 1)], si2 = x[3 + voigt(ii, 2)];
@@ -424,7 +460,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
       auto compute = [&](const R& r, int kk, int) {
         float4 x[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) x[c] = *reinterpret_cast<const float4*>(s_B + reg.f32_word(c, kk * 16 + 4 * kq, col));
+        for (int c = 0; c < 9; ++c) x[c] = *reinterpret_cast<const float4*>(s_B + vreg.f32_word(c, kk * 16 + 4 * kq, col));
         const Frag16* d = r.v[0];
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
@@ -617,7 +653,7 @@ int mfma_elastic_tile_elements(int N, int variant) {
 }
 
 MfmaPacking mfma_elastic_packing(int N, int variant) {
-#define CALL(n, p) MfmaPacking{EShape<n, p>::MB, EShape<n, p>::KP, EShape<n, p>::KL, EShape<n, p>::KS, EShape<n, p>::E, 0}
+#define CALL(n, p) MfmaPacking{EShape<n, p>::MB, EShape<n, p>::KP, EShape<n, p>::KL, EShape<n, p>::KS, EShape<n, p>::E, EShape<n, p>::KF}
   DGW_EMFMA_DISPATCH(CALL)
 #undef CALL
   return MfmaPacking{};
