@@ -73,6 +73,12 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
   __shared__ float s_cf[KT * CB];
   constexpr int FW = FaceRec<PHYS>::W;
   __shared__ float s_face[KT * 4 * FW];
+  // At the lowest degrees the operators (3 Np^2 + 4 Nfp Np floats, under
+  // 8 KB) are staged in LDS with the tile, so that the node loops read them
+  // at LDS latency instead of waiting on the cache for every k.
+  constexpr bool OPS_LDS = N <= 3;
+  constexpr int NDT = 3 * NP * NP, NLT = NFN * NP;
+  __shared__ float s_ops[OPS_LDS ? NDT + NLT : 1];
 
   const int64_t e0 = tile * KT;
   if (e0 >= a.K) return;  // whole workgroup exits together
@@ -158,6 +164,13 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
   }
   const int rec_e = tid >> 2, rec_f = tid & 3;
   const int rec_word = a.conn[(e0 + (rec_e < ne ? rec_e : 0)) * 4 + rec_f];
+  constexpr int OIT = OPS_LDS ? (NDT + NLT + kThreads - 1) / kThreads : 0;
+  float ov[OIT > 0 ? OIT : 1];
+#pragma unroll
+  for (int t = 0; t < OIT; ++t) {
+    const int i = tid + t * kThreads;
+    ov[t] = i < NDT ? a.DT[i] : a.LT[i < NDT + NLT ? i - NDT : 0];
+  }
   // volume node of each face-node item; face slots of each node item
   int vnode[FIT], nfs[NIT][3];
 #pragma unroll
@@ -213,6 +226,11 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
       if (4 * i4 + u < lim) s_q[4 * i4 + u] = x[u];
   }
   if (vec4 && 4 * nfull + tid < cnt) s_q[4 * nfull + tid] = qtail;
+#pragma unroll
+  for (int t = 0; t < OIT; ++t) {
+    const int i = tid + t * kThreads;
+    if (i < NDT + NLT) s_ops[i] = ov[t];
+  }
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
     const int i = tid + t * kThreads;
@@ -324,7 +342,7 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll 4
       for (int j = 0; j < NFP; ++j) {
         const int fm = f * NFP + j;
-        const float l = a.LT[fm * NP + n];
+        const float l = OPS_LDS ? s_ops[NDT + fm * NP + n] : a.LT[fm * NP + n];
 #pragma unroll
         for (int c = 0; c < NL; ++c) L[f][c] += l * lf[c * NFN + fm];
       }
@@ -333,9 +351,9 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
       float T0 = 0.f, T1 = 0.f, T2 = 0.f, dv = 0.f;
 #pragma unroll 4
       for (int m = 0; m < NP; ++m) {
-        const float d0 = a.DT[(0 * NP + m) * NP + n];
-        const float d1 = a.DT[(1 * NP + m) * NP + n];
-        const float d2 = a.DT[(2 * NP + m) * NP + n];
+        const float d0 = OPS_LDS ? s_ops[(0 * NP + m) * NP + n] : a.DT[(0 * NP + m) * NP + n];
+        const float d1 = OPS_LDS ? s_ops[(1 * NP + m) * NP + n] : a.DT[(1 * NP + m) * NP + n];
+        const float d2 = OPS_LDS ? s_ops[(2 * NP + m) * NP + n] : a.DT[(2 * NP + m) * NP + n];
         const float pm = qe[m];
         T0 += d0 * pm;
         T1 += d1 * pm;
@@ -361,7 +379,7 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
       for (int m = 0; m < NP; ++m) {
         float d[3];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) d[l] = a.DT[(l * NP + m) * NP + n];
+        for (int l = 0; l < 3; ++l) d[l] = OPS_LDS ? s_ops[(l * NP + m) * NP + n] : a.DT[(l * NP + m) * NP + n];
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
           const float vm = qe[ii * NP + m];
