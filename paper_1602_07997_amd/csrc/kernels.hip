@@ -73,10 +73,10 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
   __shared__ float s_cf[KT * CB];
   constexpr int FW = FaceRec<PHYS>::W;
   __shared__ float s_face[KT * 4 * FW];
-  // At the lowest degrees the operators (3 Np^2 + 4 Nfp Np floats, under
-  // 8 KB) are staged in LDS with the tile, so that the node loops read them
-  // at LDS latency instead of waiting on the cache for every k.
-  constexpr bool OPS_LDS = N <= 3;
+  // Up to N = 4 the operators (3 Np^2 + 4 Nfp Np floats, at most 23 KB) are
+  // staged in LDS with the tile, so that the node loops read them at LDS
+  // latency instead of waiting on the cache for every k.
+  constexpr bool OPS_LDS = N <= 4;
   constexpr int NDT = 3 * NP * NP, NLT = NFN * NP;
   __shared__ float s_ops[OPS_LDS ? NDT + NLT : 1];
 
