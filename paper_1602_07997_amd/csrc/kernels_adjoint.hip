@@ -137,12 +137,61 @@ dg_grad_accum_kernel(const GradArgs a) {
   const int64_t base = k * NF * NP;
   double* acc = a.gacc + k * kGradAccStride;
   const double old = lane < NACC ? acc[lane] : 0.0;
-  for (int i = lane; i < NF * NP; i += kWave) {
-    float v = a.c0 * a.phi1[base + i];
-    if (a.c1 != 0.0f) v += a.c1 * a.phi2[base + i];
-    if (a.c2 != 0.0f) v += a.c2 * a.phi3[base + i];
-    s_chi[i] = v;
-    s_r[i] = a.r[base + i];
+  // every global read of the element issued together, at clamped addresses
+  // (no load behind a branch): adjoint states and r, connectivity, own traces;
+  // then the permutation rows and the neighbour traces
+  constexpr int NIT = (NF * NP + kWave - 1) / kWave;
+  const float* p2 = a.c1 != 0.0f ? a.phi2 : a.phi1;  // read only where used
+  const float* p3 = a.c2 != 0.0f ? a.phi3 : a.phi1;
+  float x1[NIT], x2[NIT], x3[NIT], xr[NIT];
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = lane + t * kWave;
+    const int64_t ic = base + (i < NF * NP ? i : 0);
+    x1[t] = a.phi1[ic];
+    x2[t] = p2[ic];
+    x3[t] = p3[ic];
+    xr[t] = a.r[ic];
+  }
+  int word[FIT];
+  float own[FIT][NJ];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = lane + t * kWave;
+    const int ic = i < 4 * NFP ? i : 0;
+    const int f = ic / NFP, j = ic - f * NFP;
+    word[t] = a.conn[k * 4 + f];
+    const float* ow = a.tr + (k * 4 + f) * NT * NFP + j;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) own[t][c] = ow[c * NFP];
+  }
+  int jn[FIT];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = lane + t * kWave;
+    const int j = (i < 4 * NFP ? i : 0) % NFP;
+    const int o = (word[t] & 7) == 7 ? 0 : (word[t] & 7);
+    jn[t] = a.perm[o * NFP + j];
+  }
+  float nbv[FIT][NJ];
+#pragma unroll
+  for (int t = 0; t < FIT; ++t) {
+    const int i = lane + t * kWave;
+    const int ic = i < 4 * NFP ? i : 0;
+    const int f = ic / NFP, j = ic - f * NFP;
+    const bool wall = (word[t] & 7) == 7;
+    const int64_t kn = wall ? k : static_cast<int64_t>(word[t] >> 5);
+    const int fnb = wall ? f : (word[t] >> 3) & 3;
+    const float* nb = a.tr + (kn * 4 + fnb) * NT * NFP + (wall ? j : jn[t]);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) nbv[t][c] = nb[c * NFP];
+  }
+#pragma unroll
+  for (int t = 0; t < NIT; ++t) {
+    const int i = lane + t * kWave;
+    if (i >= NF * NP) continue;
+    s_chi[i] = a.c0 * x1[t] + a.c1 * x2[t] + a.c2 * x3[t];
+    s_r[i] = xr[t];
   }
   float G[9];
 #pragma unroll
@@ -154,31 +203,21 @@ dg_grad_accum_kernel(const GradArgs a) {
     const int i = lane + t * kWave;
     if (i >= 4 * NFP) continue;
     const int f = i / NFP, j = i - f * NFP;
-    const int word = a.conn[k * 4 + f];
-    const bool wall = (word & 7) == 7;
-    const float* own = a.tr + (k * 4 + f) * NT * NFP;
-    const float* nbr = own;
-    int jn = 0;
-    if (!wall) {
-      const int64_t kn = static_cast<int64_t>(word >> 5);
-      const int fnb = (word >> 3) & 3;
-      jn = a.perm[(word & 7) * NFP + j];
-      nbr = a.tr + (kn * 4 + fnb) * NT * NFP;
-    }
+    const bool wall = (word[t] & 7) == 7;
     float* sj = s_jump + f * NJ * NFP;
     if constexpr (PHYS == 0) {
-      const float pM = own[j], vnM = own[NFP + j];
-      const float pP = wall ? pM : nbr[jn];
-      const float vnP = wall ? -vnM : -nbr[NFP + jn];
+      const float pM = own[t][0], vnM = own[t][1];
+      const float pP = wall ? pM : nbv[t][0];
+      const float vnP = wall ? -vnM : -nbv[t][1];
       const float jp = 0.5f * (pP - pM), jv = 0.5f * (vnP - vnM);
       sj[j] = jp - cf[4 + f] * jv;  // alpha, Z+ of this face
       sj[NFP + j] = jv;
     } else {
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
-        const float vM = own[ii * NFP + j], tM = own[(3 + ii) * NFP + j];
-        const float vP = wall ? vM : nbr[ii * NFP + jn];
-        const float tP = wall ? -tM : -nbr[(3 + ii) * NFP + jn];
+        const float vM = own[t][ii], tM = own[t][3 + ii];
+        const float vP = wall ? vM : nbv[t][ii];
+        const float tP = wall ? -tM : -nbv[t][3 + ii];
         sj[ii * NFP + j] = 0.5f * (vP - vM);
         sj[(3 + ii) * NFP + j] = 0.5f * (tP - tM);
       }
@@ -193,6 +232,7 @@ dg_grad_accum_kernel(const GradArgs a) {
 #pragma unroll
     for (int c = 0; c < NF; ++c) mr[c] = 0.f;
     // M is symmetric: column n of M, contiguous across the lanes
+#pragma unroll 8
     for (int m = 0; m < NP; ++m) {
       const float w = a.mass[m * NP + n];
 #pragma unroll
