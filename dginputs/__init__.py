@@ -144,6 +144,33 @@ def _vectorised_ids(corners, nx, ny, nz, periodic):
     return (i * (ny + 1) + j) * (nz + 1) + k
 
 
+_EVEN_PERMS4 = [
+    p for p in itertools.permutations(range(4))
+    if sum(1 for i in range(4) for j in range(i + 1, 4) if p[i] > p[j]) % 2 == 0
+]
+
+
+def relabel_vertices(mesh: TetMesh, seed: int) -> TetMesh:
+    """The same mesh with every element's vertices listed in a random even order.
+
+    An even permutation keeps each element positively oriented, and the
+    physical mesh (and so the discrete solution, up to node numbering) is
+    unchanged; only the local vertex numbering moves, which makes the shared
+    faces of neighbours meet under all six relative orientations instead of
+    the two that a Kuhn split produces.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = np.asarray(_EVEN_PERMS4, dtype=np.int64)[rng.integers(0, len(_EVEN_PERMS4), size=mesh.K)]
+    rows = np.arange(mesh.K)[:, None]
+    return TetMesh(
+        elem_xyz=np.ascontiguousarray(mesh.elem_xyz[rows, pick]),
+        elem_topo=np.ascontiguousarray(mesh.elem_topo[rows, pick]),
+        period=mesh.period,
+        dims=mesh.dims,
+        lengths=mesh.lengths,
+    )
+
+
 def element_centroids(mesh: TetMesh) -> np.ndarray:
     return mesh.elem_xyz.mean(axis=1)
 

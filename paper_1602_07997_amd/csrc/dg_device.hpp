@@ -102,6 +102,27 @@ __device__ __forceinline__ void face_record(const float* __restrict__ G, const f
   }
 }
 
+// Face node of the neighbour's face that meets own face node j under the
+// relative orientation o (0..5): own node j <-> (a, b) with b the outer index
+// of the face lattice, barycentric beta = (N - a - b, a, b) on the own face's
+// vertices; own vertex p is the neighbour's vertex P_o[p] for the six
+// permutations P = (012, 021, 102, 120, 201, 210), so the neighbour's
+// (a', b') = (beta[p1], beta[p2]) with P_o[p1] = 1, P_o[p2] = 2.  The same
+// numbering as the host-built permutation rows, computed in registers.
+__host__ __device__ __forceinline__ int face_perm_node(int N, int o, int j) {
+  // row b of the face lattice starts at S(b) = b (N + 1) - b (b - 1) / 2
+  int b = 0;
+  for (int bb = 1; bb <= N; ++bb) b += (j >= bb * (N + 1) - bb * (bb - 1) / 2) ? 1 : 0;
+  const int a = j - (b * (N + 1) - b * (b - 1) / 2);
+  const int beta0 = N - a - b, beta1 = a, beta2 = b;
+  // p1, p2 per orientation: (1,2) (2,1) (0,2) (0,1) (2,0) (1,0)
+  const int p1 = (o == 0 || o == 5) ? 1 : ((o == 1 || o == 4) ? 2 : 0);
+  const int p2 = (o == 0 || o == 2) ? 2 : ((o == 1 || o == 3) ? 1 : 0);
+  const int a2 = p1 == 0 ? beta0 : (p1 == 1 ? beta1 : beta2);
+  const int b2 = p2 == 0 ? beta0 : (p2 == 1 ? beta1 : beta2);
+  return b2 * (N + 1) - b2 * (b2 - 1) / 2 + a2;
+}
+
 __device__ __forceinline__ int64_t tile_of_block(int xcd_remap) {
   const int64_t b = blockIdx.x;
   if (!xcd_remap) return b;

@@ -89,9 +89,9 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
   // ---- phase A: issue every global load before the first barrier ----------
   // Loads are unconditional at clamped (in-range) addresses and unused values
   // are dropped by selects, so that no load waits behind a branch or behind
-  // another item's load.  Three dependent rounds: (1) everything indexed by
-  // the tile alone, (2) the face-node permutation of each face item, (3) the
-  // neighbour traces.
+  // another item's load.  Two dependent rounds: (1) everything indexed by
+  // the tile alone, then, once the connectivity words are in and the face-node
+  // permutation is formed in registers (2), (3) the neighbour traces.
   constexpr int QV = (KT * NF * NP + 4 * kThreads - 1) / (4 * kThreads);  // float4 per thread
   constexpr int GIT = (KT * 9 + kThreads - 1) / kThreads;
   constexpr int CIT = (KT * CB + kThreads - 1) / kThreads;
@@ -188,7 +188,7 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
     for (int s = 0; s < 3; ++s) nfs[t][s] = a.nodeface[n * 3 + s];
   }
-  // (2) permuted face node on the neighbour's side
+  // (2) permuted face node on the neighbour's side (arithmetic, no load)
   int jn[FIT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
@@ -197,7 +197,7 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
     const int e = ok ? i / NFN : 0, fn = ok ? i - e * NFN : 0;
     const int j = fn - (fn / NFP) * NFP;
     const int o = (word[t] & 7) == 7 ? 0 : (word[t] & 7);
-    jn[t] = a.perm[o * NFP + j];
+    jn[t] = face_perm_node(N, o, j);
   }
   // (3) neighbour traces (a wall reads its own, in range and unused)
   float nbt[FIT][NT];

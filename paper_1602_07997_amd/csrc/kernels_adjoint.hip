@@ -139,7 +139,8 @@ dg_grad_accum_kernel(const GradArgs a) {
   const double old = lane < NACC ? acc[lane] : 0.0;
   // every global read of the element issued together, at clamped addresses
   // (no load behind a branch): adjoint states and r, connectivity, own traces;
-  // then the permutation rows and the neighbour traces
+  // then, with the face-node permutation formed in registers, the neighbour
+  // traces
   constexpr int NIT = (NF * NP + kWave - 1) / kWave;
   const float* p2 = a.c1 != 0.0f ? a.phi2 : a.phi1;  // read only where used
   const float* p3 = a.c2 != 0.0f ? a.phi3 : a.phi1;
@@ -171,7 +172,7 @@ dg_grad_accum_kernel(const GradArgs a) {
     const int i = lane + t * kWave;
     const int j = (i < 4 * NFP ? i : 0) % NFP;
     const int o = (word[t] & 7) == 7 ? 0 : (word[t] & 7);
-    jn[t] = a.perm[o * NFP + j];
+    jn[t] = face_perm_node(N, o, j);
   }
   float nbv[FIT][NJ];
 #pragma unroll

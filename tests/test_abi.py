@@ -64,9 +64,12 @@ def test_product_operators_differentiate_monomials(N):
             np.testing.assert_allclose(ops["D"][0] @ u, du, atol=1e-11)
 
 
+@pytest.mark.parametrize("relabel", [False, True])
 @pytest.mark.parametrize("periodic", [False, True])
-def test_connectivity_and_face_permutations_match_oracle(periodic):
+def test_connectivity_and_face_permutations_match_oracle(periodic, relabel):
     m = di.kuhn_box(3, 4, 3, jitter=0.1, seed=7, periodic=periodic)
+    if relabel:  # random even vertex orders: shared faces meet in all six orientations
+        m = di.relabel_vertices(m, seed=9)
     for N in (2, 5):
         geo = build_mesh(N, m.elem_xyz, m.elem_topo, m.period)
         e2e, e2f, orient = mesh_connectivity(m.elem_topo)
@@ -77,6 +80,7 @@ def test_connectivity_and_face_permutations_match_oracle(periodic):
         assert np.all(orient[k, f] >= 0)
         assert np.array_equal(perm[orient[k, f]], geo.nbr_node[k, f])
         assert np.all(orient[geo.wall] == -1)
+        assert set(np.unique(orient[k, f]).tolist()) == (set(range(6)) if relabel else {0, 1})
 
 
 def test_permutations_are_permutations():

@@ -247,3 +247,32 @@ def test_elem_variant_periodic_and_rejected_above_its_degrees():
     with pytest.raises(DGError) as ei:
         d.solver.variant = "elem"
     assert ei.value.status == DG_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("physics", ["acoustic", "elastic"])
+@pytest.mark.parametrize("variant,N,periodic", [
+    ("elem", 1, False), ("valu", 2, False), ("valu", 4, True), ("valu", 6, False),
+    ("mfma", 3, True), ("mfma", 5, False), ("mfma", 8, False), ("mfma_f16", 4, False),
+])
+def test_all_face_orientations_parity(physics, variant, N, periodic):
+    """Elements whose vertices are listed in random even orders, so that
+    shared faces meet under all six relative orientations (a Kuhn split alone
+    gives two): one right-hand side and 20 AB3 steps against the oracle."""
+    from dginputs import kuhn_box, relabel_vertices
+
+    log(f"all orientations {physics} {variant} N={N} periodic={periodic}")
+    dims = (3, 2, 3) if N <= 4 else (2, 2, 2)
+    mesh = relabel_vertices(kuhn_box(*dims, jitter=0.1, seed=80 + N, periodic=periodic), seed=90 + N)
+    c = Case(physics, N, 0, coef_kind="random", init="smooth", mesh=mesh, seed=80 + N)
+    c.solver.variant = variant
+    assert c.solver.variant == variant
+    r = c.solver.rhs(c.to_gpu(c.q0_gpu))
+    torch.cuda.synchronize()
+    err_r, _ = c.rel_l2(c.to_host(r), c.oracle.rhs(c.q0))
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    c.solver.step(20, c.dt)
+    q = c.to_host(c.solver.get_fields())
+    err_q, _ = c.rel_l2(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt))
+    log(f"  rhs rel L2 {err_r:.3e}, 20 steps {err_q:.3e}")
+    tol_r, tol_q = (1e-4, 1e-4) if variant == "mfma_f16" else (2e-6, 1e-5)
+    assert err_r <= tol_r and err_q <= tol_q

@@ -82,3 +82,22 @@ def test_physical_gradient_exact_for_polynomials(N):
     grad = np.einsum("kij,kjn->kin", geo.G, Du)
     for i in range(3):
         np.testing.assert_allclose(grad[:, i], du[i], atol=1e-10)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_relabelled_vertices_pair_faces_in_all_six_orientations(periodic):
+    """Random even vertex orders per element make shared faces meet under all
+    six relative orientations; paired face nodes still coincide in space."""
+    m = di.relabel_vertices(di.kuhn_box(3, periodic=periodic, jitter=0.05, seed=5), seed=11)
+    dets = np.linalg.det(np.stack([m.elem_xyz[:, i] - m.elem_xyz[:, 0] for i in (1, 2, 3)], axis=-1))
+    assert np.all(dets > 0.0)
+    for N in (1, 3, 4):
+        geo = build_mesh(N, m.elem_xyz, m.elem_topo, m.period)
+        k, f = np.nonzero(~geo.wall)
+        patterns = {tuple(r) for r in geo.nbr_node[k, f]}
+        assert len(patterns) == 6
+        xf = geo.xyz[:, geo.ref.Fmask]
+        d = xf[k, f] - xf[geo.EToE[k, f], geo.EToF[k, f]][np.arange(len(k))[:, None], geo.nbr_node[k, f]]
+        if periodic:
+            d -= np.round(d)
+        np.testing.assert_allclose(d, 0.0, atol=1e-13)

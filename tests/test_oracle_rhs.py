@@ -220,3 +220,35 @@ def test_energy_rate_nonpositive(physics, periodic, N):
         q = np.zeros((geo.K, o.nfields, geo.ref.Np))
         q[:, 0] = 1.0
         assert abs(o.energy_rate(q)) < 1e-11
+
+
+@pytest.mark.parametrize("physics", ["acoustic", "elastic"])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_rhs_invariant_under_vertex_relabelling(physics, periodic):
+    """Listing each element's vertices in another even order changes no
+    physical quantity: on a discontinuous state (a per-element phase, so every
+    face carries a jump) the right-hand side at each physical node is the same,
+    which pins the face-node pairing under all six orientations."""
+    N = 3
+    m = di.kuhn_box(3, periodic=periodic, jitter=0.1, seed=4)
+    r = di.relabel_vertices(m, seed=3)
+    g0 = build_mesh(N, m.elem_xyz, m.elem_topo, m.period)
+    g1 = build_mesh(N, r.elem_xyz, r.elem_topo, r.period)
+    # node i of element k in the original numbering is node pi[k, i] after relabelling
+    dist = np.linalg.norm(g0.xyz[:, :, None, :] - g1.xyz[:, None, :, :], axis=-1)
+    pi = dist.argmin(axis=2)
+    assert dist.min(axis=2).max() < 1e-12
+    nf = 4 if physics == "acoustic" else 9
+    phase = np.random.Generator(np.random.PCG64(8)).uniform(0.0, 6.0, size=(m.K, nf))
+
+    def state(x):
+        return np.stack(
+            [np.sin(phase[:, c, None] + 2.3 * x[..., 0] - 1.1 * x[..., 1] + (0.7 + 0.2 * c) * x[..., 2])
+             for c in range(nf)], axis=1)
+
+    coef = di.acoustic_loguniform(m, 1) if physics == "acoustic" else di.elastic_loguniform(m, 2)
+    O = AcousticOracle if physics == "acoustic" else ElasticOracle
+    r0 = O(g0, coef).rhs(state(g0.xyz))
+    r1 = O(g1, coef).rhs(state(g1.xyz))
+    r1_in_0 = r1[np.arange(m.K)[:, None, None], np.arange(nf)[None, :, None], pi[:, None, :]]
+    np.testing.assert_allclose(r1_in_0, r0, atol=1e-10 * np.abs(r0).max())
