@@ -20,7 +20,7 @@
 // penalties) are formed and split once per tile in LDS.  Fields, r and the
 // update stay FP32.
 //
-// Phases of one workgroup (4 wavefronts):
+// Phases of one workgroup (4 wavefronts; 6 or 8 at N >= 6):
 //   A1  every global read indexed by the tile alone (constants, connectivity
 //       words, own traces, fields), issued together; constants into LDS;
 //   A2  neighbour traces and the upwind alpha of every face node (kept in
@@ -52,6 +52,15 @@ using namespace mfma;
 constexpr int kPrefetch = 4;
 constexpr int kPrefetch16 = 1;
 
+// wavefronts per workgroup: one per (node block, element block) pair where
+// that fits the tile (N = 6: six pairs, N = 7: eight), which also leaves
+// fewer accumulators per wavefront and so more resident wavefronts; at N = 8
+// the split 16-bit products take eight wavefronts for eleven pairs, the FP32
+// ones keep four (measured faster each way)
+constexpr int acoustic_waves(int N, int PREC) {
+  return N == 6 ? 6 : (N == 7 ? 8 : ((N == 8 && PREC != 0) ? 8 : 4));
+}
+
 template <int N, int PREC>
 struct MShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
@@ -63,6 +72,8 @@ struct MShape {
   static constexpr int NBLK = (N <= 2) ? 4 : (N == 3 ? 2 : 1);
   static constexpr int E = 16 * NBLK;            // elements per tile
   static constexpr int PAIRS = MB * NBLK;
+  static constexpr int NW = acoustic_waves(N, PREC);  // wavefronts per workgroup
+  static constexpr int THREADS = 64 * NW;
   // 4-byte words of B operands: four volume sets of KP rows, then (reused)
   // two penalty sets of KL rows
   static constexpr int REGION = (4 * KP > 2 * KL ? 4 * KP : 2 * KL) * E;
@@ -96,16 +107,17 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
   constexpr int NF = 4, NT = 2, CB = 8;
   constexpr int FW = FaceRec<0>::W;
-  constexpr int NIT = (E * KP + kThreads - 1) / kThreads;  // node items (incl. padding) per thread
-  constexpr int FIT = (E * KL + kThreads - 1) / kThreads;  // face-slot items (incl. padding) per thread
-  constexpr int SCR = 16 * 17;                             // per-wave transpose scratch
-  constexpr int PPW = (S::PAIRS + 3) / 4;                  // pairs per wavefront (at most)
+  constexpr int NW = S::NW, TH = S::THREADS;
+  constexpr int NIT = (E * KP + TH - 1) / TH;  // node items (incl. padding) per thread
+  constexpr int FIT = (E * KL + TH - 1) / TH;  // face-slot items (incl. padding) per thread
+  constexpr int SCR = 16 * 17;                 // per-wave transpose scratch
+  constexpr int PPW = (S::PAIRS + NW - 1) / NW;  // pairs per wavefront (at most)
 
   __shared__ __attribute__((aligned(16))) float s_B[S::REGION];
   __shared__ float s_g[E * 9];
   __shared__ float s_cf[E * CB];
   __shared__ float s_face[E * 4 * FW];
-  __shared__ float s_scr[4 * SCR];
+  __shared__ float s_scr[NW * SCR];
 
   const int64_t e0 = tile * E;
   if (e0 >= a.K) return;  // whole workgroup exits together
@@ -124,27 +136,27 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   // Each load is unconditional at a clamped, in-range address and unused
   // values are dropped by selects, so that no load waits behind a branch or
   // behind another item's load: the phase costs one memory round trip.
-  constexpr int GIT = (E * 9 + kThreads - 1) / kThreads;
-  constexpr int CIT = (E * CB + kThreads - 1) / kThreads;
-  constexpr int PIT = (6 * NFP + kThreads - 1) / kThreads;
-  static_assert(6 * NFP <= 4 * SCR, "the permutation table borrows the transpose scratch");
-  static_assert(E * 4 <= kThreads, "one face record per thread");
+  constexpr int GIT = (E * 9 + TH - 1) / TH;
+  constexpr int CIT = (E * CB + TH - 1) / TH;
+  constexpr int PIT = (6 * NFP + TH - 1) / TH;
+  static_assert(6 * NFP <= NW * SCR, "the permutation table borrows the transpose scratch");
+  static_assert(E * 4 <= TH, "one face record per thread");
   int* s_perm = reinterpret_cast<int*>(s_scr);  // free until the epilogue
   float gv[GIT], cv[CIT];
   int pv[PIT];
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     gv[t] = (a.geo + e0 * 9)[i < ne * 9 ? i : ne * 9 - 1];
   }
 #pragma unroll
   for (int t = 0; t < CIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     cv[t] = (a.cf + e0 * CB)[i < ne * CB ? i : ne * CB - 1];
   }
 #pragma unroll
   for (int t = 0; t < PIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     pv[t] = a.perm[i < 6 * NFP ? i : 6 * NFP - 1];
   }
   // connectivity word of this thread's face record (e, f) = (tid / 4, tid % 4)
@@ -158,7 +170,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   int cw[FIT];
   float pM[FIT], vnM[FIT];
   auto load_own = [&](int t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     const int e = i / KL, slot = i - e * KL;
     const int fs = slot / KF, js = slot - fs * KF;
     const bool ok = e < ne && js < NFP;
@@ -169,7 +181,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   };
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     const int e = i / KL, slot = i - e * KL;
     const int fs = slot / KF;
     const bool ok = e < ne && slot - fs * KF < NFP;
@@ -182,7 +194,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   constexpr int NIT1 = (PREC == 0 && N >= 7) ? NIT : (NIT < 6 ? NIT : 6);
   float qv[NIT][NF];
   auto load_node = [&](int t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     const int e = i / KP, n = i - e * KP;
     const bool ok = i < E * KP && e < ne && n < NP;
     const float* qe = tq + ((ok ? e : 0) * NF * NP + (ok ? n : 0));
@@ -198,7 +210,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   if constexpr (RAW) {
 #pragma unroll
     for (int t = 0; t < NIT1; ++t) {
-      const int i = tid + t * kThreads;
+      const int i = tid + t * TH;
       if (i >= E * KP) continue;
       const int e = i / KP, n = i - e * KP;
       const bool ok = e < ne && n < NP;
@@ -208,17 +220,17 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   }
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     if (i < ne * 9) s_g[i] = gv[t];
   }
 #pragma unroll
   for (int t = 0; t < CIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     if (i < ne * CB) s_cf[i] = cv[t];
   }
 #pragma unroll
   for (int t = 0; t < PIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     if (i < 6 * NFP) s_perm[i] = pv[t];
   }
   __syncthreads();
@@ -237,7 +249,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
       for (int u = t; u < t + FCH && u < FIT; ++u) load_own(u);
     }
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     const int e = i / KL, slot = i - e * KL;
     const int fs = slot / KF, js = slot - fs * KF;
     const bool ok = e < ne && js < NFP;
@@ -264,7 +276,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   if (rec_e < ne) face_record<0>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
 #pragma unroll
   for (int t = 0; t < NIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     if (i >= E * KP) continue;
     const int e = i / KP, n = i - e * KP;
     float v0, v1, v2;
@@ -297,7 +309,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   floatx4 T0[PPW], T1[PPW], T2[PPW], DV[PPW];
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
-    const int p = wave + 4 * q;
+    const int p = wave + NW * q;
     T0[q] = T1[q] = T2[q] = DV[q] = floatx4{0, 0, 0, 0};
     if (p >= S::PAIRS) continue;
     const int mb = p % MB, nb = p / MB;
@@ -387,7 +399,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   // ---- B2: penalty operands (the region is reused) -------------------------
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
-    const int i = tid + t * kThreads;
+    const int i = tid + t * TH;
     if (i >= E * KL) continue;
     const int e = i / KL, slot = i - e * KL;
     float fp = 0.f, fv = 0.f;
@@ -407,7 +419,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   const int nl = lane & 15, eg = lane >> 4;
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
-    const int p = wave + 4 * q;
+    const int p = wave + NW * q;
     if (p >= S::PAIRS) continue;
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + nl;
@@ -563,13 +575,13 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__((MShape<N, PREC>::THREADS))
 dg_step_mfma_acoustic(StepArgs a) {
   step_mfma_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__((MShape<N, PREC>::THREADS))
 dg_step_mfma_acoustic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
@@ -581,7 +593,7 @@ template <int N, int PREC>
 hipError_t mfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(kThreads), 0,
+  hipLaunchKernelGGL((dg_step_mfma_acoustic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(MShape<N, PREC>::THREADS), 0,
                      s, args, work, phase);
   return hipGetLastError();
 }
@@ -592,7 +604,7 @@ hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
   int64_t tiles = (a.K + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(MShape<N, PREC>::THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@
 //   dv_i/dx_j = sum_l g_jl Dv_il.
 // Precisions as in the acoustic kernel: FP32 16x16x4, or BF16 / FP16
 // 16x16x16 with both operands split hi + lo and three products accumulated in
-// FP32.  Workgroups of 8 wavefronts; phases:
+// FP32.  Workgroups of 8 wavefronts (4 for the 16-bit products at N = 5);
+// phases:
 //   A1  every global read indexed by the tile alone, issued together;
 //       constants into LDS;
 //   A2  neighbour traces; face records; the five LIFT operands of every face
@@ -43,7 +44,14 @@ namespace {
 using namespace dev;
 using namespace mfma;
 
-constexpr int kEThreads = 512;  // eight wavefronts
+// eight wavefronts per workgroup; four for the split 16-bit products at
+// N = 5, whose tile has only four (node block, element block) pairs, so that
+// no wavefront idles through the products and two workgroups share a compute
+// unit (measured: ~20% faster there, neutral or slower elsewhere)
+template <int N, int PREC>
+constexpr int elastic_threads() {
+  return (N == 5 && PREC != 0) ? 256 : 512;
+}
 
 template <int N, int PREC>
 struct EShape {
@@ -58,6 +66,7 @@ struct EShape {
   static constexpr int PAIRS = MB * NBLK;
   static constexpr int NSV = 9;  // volume operand sets (the fields)
   static constexpr int NSL = 5;  // LIFT operand sets (the lifted penalty scalars)
+  static constexpr int THREADS = elastic_threads<N, PREC>();
   // 4-byte words: the LIFT sets, then (reused) the volume sets
   static constexpr int REGION = (NSV * KP > NSL * KL ? NSV * KP : NSL * KL) * E;
 };
@@ -113,9 +122,10 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
   constexpr int NF = 9, NT = 6, CB = 16;
   constexpr int FW = FaceRec<1>::W;
-  constexpr int NW = kEThreads / 64;
-  constexpr int NIT = (E * KP + kEThreads - 1) / kEThreads;
-  constexpr int FIT = (E * KL + kEThreads - 1) / kEThreads;
+  constexpr int TH = S::THREADS;
+  constexpr int NW = TH / 64;
+  constexpr int NIT = (E * KP + TH - 1) / TH;
+  constexpr int FIT = (E * KL + TH - 1) / TH;
   constexpr int SCR = 16 * 17;
   constexpr int PPW = (S::PAIRS + NW - 1) / NW;
 
@@ -139,27 +149,27 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   // Loads are unconditional at clamped (in-range) addresses and unused values
   // are dropped by selects, so that none waits behind a branch or behind
   // another item's load.
-  constexpr int GIT = (E * 9 + kEThreads - 1) / kEThreads;
-  constexpr int CIT = (E * CB + kEThreads - 1) / kEThreads;
-  constexpr int PIT = (6 * NFP + kEThreads - 1) / kEThreads;
+  constexpr int GIT = (E * 9 + TH - 1) / TH;
+  constexpr int CIT = (E * CB + TH - 1) / TH;
+  constexpr int PIT = (6 * NFP + TH - 1) / TH;
   static_assert(6 * NFP <= NW * SCR, "the permutation table borrows the transpose scratch");
-  static_assert(E * 4 <= kEThreads, "one face record per thread");
+  static_assert(E * 4 <= TH, "one face record per thread");
   int* s_perm = reinterpret_cast<int*>(s_scr);  // free until the epilogue
   float gv[GIT], cv[CIT];
   int pv[PIT];
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     gv[t] = a.geo[e0 * 9 + (i < ne * 9 ? i : 0)];
   }
 #pragma unroll
   for (int t = 0; t < CIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     cv[t] = a.cf[e0 * CB + (i < ne * CB ? i : 0)];
   }
 #pragma unroll
   for (int t = 0; t < PIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     pv[t] = a.perm[i < 6 * NFP ? i : 0];
   }
   const int rec_e = tid >> 2, rec_f = tid & 3;
@@ -170,7 +180,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   float ot[FIT][NT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     const int e = i / KL, slot = i - e * KL;
     const int fs = slot / KF, js = slot - fs * KF;
     const bool ok = e < ne && js < NFP;
@@ -182,17 +192,17 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   }
 #pragma unroll
   for (int t = 0; t < GIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     if (i < ne * 9) s_g[i] = gv[t];
   }
 #pragma unroll
   for (int t = 0; t < CIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     if (i < ne * CB) s_cf[i] = cv[t];
   }
 #pragma unroll
   for (int t = 0; t < PIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     if (i < 6 * NFP) s_perm[i] = pv[t];
   }
   __syncthreads();
@@ -201,7 +211,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   float nt[FIT][NT];
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     const int e = i / KL, slot = i - e * KL;
     const int fs = slot / KF, js = slot - fs * KF;
     const bool ok = e < ne && js < NFP;
@@ -220,7 +230,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
-    const int i = tid + t * kEThreads;
+    const int i = tid + t * TH;
     if (i >= E * KL) continue;
     const int e = i / KL, slot = i - e * KL;
     // the five lifted scalars of Sec. 2.1's elastic penalty (jumps halved):
@@ -375,7 +385,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     float x[BB][9];
 #pragma unroll
     for (int u = 0; u < BB; ++u) {
-      const int i = tid + (t0 + u) * kEThreads;
+      const int i = tid + (t0 + u) * TH;
       const int e = i / KP, n = i - e * KP;
       const bool ok = t0 + u < NIT && i < E * KP && e < ne && n < NP;
       const float* qe = a.q_in + (e0 + (ok ? e : 0)) * NF * NP + (ok ? n : 0);
@@ -384,7 +394,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     }
 #pragma unroll
     for (int u = 0; u < BB; ++u) {
-      const int i = tid + (t0 + u) * kEThreads;
+      const int i = tid + (t0 + u) * TH;
       if (t0 + u >= NIT || i >= E * KP) continue;
       const int e = i / KP, n = i - e * KP;
       const bool ok = e < ne && n < NP;
@@ -585,13 +595,13 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__(kEThreads)
+__global__ void __launch_bounds__((elastic_threads<N, PREC>()))
 dg_step_mfma_elastic(StepArgs a) {
   step_mfma_elastic_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__(kEThreads)
+__global__ void __launch_bounds__((elastic_threads<N, PREC>()))
 dg_step_mfma_elastic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
@@ -605,7 +615,7 @@ hipError_t emfma_impl(const StepArgs& a, hipStream_t s) {
   int64_t tiles = (a.K + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(kEThreads), 0, s, a);
+  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(elastic_threads<N, PREC>()), 0, s, a);
   return hipGetLastError();
 }
 
@@ -613,7 +623,7 @@ template <int N, int PREC>
 hipError_t emfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_elastic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(kEThreads), 0,
+  hipLaunchKernelGGL((dg_step_mfma_elastic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(elastic_threads<N, PREC>()), 0,
                      s, args, work, phase);
   return hipGetLastError();
 }
