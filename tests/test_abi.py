@@ -83,6 +83,13 @@ def test_connectivity_and_face_permutations_match_oracle(periodic, relabel):
         assert set(np.unique(orient[k, f]).tolist()) == (set(range(6)) if relabel else {0, 1})
 
 
+def test_mass_matrix_is_exactly_symmetric():
+    # the energy kernel reads row n of M as column n
+    for N in range(1, 9):
+        M = reference_operators(N)["mass"]
+        assert np.array_equal(M, M.T)
+
+
 def test_permutations_are_permutations():
     for N in range(1, 9):
         perm = reference_operators(N)["perm"]
