@@ -18,8 +18,8 @@
 //   dv_i/dx_j = sum_l g_jl Dv_il.
 // Precisions as in the acoustic kernel: FP32 16x16x4, or BF16 / FP16
 // 16x16x16 with both operands split hi + lo and three products accumulated in
-// FP32.  Workgroups of 8 wavefronts (4 for the 16-bit products at N = 5);
-// phases:
+// FP32.  Workgroups of 8 wavefronts (4 for the 16-bit products at N = 5,
+// 12 for FP32 at N = 8); phases:
 //   A1  every global read indexed by the tile alone, issued together;
 //       constants into LDS;
 //   A2  neighbour traces; face records; the five LIFT operands of every face
@@ -47,10 +47,12 @@ using namespace mfma;
 // eight wavefronts per workgroup; four for the split 16-bit products at
 // N = 5, whose tile has only four (node block, element block) pairs, so that
 // no wavefront idles through the products and two workgroups share a compute
-// unit (measured: ~20% faster there, neutral or slower elsewhere)
+// unit (measured: ~20% faster there, neutral or slower elsewhere); twelve for
+// the FP32 products at N = 8, whose eleven pairs then take one round instead
+// of two (5% faster despite a few spilled registers; neutral for 16-bit)
 template <int N, int PREC>
 constexpr int elastic_threads() {
-  return (N == 5 && PREC != 0) ? 256 : 512;
+  return (N == 5 && PREC != 0) ? 256 : ((N == 8 && PREC == 0) ? 768 : 512);
 }
 
 template <int N, int PREC>
