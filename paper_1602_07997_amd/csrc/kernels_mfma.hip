@@ -61,6 +61,15 @@ constexpr int acoustic_waves(int N, int PREC) {
   return N == 6 ? 6 : (N == 7 ? 8 : ((N == 8 && PREC != 0) ? 8 : 4));
 }
 
+// resident wavefronts per SIMD that the register allocation must allow: the
+// staging phases of N = 4, 5 are latency-bound, and the compiler fits them
+// in 78 / 96 registers without spilling when asked (six / five workgroups
+// per compute unit instead of four: 2-8% faster); the FP16 split products
+// would spill, so they keep the default
+constexpr int acoustic_min_waves(int N, int PREC) {
+  return (N == 4 && PREC == 0) ? 6 : ((N == 4 || N == 5) && PREC != 2 ? 5 : 1);
+}
+
 template <int N, int PREC>
 struct MShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
@@ -575,13 +584,13 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__((MShape<N, PREC>::THREADS))
+__global__ void __launch_bounds__((MShape<N, PREC>::THREADS), (acoustic_min_waves(N, PREC)))
 dg_step_mfma_acoustic(StepArgs a) {
   step_mfma_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__((MShape<N, PREC>::THREADS))
+__global__ void __launch_bounds__((MShape<N, PREC>::THREADS), (acoustic_min_waves(N, PREC)))
 dg_step_mfma_acoustic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
