@@ -81,6 +81,19 @@ def test_energy_parity(physics, N):
 
 
 @pytest.mark.parametrize("physics", ["acoustic", "elastic"])
+@pytest.mark.parametrize("N", [6, 7, 8])
+def test_energy_parity_ragged_element_groups(physics, N):
+    """30 elements: the energy kernel's element groups (8 or 4 elements per
+    item from N = 6 / 7) and its tiles end part-way through."""
+    log(f"energy parity, ragged groups, {physics} N={N}")
+    c = Case(physics, N, 0, jitter=0.1, seed=40 + N, coef_kind="random", init="smooth", dims=(5, 1, 1))
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    e = c.solver.energy()
+    e_ref = c.oracle.energy(c.q0)
+    assert abs(e - e_ref) <= 1e-9 * e_ref
+
+
+@pytest.mark.parametrize("physics", ["acoustic", "elastic"])
 def test_periodic_plane_wave_parity(physics):
     log(f"periodic parity {physics}")
     c = Case(physics, 3, 3, jitter=0.05, seed=3, coef_kind="random", periodic=True, init="smooth")
