@@ -20,7 +20,8 @@
 // penalties) are formed and split once per tile in LDS.  Fields, r and the
 // update stay FP32.
 //
-// Phases of one workgroup (4 wavefronts; 6 or 8 at N >= 6):
+// Phases of one workgroup (4 wavefronts; 6 at N = 6, 8 at N = 7 and for the
+// 16-bit products at N = 8):
 //   A1  every global read indexed by the tile alone (constants, connectivity
 //       words, own traces, fields), issued together; constants into LDS;
 //   A2  neighbour traces and the upwind alpha of every face node (kept in
@@ -48,8 +49,11 @@ namespace {
 using namespace dev;
 using namespace mfma;
 
-// k-steps of operator prefetch in the FP32 and the 16-bit products
-constexpr int kPrefetch = 4;
+// k-steps of operator prefetch in the FP32 products (the LIFT stream takes
+// twice as many) and in the 16-bit ones; the shallower FP32 depth at
+// N = 5..7 leaves registers for more resident wavefronts (measured 1-4%
+// faster there, 3% slower at N = 8)
+constexpr int prefetch_fp32(int N) { return (N >= 5 && N <= 7) ? 2 : 4; }
 constexpr int kPrefetch16 = 1;
 
 // wavefronts per workgroup: one per (node block, element block) pair where
@@ -330,7 +334,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
       // loads of the next group of PD k-steps are issued before the products
       // of the current group (the scheduling barrier keeps them there), so
       // their latency overlaps PD k-steps of products.
-      constexpr int NK = KP / 4, PD = NK < kPrefetch ? NK : kPrefetch;
+      constexpr int NK = KP / 4, PD = NK < prefetch_fp32(N) ? NK : prefetch_fp32(N);
       using R = Ring<float, PD, 3>;
       auto load = [&](R& r, int g) {
 #pragma unroll
@@ -440,7 +444,7 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     for (int f = 0; f < 4; ++f) LV[f] = floatx4{0, 0, 0, 0};
     if constexpr (PREC == 0) {
       const float* Lp = a.Lpack + static_cast<int64_t>(mb) * (KL / 4) * 64 + lane;
-      constexpr int NK = KL / 4, PD = NK < 2 * kPrefetch ? NK : 2 * kPrefetch;
+      constexpr int NK = KL / 4, PD = NK < 2 * prefetch_fp32(N) ? NK : 2 * prefetch_fp32(N);
       using R = Ring<float, PD, 1>;
       auto load = [&](R& r, int g) {
 #pragma unroll
