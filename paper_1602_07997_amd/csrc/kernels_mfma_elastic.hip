@@ -19,7 +19,7 @@
 // Precisions as in the acoustic kernel: FP32 16x16x4, or BF16 / FP16
 // 16x16x16 with both operands split hi + lo and three products accumulated in
 // FP32.  Workgroups of 8 wavefronts (4 for the 16-bit products at N = 5,
-// 12 for FP32 at N = 8); phases:
+// 12 for FP32 at N = 6, with 32-element tiles, and N = 8); phases:
 //   A1  every global read indexed by the tile alone, issued together;
 //       constants into LDS;
 //   A2  neighbour traces; face records; the five LIFT operands of every face
@@ -49,10 +49,12 @@ using namespace mfma;
 // no wavefront idles through the products and two workgroups share a compute
 // unit (measured: ~20% faster there, neutral or slower elsewhere); twelve for
 // the FP32 products at N = 8, whose eleven pairs then take one round instead
-// of two (5% faster despite a few spilled registers; neutral for 16-bit)
+// of two (5% faster despite a few spilled registers; neutral for 16-bit),
+// and for FP32 at N = 6 with 32-element tiles, whose twelve pairs take one
+// wavefront each (7% faster than 16-element tiles on eight wavefronts)
 template <int N, int PREC>
 constexpr int elastic_threads() {
-  return (N == 5 && PREC != 0) ? 256 : ((N == 8 && PREC == 0) ? 768 : 512);
+  return (N == 5 && PREC != 0) ? 256 : (((N == 8 || N == 6) && PREC == 0) ? 768 : 512);
 }
 
 template <int N, int PREC>
@@ -63,7 +65,8 @@ struct EShape {
   static constexpr int KP = rup(NP, KS);
   static constexpr int KF = rup(NFP, KS);  // LIFT K of one face, zero padded
   static constexpr int KL = 4 * KF;        // LIFT K, face blocks of KF
-  static constexpr int NBLK = (N == 1) ? 4 : (N <= 3 ? 2 : 1);
+  // 32-element tiles for FP32 at N = 6: twelve pairs, one per wavefront
+  static constexpr int NBLK = (N == 1) ? 4 : (N <= 3 ? 2 : ((N == 6 && PREC == 0) ? 2 : 1));
   static constexpr int E = 16 * NBLK;
   static constexpr int PAIRS = MB * NBLK;
   static constexpr int NSV = 9;  // volume operand sets (the fields)
