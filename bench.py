@@ -1,28 +1,37 @@
 #!/usr/bin/env python3
 """Throughput of the nodal DG wave step on one MI355X.
 
-Default workload (the paper-scale acoustic sweep): for every degree N = 1..8 a
-Kuhn-split unit cube with ~2M nodes (n^3 subcubes x 6 tetrahedra, n chosen so
-that 6 n^3 N_p ~ 2e6), interior vertices jittered by up to 10% of h (seed 0),
-two-layer (rho, c) = (1, 1) / (2, 1.5) by element centroid, Gaussian pressure
+Default workload (``--config sweep``): the paper-scale acoustic and elastic
+sweeps.  For every degree N = 1..8 one Kuhn-split unit cube with ~2M nodes
+(n^3 subcubes x 6 tetrahedra, n chosen so that 6 n^3 N_p ~ 2e6), interior
+vertices jittered by up to 10% of h (seed 0); acoustic two-layer (rho, c) =
+(1, 1) / (2, 1.5) by element centroid with a Gaussian pressure pulse, elastic
+log-uniform (rho, lambda, mu) in [0.5, 2] (seed 1) with a Gaussian velocity
 pulse.  One benchmark step = one AB3 step (the fused volume + flux + LIFT +
-update kernel) on each of the eight meshes; value = total node updates / s.
-``--config elastic`` runs the elastic sweep (log-uniform rho, lambda, mu in
-[0.5, 2], seed 1, Gaussian velocity pulse).  ``--config batched`` runs 64
-independent acoustic meshes (K log-uniform in [2e3, 2e5] snapped to Kuhn
-boxes, N uniform in {2..6}, seed 2, per-mesh jitter and log-uniform
+update kernel) on each of the sixteen meshes; value = total node updates / s
+of that FP32 sweep, each degree's kernel variant picked by the autotuner
+among the FP32 variants.  The same sweep is then timed with the split 16-bit
+variants admitted ("mixed"), each only where its right-hand side stays
+within 1e-4 relative L2 of the FP64 oracle on that mesh; the accuracy of
+every variant (overall and per field, one right-hand side of a Gaussian
+pulse per field) is reported.  A device-to-device copy gives the achievable
+HBM bandwidth beside the 8 TB/s peak.
+
+``--config acoustic`` / ``elastic`` run one physics; ``--config batched``
+runs 64 independent acoustic meshes (K log-uniform in [2e3, 2e5] snapped to
+Kuhn boxes, N uniform in {2..6}, seed 2, per-mesh jitter and log-uniform
 coefficients), each member's kernel variant picked by the autotuner, all
-advanced together by the batch (one launch per degree/variant group, six-step
-HIP graph replays); the same meshes stepped one by one with the plain
-node-per-thread kernel are timed beside it.  ``--config adjoint`` times the
-misfit forward solve and the adjoint gradient at the elastic N=4 workload
-(14,196 tetrahedra, 200 steps, checkpoints every 20).
+advanced together by the batch, against the same tuned meshes stepped one by
+one; ``--config adjoint`` times the misfit forward solve and the adjoint
+gradient at the elastic N=4 workload (14,196 tetrahedra, 200 steps,
+checkpoints every 20).
 
 Prints one JSON line with the throughput, a roofline object for the kernel
 that takes the largest share of the time (algorithmic bytes and flops per
 element from the model below, divided by its average launch duration from HIP
-events recorded on the launch stream), per-degree details, and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+events recorded on the launch stream), per-(physics, degree, precision)
+details, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 """
 
 from __future__ import annotations
@@ -150,12 +159,12 @@ def init_fields(physics, xyz):
     return np.ascontiguousarray(np.moveaxis(f, 0, 1)).astype(np.float32)
 
 
-def run_gpu(physics, degrees, steps, warmup, log, variant="valu", variant_map=None):
+def setup_sweep(physics, degrees, log, stream):
+    """Solvers on the paper-scale meshes, past the start-up steps."""
     import torch
 
     from paper_1602_07997_amd import DGSolver
 
-    stream = torch.cuda.current_stream()
     cases = []
     for N in degrees:
         n, mesh, coef = workload(physics, N)
@@ -164,43 +173,319 @@ def run_gpu(physics, degrees, steps, warmup, log, variant="valu", variant_map=No
         s.set_fields(torch.tensor(init_fields(physics, s.node_coordinates()), device="cuda"))
         dt = di.time_step(mesh, N, di.max_wave_speed(coef, physics))
         s.step(2, dt)  # Euler and two-step start-up
+        s.energy()  # reference of the library's energy-growth check (flags DG_E_UNSTABLE later)
+        cases.append({"physics": physics, "N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt,
+                      "mesh": mesh, "coef": coef})
+        log(f"  set up {physics} N={N}: n={n} K={mesh.K} nodes={mesh.K * s.Np}")
+    return cases
+
+
+def choose_variants(cases, log, variant="auto", variant_map=None, allowed=None, key="variant"):
+    """Sets each case's kernel variant: fixed, from the map, or autotuned
+    among `allowed[(physics, N)]` (default: the FP32 variants)."""
+    for c in cases:
+        s = c["solver"]
         tuned = None
-        if variant_map and N in variant_map:
-            s.variant = variant_map[N]
+        if variant_map and c["N"] in variant_map:
+            s.variant = variant_map[c["N"]]
         elif variant in ("auto", "auto-mixed"):
-            tuned = s.autotune(3, dt, FP32_VARIANTS if variant == "auto" else None)
+            cands = FP32_VARIANTS if variant == "auto" else None
+            if allowed is not None:
+                cands = allowed[(c["physics"], c["N"])]
+            tuned = s.autotune(3, c["dt"], cands)
         else:
             s.variant = variant
-        cases.append({"N": N, "n": n, "K": mesh.K, "Np": s.Np, "solver": s, "dt": dt, "variant": s.variant,
-                      "autotune_us": tuned})
-        log(f"  set up {physics} N={N}: n={n} K={mesh.K} nodes={mesh.K * s.Np} variant={s.variant}"
-            + (f" (autotune us/step {tuned})" if tuned else ""))
+        c[key] = s.variant
+        c[key + "_autotune_us"] = tuned
+        log(f"  {c['physics']} N={c['N']}: {key} {s.variant}" + (f" (autotune us/step {tuned})" if tuned else ""))
+
+
+def time_sweep(cases, steps, warmup, stream):
+    """Times `steps` sweep steps (one AB3 step on every mesh each), per-launch
+    HIP events on the launch stream; returns (wall seconds, per-case mean and
+    min kernel seconds)."""
+    import torch
+
     for c in cases:
         c["solver"].step(warmup, c["dt"])
     torch.cuda.synchronize()
-    ev = {c["N"]: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)] for c in cases}
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+          for _ in cases]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        for c in cases:
-            a, b = ev[c["N"]][k]
+        for i, c in enumerate(cases):
+            a, b = ev[i][k]
             a.record(stream)
             c["solver"].step(1, c["dt"])
             b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    for c in cases:
-        times = [a.elapsed_time(b) * 1e-3 for a, b in ev[c["N"]]]
-        c["kernel_s"] = float(np.mean(times))
-        c["kernel_s_min"] = float(np.min(times))
-        e = c["solver"].energy()
-        if not math.isfinite(e):
-            raise RuntimeError(f"non-finite energy at N={c['N']}")
-        c["energy"] = e
+    out = []
+    for i, c in enumerate(cases):
+        times = [a.elapsed_time(b) * 1e-3 for a, b in ev[i]]
+        out.append((float(np.mean(times)), float(np.min(times))))
+        # raises DG_E_UNSTABLE if the energy is not finite or grew since the
+        # evaluation after the start-up steps
+        c["energy"] = c["solver"].energy()
+    return wall, out
+
+
+def run_gpu(physics, degrees, steps, warmup, log, variant="valu", variant_map=None):
+    import torch
+
+    stream = torch.cuda.current_stream()
+    cases = setup_sweep(physics, degrees, log, stream)
+    choose_variants(cases, log, variant, variant_map)
+    wall, times = time_sweep(cases, steps, warmup, stream)
+    for c, (t, tmin) in zip(cases, times):
+        c["kernel_s"], c["kernel_s_min"] = t, tmin
+        c["autotune_us"] = c["variant_autotune_us"]
     for c in cases:
         c["solver"].close()
         del c["solver"]
     return cases, wall
+
+
+def copy_bandwidth(log, mib=1024, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of `mib` MiB (read
+    and write counted), timed with HIP events over `reps` copies."""
+    import torch
+
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    t = a.elapsed_time(b) * 1e-3 / reps
+    nbytes = 2 * (mib << 20)
+    del src, dst
+    torch.cuda.empty_cache()
+    bw = nbytes / t
+    log(f"device copy: {mib} MiB in {t * 1e6:.1f} us, {bw / 1e9:.0f} GB/s ({bw / HBM_PEAK:.3f} of 8 TB/s)")
+    return {"GBps": bw / 1e9, "bytes_per_copy": nbytes, "us_per_copy": t * 1e6, "frac_of_peak": bw / HBM_PEAK,
+            "how": f"torch copy_ of a {mib} MiB float32 tensor, mean of {reps} after 3 untimed"}
+
+
+ALL_VARIANTS = ("valu", "mfma", "elem", "mfma_bf16", "mfma_f16")
+SPLIT16 = ("mfma_bf16", "mfma_f16")
+MIXED_TOL = 1e-4  # relative L2 vs the FP64 oracle, overall and per field
+
+
+def sweep_accuracy(cases, log):
+    """One right-hand side per (physics, degree, variant) on the sweep's own
+    meshes against the FP64 oracle, from a state with a Gaussian pulse in
+    every field; the oracle's step is timed as the CPU baseline sample.
+
+    Returns {(physics, N): {variant: (overall, per-field list)}} and the CPU
+    timing record."""
+    import torch
+    from threadpoolctl import threadpool_info
+
+    from oracle.dg import AB3Stepper, make_oracle
+    from oracle.mesh import build_mesh
+    from paper_1602_07997_amd._native import DG_E_UNSUPPORTED, DGError
+
+    acc = {}
+    cpu = {"nodes": 0, "wall": 0.0, "cpu": 0.0, "parts": []}
+    geo = None
+    # both physics use the degree's mesh: one oracle geometry per degree
+    for c in sorted(cases, key=lambda c: (c["N"], c["physics"])):
+        N, physics, s = c["N"], c["physics"], c["solver"]
+        if geo is None or geo.N != N:
+            geo = None
+            geo = build_mesh(N, c["mesh"].elem_xyz, c["mesh"].elem_topo, None)
+        o = make_oracle(physics, geo, c["coef"])
+        nf = o.nfields
+        q = np.ascontiguousarray(np.moveaxis(di.gaussian_pulses(geo.xyz, nf), 0, 1)).astype(np.float32)
+        st = AB3Stepper(o, q.astype(np.float64))
+        c0, t0 = time.process_time(), time.perf_counter()
+        st.step(1, c["dt"])
+        t = time.perf_counter() - t0
+        cpu["cpu"] += time.process_time() - c0
+        cpu["wall"] += t
+        cpu["nodes"] += geo.K * geo.ref.Np
+        cpu["parts"].append(f"{physics[0]}N{N}")
+        r_ref = st.r1
+        qg = np.ascontiguousarray(np.moveaxis(di.gaussian_pulses(s.node_coordinates(), nf), 0, 1)).astype(np.float32)
+        qg = torch.tensor(qg, device="cuda")
+        keep = s.variant
+        res = {}
+        for v in ALL_VARIANTS:
+            try:
+                s.variant = v
+            except DGError as e:
+                if e.status != DG_E_UNSUPPORTED:
+                    raise
+                continue
+            r = s.rhs(qg).double().cpu().numpy()
+            err, per = o.rel_l2(r, r_ref)
+            res[v] = (float(err), [float(x) for x in per])
+        s.variant = keep
+        acc[(physics, N)] = res
+        log(f"  accuracy {physics} N={N} (oracle step {t:.1f} s): "
+            + ", ".join(f"{v} {e[0]:.1e}/{max(e[1]):.1e}" for v, e in res.items()))
+        del o, st, r_ref
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    cpu_rec = {
+        "value": cpu["nodes"] / cpu["wall"], "unit": "node-updates/s", "cores": int(threads), "kind": "oracle",
+        "sample": "one FP64 oracle AB3 step (right-hand side and update, from the accuracy check's pulse state) "
+        f"on each of the sweep's {len(cases)} meshes ({', '.join(cpu['parts'])}), acoustic and elastic N=1..8 at "
+        f"~2M nodes; {cpu['wall']:.1f} s wall, {cpu['cpu'] / max(cpu['wall'], 1e-9):.1f} cores busy on average",
+    }
+    return acc, cpu_rec
+
+
+def roofline_row(c, t, tmin, variant, copy_bw=None):
+    physics, N, K = c["physics"], c["N"], c["K"]
+    nbytes, flops = algorithmic_model(physics, N)
+    bw = nbytes * K / t
+    fl = flops * K / t
+    t_hbm = nbytes * K / HBM_PEAK
+    t_alu = compute_floor(physics, N, variant) * K
+    bound = "hbm" if t_hbm >= t_alu else ("mfma" if variant.startswith("mfma") else "alu")
+    frac = (t_hbm if bound == "hbm" else t_alu) / t
+    row = {
+        "physics": physics, "N": N, "n": c["n"], "K": K, "nodes": K * c["Np"], "variant": variant,
+        "kernel": kernel_name(physics, N, variant),
+        "kernel_us": round(t * 1e6, 2), "kernel_us_min": round(tmin * 1e6, 2),
+        "node_updates_per_s": K * c["Np"] / t,
+        "alg_bytes_per_elem": nbytes, "alg_flops_per_elem": flops,
+        "achieved_GBps": bw / 1e9, "achieved_TFLOPs": fl / 1e12,
+        "bound": bound, "frac": frac,
+        "traffic_bytes": measured_traffic(physics, N, variant),
+    }
+    if copy_bw:
+        row["frac_of_copy_bw"] = bw / (copy_bw * 1e9)
+    return row
+
+
+def roofline_object(row):
+    t = row["kernel_us"] * 1e-6
+    nb, nf = row["alg_bytes_per_elem"] * row["K"], row["alg_flops_per_elem"] * row["K"]
+    if row["bound"] == "hbm":
+        roof = {"bound": "hbm", "achieved": nb / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    else:
+        # compute-bound: algorithmic flops against the variant's own floor
+        # (FP32 peak; for the split 16-bit variants the contractions are
+        # priced as three products at the 16-bit matrix peak)
+        peak = row["alg_flops_per_elem"] / compute_floor(row["physics"], row["N"], row["variant"])
+        roof = {"bound": "mfma" if row["variant"].startswith("mfma") else "alu",
+                "achieved": nf / t / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = row["traffic_bytes"]
+    roof["kernel"] = row["kernel"]
+    return roof
+
+
+def main_sweep(args, log, degrees):
+    """Acoustic and elastic sweeps, FP32-autotuned (headline) and mixed."""
+    import torch
+
+    copy = copy_bandwidth(log)
+    stream = torch.cuda.current_stream()
+    cases = []
+    for physics in ("acoustic", "elastic"):
+        cases += setup_sweep(physics, degrees, log, stream)
+    acc, cpu = (None, None)
+    if not args.no_accuracy:
+        log("accuracy against the FP64 oracle (one right-hand side per variant) and CPU baseline")
+        acc, cpu = sweep_accuracy(cases, log)
+    if args.no_cpu_baseline:
+        cpu = None
+    vmap = {int(k): v for k, v in (item.split(":") for item in args.variant_map.split(",") if item)}
+    log("FP32 sweep")
+    choose_variants(cases, log, "auto" if args.variant not in ("valu", "mfma", "elem") else args.variant, vmap,
+                    key="v32")
+    wall32, t32 = time_sweep(cases, args.steps, args.warmup, stream)
+    allowed = {}
+    for c in cases:
+        ok = list(FP32_VARIANTS)
+        if acc is not None:
+            ok += [v for v in SPLIT16 if v in acc[(c["physics"], c["N"])]
+                   and acc[(c["physics"], c["N"])][v][0] <= MIXED_TOL
+                   and max(acc[(c["physics"], c["N"])][v][1]) <= MIXED_TOL]
+        allowed[(c["physics"], c["N"])] = ok
+    log("mixed sweep (split 16-bit variants admitted where accurate to 1e-4)")
+    choose_variants(cases, log, "auto-mixed", None, allowed=allowed, key="vmx")
+    wallmx, tmx = time_sweep(cases, args.steps, args.warmup, stream)
+
+    per = []
+    for prec, key, times in (("fp32", "v32", t32), ("mixed", "vmx", tmx)):
+        for c, (t, tmin) in zip(cases, times):
+            row = roofline_row(c, t, tmin, c[key], copy["GBps"])
+            row["precision"] = prec
+            row["autotune_us"] = c[key + "_autotune_us"]
+            if acc is not None:
+                e = acc[(c["physics"], c["N"])].get(c[key])
+                row["rhs_rel_l2_vs_fp64"] = e[0] if e else None
+                row["rhs_rel_l2_per_field"] = e[1] if e else None
+                row["admitted_split_variants"] = [v for v in allowed[(c["physics"], c["N"])] if v in SPLIT16]
+            per.append(row)
+            log(f"  {prec:5s} {c['physics']:8s} N={c['N']} {c[key]:9s}: {t * 1e6:8.1f} us  "
+                f"{row['node_updates_per_s']:.3e} node-upd/s  {row['bound']} frac {row['frac']:.3f}"
+                + (f"  rhs err {row['rhs_rel_l2_vs_fp64']:.1e}" if acc is not None else ""))
+    total_nodes = sum(c["K"] * c["Np"] for c in cases)
+    value32 = total_nodes / (wall32 / args.steps)
+    valuemx = total_nodes / (wallmx / args.steps)
+    rows32 = [r for r in per if r["precision"] == "fp32"]
+    dom = max(rows32, key=lambda r: r["kernel_us"])
+    by_phys = {}
+    for physics in ("acoustic", "elastic"):
+        for prec in ("fp32", "mixed"):
+            rs = [r for r in per if r["physics"] == physics and r["precision"] == prec]
+            by_phys[f"{physics}_{prec}"] = {
+                "node_updates_per_s": sum(r["nodes"] for r in rs) / sum(r["kernel_us"] * 1e-6 for r in rs),
+                "kernel_ms_per_sweep": sum(r["kernel_us"] for r in rs) / 1e3,
+                "variants": {r["N"]: r["variant"] for r in rs},
+            }
+    for c in cases:
+        c["solver"].close()
+        del c["solver"]
+    out = {
+        "metric": METRIC,
+        "value": value32,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall32 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"acoustic and elastic sweeps N={degrees[0]}..{degrees[-1]}, one ~2M-node jittered Kuhn cube "
+            "per degree and physics, one AB3 step on each of the meshes per benchmark step; value: FP32 variants "
+            "autotuned per degree; 'mixed': BF16/FP16 split-product variants admitted where their right-hand "
+            "side is within 1e-4 relative L2 of the FP64 oracle",
+            "physics": ["acoustic", "elastic"],
+            "precisions": ["fp32", "mixed"],
+            "degrees": degrees,
+            "total_nodes": total_nodes,
+        },
+        "roofline": roofline_object(dom),
+        "cpu_baseline": cpu,
+        "mixed": {
+            "value": valuemx, "ms_per_step": wallmx / args.steps * 1e3, "speedup_vs_fp32": valuemx / value32,
+            "dtype": dtype_of(sorted({c["vmx"] for c in cases})),
+            "accuracy_gate": f"rhs relative L2 vs FP64 <= {MIXED_TOL} overall and per field",
+        },
+        "by_physics": by_phys,
+        "copy_bandwidth": copy,
+        "per_degree": per,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def run_cpu_baseline(physics, degrees, steps, log):
@@ -287,7 +572,7 @@ def run_batched(steps, warmup, log, count=64, seed=2, candidates=FP32_VARIANTS):
     one_by_one(warmup)
     t_plain, _ = timed(one_by_one, steps)
     log(f"  one mesh at a time, node-per-thread: {t_plain / steps * 1e3:.3f} ms/step")
-    # autotuned variant per member, then the batch
+    # autotuned variant per member, then the same meshes one by one, then the batch
     t0 = time.perf_counter()
     choice = {}
     for m in members:
@@ -295,6 +580,9 @@ def run_batched(steps, warmup, log, count=64, seed=2, candidates=FP32_VARIANTS):
         choice.setdefault((m["N"], m["solver"].variant), 0)
         choice[(m["N"], m["solver"].variant)] += 1
     log(f"  autotune {time.perf_counter() - t0:.1f} s: {sorted(choice.items())}")
+    one_by_one(warmup)
+    t_tuned, _ = timed(one_by_one, steps)
+    log(f"  one mesh at a time, autotuned variants: {t_tuned / steps * 1e3:.3f} ms/step")
     batch = DGBatch([m["solver"] for m in members], stream=stream, graph=True)
     nsteps = 6 * max(1, steps // 6)
     batch.step(6 * max(1, warmup // 6), dts)
@@ -310,7 +598,7 @@ def run_batched(steps, warmup, log, count=64, seed=2, candidates=FP32_VARIANTS):
         m["solver"].close()
     return {
         "total_nodes": total_nodes, "steps": nsteps, "t_batch": t_batch, "wall": wall, "t_plain": t_plain,
-        "plain_steps": steps, "alg_bytes_per_step": nbytes, "groups": groups,
+        "t_tuned": t_tuned, "plain_steps": steps, "alg_bytes_per_step": nbytes, "groups": groups,
         "choice": {f"N={k[0]}:{k[1]}": v for k, v in sorted(choice.items())},
     }
 
@@ -388,6 +676,7 @@ def main_batched(args, log):
     r = run_batched(args.steps, args.warmup, log, candidates=cands)
     step_s = r["t_batch"] / r["steps"]
     plain_s = r["t_plain"] / r["plain_steps"]
+    tuned_s = r["t_tuned"] / r["plain_steps"]
     achieved = r["alg_bytes_per_step"] / step_s
     out = {
         "metric": METRIC,
@@ -417,6 +706,8 @@ def main_batched(args, log):
         },
         "cpu_baseline": None,
         "plain_fp32_one_by_one": {"node_updates_per_s": r["total_nodes"] / plain_s, "ms_per_step": plain_s * 1e3},
+        "tuned_one_by_one": {"node_updates_per_s": r["total_nodes"] / tuned_s, "ms_per_step": tuned_s * 1e3},
+        "speedup_vs_tuned_one_by_one": tuned_s / step_s,
         "speedup_vs_plain": plain_s / step_s,
     }
     print(json.dumps(out), flush=True)
@@ -428,7 +719,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", choices=["acoustic", "elastic", "batched", "adjoint"], default="acoustic")
+    ap.add_argument("--config", choices=["sweep", "acoustic", "elastic", "batched", "adjoint"], default="sweep")
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument(
@@ -442,6 +733,8 @@ def main(argv=None):
         "profiling runs use it so that the profiler's own timing does not change the autotuner's choice)",
     )
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="sweep: skip the FP64 oracle accuracy check (the mixed sweep then admits every variant)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument(
         "--copy-calibration-mib", type=int, default=0,
@@ -486,6 +779,8 @@ def main(argv=None):
         return main_batched(args, log)
     if physics == "adjoint":
         return main_adjoint(args, log)
+    if physics == "sweep":
+        return main_sweep(args, log, degrees)
     log(f"bench: {physics} sweep N={degrees}, {args.steps} timed steps, {args.warmup} warm-up")
     vmap = {int(k): v for k, v in (item.split(":") for item in args.variant_map.split(",") if item)}
     cases, wall = run_gpu(physics, degrees, args.steps, args.warmup, log, args.variant, vmap)

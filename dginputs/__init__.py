@@ -263,6 +263,15 @@ def elastic_gaussian(x: np.ndarray, center=(0.5, 0.5, 0.5), sigma=0.1) -> np.nda
     return out
 
 
+def gaussian_pulses(x: np.ndarray, nfields: int, seed: int = 7, sigma: float = 0.1) -> np.ndarray:
+    """Fields [nfields, ...]: field c is a Gaussian pulse of width sigma and
+    amplitude 1 + 0.3 c centred at a seeded point of [0.3, 0.7]^3, so that
+    every field carries the pulse's length scale (a state in which no field
+    vanishes, for per-field error norms)."""
+    centres = np.random.default_rng(seed).uniform(0.3, 0.7, (nfields, 3))
+    return np.stack([(1.0 + 0.3 * c) * gaussian(x, centres[c], sigma) for c in range(nfields)])
+
+
 def acoustic_plane_wave(x, m, rho=1.0, c=1.0, t=0.0) -> np.ndarray:
     """Travelling acoustic plane wave p = cos(2 pi m.x - omega t), omega =
     2 pi |m| c, v = mhat p / (rho c): an exact solution of the pressure-velocity

@@ -64,7 +64,7 @@ typedef int dg_status;
 #define DG_E_STATE (-4)       /* call out of order (e.g. step before fields)  */
 #define DG_E_HIP (-5)         /* HIP runtime error                            */
 #define DG_E_UNSUPPORTED (-6) /* degree or physics not built                  */
-#define DG_E_UNSTABLE (-7)    /* non-finite energy detected                   */
+#define DG_E_UNSTABLE (-7)    /* non-finite or growing energy detected        */
 
 #define DG_ACOUSTIC 0
 #define DG_ELASTIC 1
@@ -202,9 +202,18 @@ dg_status dg_rhs(dg_solver* s, const float* q, float* r);
  * acoustic 1/2 sum_k J_k [p^T M p/(rho c^2) + rho sum_i v_i^T M v_i];
  * elastic 1/2 sum_k J_k [rho sum_i v_i^T M v_i + (s:s - lambda/(3 lambda +
  * 2 mu) tr(s)^2)/(2 mu)] with the mass matrix (off-diagonal stresses twice).
- * Synchronises; *e is host float64.  Returns DG_E_UNSTABLE (with *e set) if
- * the energy is not finite.                                                  */
+ * Synchronises; *e is host float64.  Stability check: the upwind flux of
+ * Sec. 2.1 only dissipates, so returns DG_E_UNSTABLE (with *e set) if the
+ * energy is not finite, or if it exceeds (1 + tol) times the previous
+ * dg_energy result of the same trajectory, both evaluations in the AB3
+ * regime (step index >= 2; dg_set_fields / dg_set_state start a new
+ * trajectory).  tol defaults to 1e-4, see dg_set_energy_tolerance.          */
 dg_status dg_energy(dg_solver* s, double* e);
+
+/* Growth tolerance of dg_energy's stability check (>= 0); a negative value
+ * disables the growth check (non-finite energies are still flagged).
+ * Errors: DG_E_ARG (NaN).                                                    */
+dg_status dg_set_energy_tolerance(dg_solver* s, double tol);
 
 /* Diagnostics: copy one internal device buffer of the solver into caller
  * memory (host), for layout and data checks in tests.  `name` is one of
@@ -326,8 +335,9 @@ dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, doub
  * (W the energy weight, P = -1 on velocities), checkpointed segments are
  * recomputed, and the coefficient derivatives of the energy weight and of
  * the upwind penalty are accumulated per element in float64.  Needs a
- * preceding dg_misfit_forward with data and unchanged coefficients.
- * Errors: DG_E_STATE, DG_E_HIP.                                             */
+ * preceding dg_misfit_forward with data; DG_E_STATE if there was none or if
+ * dg_set_coefficients was called on the solver after it.  Errors:
+ * DG_E_STATE, DG_E_HIP.                                                     */
 dg_status dg_misfit_gradient(dg_misfit* f, float* grad);
 
 #ifdef __cplusplus

@@ -46,6 +46,13 @@ class DGMisfit:
         )
         self._h = h
         self.channels = int(lib.dg_misfit_channels(h))
+        self._forwards = 0
+
+    @property
+    def generation(self):
+        """Changes with every forward solve and every coefficient change of
+        the solver: a gradient belongs to the forward of the same generation."""
+        return (self._forwards, getattr(self.solver, "coef_generation", 0))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -74,6 +81,7 @@ class DGMisfit:
                                   C.byref(J)),
             "dg_misfit_forward",
         )
+        self._forwards += 1
         return traces, J.value
 
     def gradient(self):
@@ -96,15 +104,30 @@ def _misfit_function():
 
         @staticmethod
         def forward(ctx, coef, misfit, data):
-            coef = coef.detach().contiguous()
+            coef = coef.detach().contiguous().clone()
             misfit.solver.set_coefficients(coef)
             _, J = misfit.forward(data)
             ctx.misfit = misfit
+            ctx.coef, ctx.data = coef, data
+            ctx.generation = misfit.generation
             return torch.tensor(J, dtype=torch.float64, device=coef.device)
 
         @staticmethod
         def backward(ctx, gJ):
-            g = ctx.misfit.gradient()
+            f = ctx.misfit
+            if f.generation != ctx.generation:
+                # another forward solve or a coefficient change came between:
+                # redo this call's forward solve so that the gradient belongs
+                # to its coefficients and data, then restore the solver's
+                # coefficients
+                prev = getattr(f.solver, "last_coefficients", None)
+                f.solver.set_coefficients(ctx.coef)
+                f.forward(ctx.data)
+                g = f.gradient()
+                if prev is not None:
+                    f.solver.set_coefficients(prev)
+            else:
+                g = f.gradient()
             return (g * gJ.to(g.dtype)), None, None
 
     return MisfitFunction

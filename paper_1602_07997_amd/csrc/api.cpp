@@ -470,6 +470,7 @@ dg_status dg_set_coefficients(dg_solver* s, const float* coef) {
     }
   DG_HIP(dgw::launch_coef_prep(s->physics, s->K, s->coef, s->conn, s->cf, s->stream));
   s->have_coef = true;
+  s->coef_gen += 1;
   return DG_OK;
 }
 
@@ -484,6 +485,8 @@ dg_status dg_set_fields(dg_solver* s, const float* q) {
   s->cur = 0;
   s->m = 0;
   s->have_fields = true;
+  s->e_prev = -1.0;
+  s->e_prev_m = -1;
   return DG_OK;
 }
 
@@ -517,6 +520,8 @@ dg_status dg_set_state(dg_solver* s, const float* q, const float* r1, const floa
   s->cur = 0;
   s->m = step_index;
   s->have_fields = true;
+  s->e_prev = -1.0;
+  s->e_prev_m = -1;
   return DG_OK;
 }
 
@@ -601,8 +606,33 @@ dg_status dg_energy(dg_solver* s, double* e) {
   DG_HIP(hipStreamSynchronize(s->stream));
   if (!std::isfinite(*e)) {
     set_error("energy is not finite");
+    s->e_prev = -1.0;
     return DG_E_UNSTABLE;
   }
+  // The upwind flux only removes energy (Sec. 2.1), so in the AB3 regime the
+  // energy of one trajectory must not grow between two evaluations; the
+  // Euler and two-step start-up steps may raise it slightly and are exempt.
+  const double prev = s->e_prev;
+  const int64_t prev_m = s->e_prev_m;
+  s->e_prev = *e;
+  s->e_prev_m = s->m;
+  if (s->e_tol >= 0.0 && prev >= 0.0 && prev_m >= 2 && s->m > prev_m && *e > prev * (1.0 + s->e_tol)) {
+    std::ostringstream os;
+    os << "energy grew from " << prev << " at step " << prev_m << " to " << *e << " at step " << s->m
+       << " (tolerance " << s->e_tol << "): the step size is likely above the stability limit";
+    set_error(os.str());
+    return DG_E_UNSTABLE;
+  }
+  return DG_OK;
+}
+
+dg_status dg_set_energy_tolerance(dg_solver* s, double tol) {
+  if (dg_status st = check_solver(s)) return st;
+  if (std::isnan(tol)) {
+    set_error("tolerance is NaN");
+    return DG_E_ARG;
+  }
+  s->e_tol = tol;
   return DG_OK;
 }
 

@@ -158,6 +158,7 @@ struct dg_misfit {
   DevBuf<float> ch_w;
   DevBuf<float> traces, data;  // [M+1][R]
   bool have_data = false, have_forward = false;
+  uint64_t fwd_coef_gen = 0;  // the solver's coefficient generation of the last forward
   // segment of C steps: states, traces and right-hand sides
   DevBuf<float> seg_q, seg_tr, seg_r;
   // checkpoints: q at the segment start and the two previous right-hand sides
@@ -400,6 +401,7 @@ dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, doub
     if (dg_status st = run_segment(f, seg, true)) return st;
   }
   f->have_forward = true;
+  f->fwd_coef_gen = s->coef_gen;
   if (traces)
     DG_HIP(hipMemcpyAsync(traces, f->traces.p, ntrace * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
   f->have_data = data != nullptr;
@@ -433,6 +435,10 @@ dg_status dg_misfit_gradient(dg_misfit* f, float* grad) {
     return DG_E_STATE;
   }
   dg_solver* s = f->s;
+  if (s->coef_gen != f->fwd_coef_gen) {
+    set_error("dg_misfit_gradient: the coefficients changed after the last dg_misfit_forward");
+    return DG_E_STATE;
+  }
   const dgw::RefElement* ref = dgw::reference_element(s->N);
   const int Np = ref->Np;
   // adjoint source vectors s = P W^{-1} g: per channel

@@ -49,6 +49,12 @@ struct dg_solver {
   int cur = 0;     // trace buffer holding the traces of q
   int64_t m = 0;   // step index
   bool have_coef = false, have_fields = false;
+  uint64_t coef_gen = 0;  // bumped by every dg_set_coefficients
+  // energy growth check: the last dg_energy result and the step index it
+  // belongs to (-1: none since the fields were set); growth tolerance
+  double e_prev = -1.0;
+  int64_t e_prev_m = -1;
+  double e_tol = 1e-4;
   int xcd_remap = 1;
   int variant = 0;
   float* Dpack = nullptr;

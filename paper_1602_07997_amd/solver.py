@@ -141,6 +141,8 @@ class DGSolver:
     def set_coefficients(self, coef):
         p = _require_torch_device_tensor(coef, (self.K, self.ncoef), "coef")
         check(lib.dg_set_coefficients(self._h, p), "dg_set_coefficients")
+        self.coef_generation = getattr(self, "coef_generation", 0) + 1
+        self.last_coefficients = coef.detach().clone()
 
     def set_fields(self, q):
         check(lib.dg_set_fields(self._h, _require_torch_device_tensor(q, self.field_shape, "q")), "dg_set_fields")
@@ -231,6 +233,10 @@ class DGSolver:
         e = C.c_double()
         check(lib.dg_energy(self._h, C.byref(e)), "dg_energy")
         return e.value
+
+    def set_energy_tolerance(self, tol: float):
+        """Growth tolerance of the energy stability check (negative: off)."""
+        check(lib.dg_set_energy_tolerance(self._h, float(tol)), "dg_set_energy_tolerance")
 
     def debug_buffer(self, name: str) -> np.ndarray:
         """Copy of an internal device buffer (see dg_debug_buffer)."""

@@ -42,6 +42,8 @@ def initial_fields(physics: str, xyz: np.ndarray, kind: str = "gaussian") -> np.
     """[K, Nf, Np] from node coordinates [K, Np, 3]."""
     if kind == "gaussian":
         f = di.acoustic_gaussian(xyz) if physics == "acoustic" else di.elastic_gaussian(xyz)
+    elif kind == "pulses":
+        f = di.gaussian_pulses(xyz, 4 if physics == "acoustic" else 9)
     elif kind == "smooth":
         # a smooth state that excites every field (all non-zero)
         nf = 4 if physics == "acoustic" else 9
@@ -87,3 +89,36 @@ class Case:
 
     def rel_l2(self, q_gpu: np.ndarray, q_ref: np.ndarray):
         return self.oracle.rel_l2(q_gpu, q_ref)
+
+    def check(self, q_gpu: np.ndarray, q_ref: np.ndarray, l2: float, what: str = "", per_field: float | None = None,
+              node: float | None = None):
+        """Asserts the GPU result against the oracle's, see ``check_close``."""
+        return check_close(self.oracle, q_gpu, q_ref, l2, what, per_field, node)
+
+
+def node_errors(q: np.ndarray, q_ref: np.ndarray) -> np.ndarray:
+    """Element-wise error per field: max over elements and nodes of |q - q_ref|
+    divided by the field's largest |q_ref| (floored at 1e-3 of the largest
+    field maximum, so that a field that is nearly zero is measured against
+    the state's scale)."""
+    d = np.abs(q - q_ref).max(axis=(0, 2))
+    scale = np.abs(q_ref).max(axis=(0, 2))
+    return d / np.maximum(scale, 1e-3 * scale.max())
+
+
+def check_close(oracle, q: np.ndarray, q_ref: np.ndarray, l2: float, what: str = "",
+                per_field: float | None = None, node: float | None = None):
+    """Mass-weighted relative L2 over all fields <= l2, per field <=
+    per_field (default l2) and, node by node, |q - q_ref| <= node times the
+    field's largest |q_ref| (default 10 l2).  The node-wise bar catches a
+    single wrong element that the norms would average away.  Returns
+    (overall L2, per-field L2, per-field node-wise ratio)."""
+    per_field = l2 if per_field is None else per_field
+    node = 10.0 * l2 if node is None else node
+    err, per = oracle.rel_l2(q, q_ref)
+    nd = node_errors(q, q_ref)
+    log(f"  {what} rel L2 {err:.2e}, per field max {np.nanmax(per):.2e}, node-wise max {nd.max():.2e}")
+    assert err <= l2, (what, err)
+    assert np.all(np.nan_to_num(per) <= per_field), (what, per)
+    assert np.all(nd <= node), (what, nd)
+    return err, per, nd

@@ -140,6 +140,40 @@ def test_autograd_function():
     torch.testing.assert_close(c.grad, 3.0 * g)
 
 
+def test_autograd_interleaved_forwards_and_coefficient_changes():
+    """Two misfit evaluations (a line search, or a sum of two misfits) before
+    one backward: each gradient belongs to its own call's coefficients, and
+    the solver's coefficients are left as they were.  At the ABI level a
+    gradient after a coefficient change is refused."""
+    from paper_1602_07997_amd import misfit
+    from paper_1602_07997_amd._native import DG_E_STATE, DGError
+
+    _, coef, pr, data, s, f = _setup("acoustic", 2)
+    d = torch.tensor(data, dtype=torch.float32, device="cuda")
+    c1 = torch.tensor(coef, dtype=torch.float32, device="cuda", requires_grad=True)
+    c2 = torch.tensor(coef * 1.03, dtype=torch.float32, device="cuda", requires_grad=True)
+    # reference gradients, one call at a time
+    misfit(c1, f, d).backward()
+    g1_ref = c1.grad.clone()
+    misfit(c2, f, d).backward()
+    g2_ref = c2.grad.clone()
+    assert not torch.allclose(g1_ref, g2_ref)
+    c1.grad = None
+    c2.grad = None
+    J = misfit(c1, f, d) + 2.0 * misfit(c2, f, d)
+    J.backward()
+    torch.testing.assert_close(c1.grad, g1_ref)
+    torch.testing.assert_close(c2.grad, 2.0 * g2_ref)
+    # the solver's coefficients are those of the last forward call (c2)
+    torch.testing.assert_close(s.last_coefficients, c2.detach())
+    # ABI: forward, coefficient change, gradient -> DG_E_STATE
+    f.forward(d)
+    s.set_coefficients(c1.detach())
+    with pytest.raises(DGError) as ei:
+        f.gradient()
+    assert ei.value.status == DG_E_STATE
+
+
 def test_paper_scale_adjoint_finite_differences():
     """Elastic N=4 on the 13x13x14 Kuhn box (14,196 tetrahedra), 200 steps,
     checkpoints every 20, Ricker source (peak frequency 5) at the box centre,

@@ -3,8 +3,9 @@
 A batch member must follow exactly the trajectory it would follow alone:
 each member is compared with a twin solver built from the same inputs and
 stepped by itself with dg_step (relative L2 <= 1e-6; the kernels are the
-same code, so in practice the results are identical), and one member per
-test is also compared with the FP64 oracle at the AB3 tolerance (1e-5).
+same code, so in practice the results are identical), and every member is
+also compared with the FP64 oracle at the AB3 tolerance (1e-5, or 1e-4 for
+the split 16-bit variants).
 """
 
 import numpy as np
@@ -50,7 +51,7 @@ def _rel(a: torch.Tensor, b: torch.Tensor) -> float:
 ACOUSTIC_SPECS = [(1, (3, 2, 2), "valu"), (2, (2, 3, 2), "valu"), (3, (3, 3, 2), "mfma"),
                   (3, (2, 2, 2), "valu"), (5, (2, 2, 3), "mfma"), (2, (4, 3, 3), "mfma")]
 ELASTIC_SPECS = [(1, (3, 2, 2), "valu"), (2, (2, 3, 2), "valu"), (4, (2, 2, 2), "valu"),
-                 (2, (3, 3, 2), "valu")]
+                 (2, (3, 3, 2), "valu"), (6, (3, 2, 3), "mfma"), (1, (3, 3, 2), "elem")]
 
 
 @pytest.mark.parametrize("graph", [False, True])
@@ -78,11 +79,9 @@ def test_batch_matches_individual(physics, graph):
         e = _rel(c.solver.get_fields(), t.get_fields())
         log(f"  N={c.N} {c.solver.variant} K={c.mesh.K}: batch vs alone {e:.2e}")
         assert e <= SAME
-    c = pairs[2][0]
-    ref = AB3Stepper(c.oracle, c.q0).step(nsteps, c.dt)
-    err, _ = c.rel_l2(c.to_host(c.solver.get_fields()), ref)
-    log(f"  member N={c.N} vs oracle {err:.2e}")
-    assert err <= 1e-5
+    for c, _ in pairs:
+        ref = AB3Stepper(c.oracle, c.q0).step(nsteps, c.dt)
+        c.check(c.to_host(c.solver.get_fields()), ref, 1e-5, f"member N={c.N} K={c.mesh.K} vs oracle")
     batch.close()
 
 
@@ -194,15 +193,14 @@ def test_autotune_keeps_state_and_picks_a_built_variant(physics, N):
     # the traces were restored too: continuing gives the oracle's trajectory
     c.solver.step(6, c.dt)
     ref = AB3Stepper(c.oracle, c.q0).step(10, c.dt)
-    err, _ = c.rel_l2(c.to_host(c.solver.get_fields()), ref)
-    log(f"  after tuning, 10 steps vs oracle {err:.2e}")
-    assert err <= 1e-5
+    tol = 1e-4 if c.solver.variant in ("mfma_bf16", "mfma_f16") else 1e-5
+    c.check(c.to_host(c.solver.get_fields()), ref, tol, "after tuning, 10 steps")
 
 
 def test_batch_recipe_shapes():
     """The batched workload's recipe at a reduced count: sizes are Kuhn boxes
-    in range, degrees in {2..6}; a small batch built from it steps to the
-    oracle's trajectory for its smallest member."""
+    in range, degrees in {2..6}; a small batch built from it steps every
+    member to the oracle's trajectory."""
     from paper_1602_07997_amd import DGBatch
 
     recipe = di.batch_recipe(count=6, seed=2, k_lo=200, k_hi=2000, n_lo=2, n_hi=4)
@@ -221,11 +219,10 @@ def test_batch_recipe_shapes():
     batch.step(14, [c.dt for c in cases])
     stream.synchronize()
     torch.cuda.synchronize()
-    c = min(cases, key=lambda c: c.mesh.K * c.solver.Np)
-    ref = AB3Stepper(c.oracle, c.q0).step(14, c.dt)
-    err, _ = c.rel_l2(c.to_host(c.solver.get_fields()), ref)
-    log(f"  smallest member N={c.N} K={c.mesh.K}: {err:.2e}")
-    assert err <= 1e-5
+    for c in cases:
+        ref = AB3Stepper(c.oracle, c.q0).step(14, c.dt)
+        tol = 1e-4 if c.solver.variant in ("mfma_bf16", "mfma_f16") else 1e-5
+        c.check(c.to_host(c.solver.get_fields()), ref, tol, f"member N={c.N} K={c.mesh.K} {c.solver.variant}")
     batch.close()
 
 
