@@ -15,7 +15,8 @@ Mesh format (the product's set-up call takes the same arrays):
   a face iff they share the three ids of that face (periodic boxes identify
   opposite vertices through these ids, while ``elem_xyz`` keeps the unwrapped
   coordinates);
-* ``period``    float64 [3] or None, the box lengths of a periodic mesh.
+* ``period``    float64 [3] or None, the box lengths of a periodic mesh
+  (0 along an axis that is not periodic).
 
 Faces that have no partner are boundary faces (reflecting walls).
 """
@@ -56,7 +57,7 @@ def kuhn_box(
     lengths=(1.0, 1.0, 1.0),
     jitter: float = 0.0,
     seed: int = 0,
-    periodic: bool = False,
+    periodic=False,
 ) -> TetMesh:
     """Box of nx*ny*nz subcubes, each split into 6 Kuhn tetrahedra.
 
@@ -66,14 +67,16 @@ def kuhn_box(
     and compatible with periodic identification.  Elements are ordered
     subcube by subcube (x fastest), six consecutive elements per subcube.
 
+    ``periodic`` is one flag for all axes or a triple of per-axis flags.
     ``jitter`` moves vertices by U[-jitter*h, jitter*h] per coordinate (h the
-    subcube edge along that axis): interior vertices only for a wall-bounded
-    box, every vertex (consistently through its topological id) for a periodic
-    one.  The draw is repeated with the next seed offset until every element
-    is positively oriented.
+    subcube edge along that axis), consistently through the topological id;
+    vertices on the boundary planes of a non-periodic axis stay fixed.  The
+    draw is repeated with the next seed offset until every element is
+    positively oriented.
     """
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
+    per_axis = tuple(bool(x) for x in (periodic if isinstance(periodic, (tuple, list)) else (periodic,) * 3))
     L = np.asarray(lengths, dtype=float)
     h = L / np.array([nx, ny, nz], dtype=float)
     gi, gj, gk = np.meshgrid(
@@ -96,7 +99,7 @@ def kuhn_box(
             path[2], path[3] = path[3], path[2]
         corners[:, p] = np.stack(path, axis=1)
     corners = corners.reshape(K, 4, 3)
-    topo = _vectorised_ids(corners, nx, ny, nz, periodic)
+    topo = _vectorised_ids(corners, nx, ny, nz, per_axis)
 
     base = corners.astype(float) * h  # unwrapped coordinates
     attempt = 0
@@ -104,11 +107,11 @@ def kuhn_box(
         xyz = base.copy()
         if jitter > 0.0:
             rng = np.random.Generator(np.random.PCG64(seed + 7919 * attempt))
-            if periodic:
+            if all(per_axis):
                 nv = nx * ny * nz
                 d = rng.uniform(-jitter, jitter, size=(nv, 3)) * h
                 xyz += d[topo]
-            else:
+            elif not any(per_axis):
                 nv = (nx + 1) * (ny + 1) * (nz + 1)
                 d = rng.uniform(-jitter, jitter, size=(nv, 3)) * h
                 interior = (
@@ -119,6 +122,16 @@ def kuhn_box(
                 d[~interior] = 0.0
                 gid = (corners[..., 0] * (ny + 1) + corners[..., 1]) * (nz + 1) + corners[..., 2]
                 xyz += d[gid]
+            else:
+                nv = int(topo.max()) + 1
+                d = rng.uniform(-jitter, jitter, size=(nv, 3)) * h
+                fixed = np.zeros(corners.shape[:-1], dtype=bool)
+                for a, n_a in enumerate((nx, ny, nz)):
+                    if not per_axis[a]:
+                        fixed |= (corners[..., a] == 0) | (corners[..., a] == n_a)
+                dv = d[topo]
+                dv[fixed] = 0.0
+                xyz += dv
         dets = np.linalg.det(
             np.stack([xyz[:, 1] - xyz[:, 0], xyz[:, 2] - xyz[:, 0], xyz[:, 3] - xyz[:, 0]], axis=-1)
         )
@@ -127,7 +140,7 @@ def kuhn_box(
         attempt += 1
         if attempt > 50:
             raise RuntimeError("could not draw a valid jittered mesh")
-    period = L.copy() if periodic else None
+    period = np.where(per_axis, L, 0.0) if any(per_axis) else None
     return TetMesh(
         elem_xyz=np.ascontiguousarray(xyz),
         elem_topo=np.ascontiguousarray(topo),
@@ -137,11 +150,14 @@ def kuhn_box(
     )
 
 
-def _vectorised_ids(corners, nx, ny, nz, periodic):
-    i, j, k = corners[..., 0], corners[..., 1], corners[..., 2]
-    if periodic:
-        return ((i % nx) * ny + (j % ny)) * nz + (k % nz)
-    return (i * (ny + 1) + j) * (nz + 1) + k
+def _vectorised_ids(corners, nx, ny, nz, per_axis):
+    ids = []
+    sizes = []
+    for a, n_a in enumerate((nx, ny, nz)):
+        c = corners[..., a]
+        ids.append(c % n_a if per_axis[a] else c)
+        sizes.append(n_a if per_axis[a] else n_a + 1)
+    return (ids[0] * sizes[1] + ids[1]) * sizes[2] + ids[2]
 
 
 _EVEN_PERMS4 = [

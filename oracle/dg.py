@@ -29,6 +29,13 @@ Walls (unpaired faces; the paper is silent): mirror ghost state with the
 element's own coefficients -- acoustic p^+ = p^-, v_n^+ = -v_n^- (rigid wall);
 elastic v^+ = v^-, (s n)^+ = -(s n)^- (traction-free).
 
+Absorbing faces (an optional subset of the unpaired faces; Sec. 5 names
+artificial boundary conditions as future work, so the reading is ours): the
+exterior state is zero, with the element's own coefficients.  The upwind
+flux of Sec. 2.1 then solves the Riemann problem against a medium at rest,
+so no characteristic enters through the face: acoustic alpha reduces to
+-(p - Z v_n)^-/2, the element's own incoming characteristic.
+
 Time stepping (eq. (4)): q^{m+1} = q^m + dt (a1 r^m + a2 r^{m-1} + a3 r^{m-2}),
 a = (23, -16, 5)/12.  The paper is silent on the start: step 0 uses forward
 Euler, step 1 the two-step formula (3/2, -1/2), unless the history is given.
@@ -57,7 +64,7 @@ def ab3_coefficients(m: int):
 class _Base:
     nfields = 0
 
-    def __init__(self, mesh: MeshGeometry, coef: np.ndarray):
+    def __init__(self, mesh: MeshGeometry, coef: np.ndarray, absorbing=None):
         self.mesh = mesh
         self.ref = mesh.ref
         # real coefficients in float64; complex ones are kept (complex-step
@@ -68,6 +75,11 @@ class _Base:
         if self.coef.shape != (mesh.K, self.ncoef):
             raise ValueError("coefficient array has the wrong shape")
         self.K = mesh.K
+        if absorbing is None:
+            absorbing = np.zeros((mesh.K, 4), dtype=bool)
+        self.absorbing = np.asarray(absorbing, dtype=bool)
+        if self.absorbing.shape != (mesh.K, 4) or np.any(self.absorbing & ~mesh.wall):
+            raise ValueError("absorbing faces must be a (K, 4) mask of unpaired faces")
         # neighbour lookups for every face node (walls point to themselves)
         K, Nfp = mesh.K, self.ref.Nfp
         kk = np.repeat(np.arange(K)[:, None], 4, axis=1)
@@ -116,8 +128,8 @@ class AcousticOracle(_Base):
     nfields = 4
     ncoef = 2  # (rho, c)
 
-    def __init__(self, mesh, coef):
-        super().__init__(mesh, coef)
+    def __init__(self, mesh, coef, absorbing=None):
+        super().__init__(mesh, coef, absorbing)
         rho, c = self.coef[:, 0], self.coef[:, 1]
         self.rho, self.c = rho, c
         self.Z = rho * c
@@ -146,6 +158,9 @@ class AcousticOracle(_Base):
         wall = mesh.wall[..., None]
         pP = np.where(wall, pM, pP)
         vnP = np.where(wall, -vnM, vnP)
+        absorb = self.absorbing[..., None]
+        pP = np.where(absorb, 0.0, pP)
+        vnP = np.where(absorb, 0.0, vnP)
         Zm = self.Z[:, None, None]
         Zp = self.Znb[..., None]
         jp = 0.5 * (pP - pM)
@@ -182,8 +197,8 @@ class ElasticOracle(_Base):
     nfields = 9
     ncoef = 3  # (rho, lambda, mu)
 
-    def __init__(self, mesh, coef):
-        super().__init__(mesh, coef)
+    def __init__(self, mesh, coef, absorbing=None):
+        super().__init__(mesh, coef, absorbing)
         rho, lam, mu = self.coef[:, 0], self.coef[:, 1], self.coef[:, 2]
         if np.any(np.real(mu) <= 0.0):
             raise ValueError("the elastic flux needs mu > 0")
@@ -234,6 +249,9 @@ class ElasticOracle(_Base):
         wall = mesh.wall[None, :, :, None].transpose(1, 0, 2, 3)  # (K,1,4,1)
         vP = np.where(wall, vM, vP)
         tP = np.where(wall, -tM, tP)
+        absorb = self.absorbing[:, None, :, None]
+        vP = np.where(absorb, 0.0, vP)
+        tP = np.where(absorb, 0.0, tP)
         jv = 0.5 * (vP - vM)  # (K, 3, 4, Nfp)
         jt = 0.5 * (tP - tM)
         jvn = np.einsum("kifx,kfi->kfx", jv, n)
@@ -301,11 +319,13 @@ class ElasticOracle(_Base):
         return float(e.sum())
 
 
-def make_oracle(physics: str, mesh: MeshGeometry, coef: np.ndarray):
+def make_oracle(physics: str, mesh: MeshGeometry, coef: np.ndarray, absorbing=None):
+    """``absorbing``: optional (K, 4) bool mask of unpaired faces that absorb
+    instead of reflecting."""
     if physics == "acoustic":
-        return AcousticOracle(mesh, coef)
+        return AcousticOracle(mesh, coef, absorbing)
     if physics == "elastic":
-        return ElasticOracle(mesh, coef)
+        return ElasticOracle(mesh, coef, absorbing)
     raise ValueError(physics)
 
 

@@ -98,7 +98,8 @@ def build_mesh(N: int, elem_xyz: np.ndarray, elem_topo: np.ndarray, period=None)
         b = xf[k2, f2]
         d = a[:, :, None, :] - b[:, None, :, :]
         if per is not None:
-            d = d - per * np.round(d / per)
+            # axes with a zero period are not periodic
+            d = d - per * np.round(d / np.where(per > 0.0, per, 1.0))
         dist = np.linalg.norm(d, axis=-1)  # (B, Nfp, Nfp)
         j = np.argmin(dist, axis=-1)
         if np.max(np.take_along_axis(dist, j[..., None], -1)) > 1e-9:

@@ -125,18 +125,25 @@ def test_misfit_vanishes_at_the_data(physics):
     assert np.abs(g).max() <= 1e-9 * scale
 
 
+@pytest.mark.parametrize("absorbing", [False, True])
 @pytest.mark.parametrize("physics", ["acoustic", "elastic"])
-def test_transpose_identity(physics):
+def test_transpose_identity(physics, absorbing):
     """A^T = P W A P W^{-1}: W the energy weight (J M times the material
     block), P = +1 on p / stresses and -1 on velocities.  It follows from
     exact summation by parts on affine elements and the symmetric,
     velocity/stress-decoupled upwind dissipation, and lets the adjoint run on
-    the forward operator."""
+    the forward operator.  Absorbing faces keep it: their boundary term is
+    -1/2 W |A_n|, and |A_n| couples velocities with velocities and stresses
+    (pressure) with stresses only."""
     N = 2
     mesh = di.kuhn_box(2, 1, 1, jitter=0.15, seed=3)
     geo = build_mesh(N, mesh.elem_xyz, mesh.elem_topo)
     coef = di.acoustic_loguniform(mesh, 5) if physics == "acoustic" else di.elastic_loguniform(mesh, 5)
-    o = make_oracle(physics, geo, coef)
+    mask = None
+    if absorbing:  # every other unpaired face
+        mask = geo.wall & (np.arange(geo.K * 4).reshape(geo.K, 4) % 2 == 0)
+        assert 0 < mask.sum() < geo.wall.sum()
+    o = make_oracle(physics, geo, coef, absorbing=mask)
     K, NF, Np = geo.K, o.nfields, geo.ref.Np
     n = K * NF * Np
     A = np.zeros((n, n))
