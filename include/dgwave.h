@@ -210,6 +210,22 @@ dg_status dg_rhs(dg_solver* s, const float* q, float* r);
  * trajectory).  tol defaults to 1e-4, see dg_set_energy_tolerance.          */
 dg_status dg_energy(dg_solver* s, double* e);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * of dg_energy, computed by the same kernels, written to the device float64
+ * *e_dev on the solver's stream without synchronising, without a host copy
+ * and without the growth check.  The per-workgroup partial sums go to a
+ * static device array of the library (16384 float64, 128 KiB, one per
+ * device, held until the process ends) instead of the solver's buffers; the
+ * call allocates nothing.  Meshes that need more partial sums than that
+ * (elements per energy workgroup: 64 at N = 1 down to 3 at elastic N = 6,
+ * e.g. acoustic N = 5 beyond 65536 elements) get DG_E_SHAPE.  Every call on
+ * one device shares that array: calls that overlap on one GPU (from
+ * different streams or threads) race and may return wrong sums; calls on one
+ * stream are ordered and safe.  Errors: DG_E_ARG (null e_dev), DG_E_SHAPE,
+ * DG_E_STATE (no coefficients or fields), DG_E_HIP.                         */
+dg_status dg_energy_noalloc(dg_solver* s, double* e_dev);
+
 /* Growth tolerance of dg_energy's stability check (>= 0); a negative value
  * disables the growth check (non-finite energies are still flagged).
  * Errors: DG_E_ARG (NaN).                                                    */

@@ -86,6 +86,7 @@ SIGNATURES = {
     "dg_step": (C.c_int, [_p, C.c_int, C.c_double]),
     "dg_rhs": (C.c_int, [_p, _p, _p]),
     "dg_energy": (C.c_int, [_p, _dp]),
+    "dg_energy_noalloc": (C.c_int, [_p, _p]),
     "dg_set_energy_tolerance": (C.c_int, [_p, C.c_double]),
     "dg_debug_buffer": (C.c_int, [_p, C.c_char_p, _p, C.POINTER(C.c_size_t)]),
     "dg_autotune": (C.c_int, [_p, C.c_int, C.c_double, C.c_uint, _dp]),

@@ -626,6 +626,32 @@ dg_status dg_energy(dg_solver* s, double* e) {
   return DG_OK;
 }
 
+dg_status dg_energy_noalloc(dg_solver* s, double* e_dev) {
+  if (dg_status st = check_solver(s)) return st;
+  if (!e_dev) {
+    set_error("null output");
+    return DG_E_ARG;
+  }
+  const int64_t blocks = dgw::energy_blocks(s->physics, s->N, s->K);
+  if (blocks < 1 || blocks > dgw::kStaticEnergyPartials) {
+    std::ostringstream os;
+    os << "dg_energy_noalloc: this mesh needs " << blocks << " partial sums, the static array holds "
+       << dgw::kStaticEnergyPartials << " (use dg_energy)";
+    set_error(os.str());
+    return DG_E_SHAPE;
+  }
+  if (!s->have_coef || !s->have_fields) {
+    set_error("set coefficients and fields first");
+    return DG_E_STATE;
+  }
+  double* partial = nullptr;
+  DG_HIP(dgw::static_energy_partials(s->device, &partial));
+  // every partial sum the reduction reads is written first by the same
+  // launch sequence, so the array needs no clearing
+  DG_HIP(dgw::launch_energy(s->physics, s->N, s->K, s->q, s->coef, s->J, s->mass, partial, e_dev, s->stream));
+  return DG_OK;
+}
+
 dg_status dg_set_energy_tolerance(dg_solver* s, double tol) {
   if (dg_status st = check_solver(s)) return st;
   if (std::isnan(tol)) {

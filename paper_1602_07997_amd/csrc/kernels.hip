@@ -21,9 +21,16 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "dg_device.hpp"
 #include "kernels.hpp"
+
+// Partial sums of the allocation-free energy entry point.  Each device that
+// loads the library holds its own copy until the process ends.  In host code
+// this name is only a stand-in for the symbol: the device address comes from
+// hipGetSymbolAddress (static_energy_partials below) and is what kernels get.
+static __device__ __align__(256) double scratch[dgw::kStaticEnergyPartials];
 
 namespace dgw {
 
@@ -879,6 +886,34 @@ hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int
     hipLaunchKernelGGL(dg_coef_kernel<1>, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, K,
                        coef, conn, cf);
   return hipGetLastError();
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_energy_partials(int device, double** ptr) {
+  if (device < 0 || device >= kMaxDevices || !ptr) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    int prev = 0;
+    hipError_t err = hipGetDevice(&prev);
+    if (err != hipSuccess) return err;
+    if (prev != device && (err = hipSetDevice(device)) != hipSuccess) return err;
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (err == hipSuccess) err = e2;
+    }
+    if (err != hipSuccess) return err;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 int64_t energy_blocks(int physics, int N, int64_t K) {

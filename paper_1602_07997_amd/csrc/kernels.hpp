@@ -147,5 +147,11 @@ int64_t energy_blocks(int physics, int N, int64_t K);
 hipError_t launch_energy(int physics, int N, int64_t K, const float* q, const float* coef,
                          const double* J, const double* mass, double* partial, double* out,
                          hipStream_t s);
+// Partial sums of the allocation-free energy entry point live in a static
+// device array of this many doubles (one copy per device, in kernels.hip).
+constexpr int64_t kStaticEnergyPartials = 16384;
+// Device address of that array on `device` (looked up once per device, with
+// the device current, and cached).
+hipError_t static_energy_partials(int device, double** ptr);
 
 }  // namespace dgw
