@@ -187,6 +187,29 @@ def relabel_vertices(mesh: TetMesh, seed: int) -> TetMesh:
     )
 
 
+def graded_kuhn_box(n_fine: int, n_coarse: int, split: float = 0.5, periodic=False) -> TetMesh:
+    """Kuhn box on the unit cube graded along every axis: cells are
+    split / n_fine wide below `split` and (1 - split) / n_coarse wide above,
+    so the corner region [0, split)^3 holds the smallest elements and
+    [split, 1]^3 the largest (a mesh for local time stepping); ``periodic``
+    as in ``kuhn_box``."""
+    n = n_fine + n_coarse
+    base = kuhn_box(n, n, n, lengths=(float(n),) * 3, periodic=periodic)
+    i = base.elem_xyz  # integer node indices (unwrapped)
+    x = np.where(i <= n_fine, i * (split / n_fine), split + (i - n_fine) * ((1.0 - split) / n_coarse))
+    period = None if base.period is None else np.where(base.period > 0, 1.0, 0.0)
+    return TetMesh(elem_xyz=np.ascontiguousarray(x), elem_topo=base.elem_topo, period=period,
+                   dims=base.dims, lengths=(1.0, 1.0, 1.0))
+
+
+def permute_elements(mesh: TetMesh, order: np.ndarray) -> TetMesh:
+    """The same mesh with element i of the result being element order[i]."""
+    order = np.asarray(order, dtype=np.int64)
+    return TetMesh(elem_xyz=np.ascontiguousarray(mesh.elem_xyz[order]),
+                   elem_topo=np.ascontiguousarray(mesh.elem_topo[order]),
+                   period=mesh.period, dims=mesh.dims, lengths=mesh.lengths)
+
+
 def element_centroids(mesh: TetMesh) -> np.ndarray:
     return mesh.elem_xyz.mean(axis=1)
 
@@ -353,6 +376,29 @@ CFL_DEFAULT = 0.5
 def time_step(mesh: TetMesh, N: int, cmax: float, cfl: float = CFL_DEFAULT) -> float:
     """dt = cfl * min inradius / (cmax * (N+1)^2), from raw vertex geometry."""
     return float(cfl * inradius(mesh).min() / (cmax * (N + 1) ** 2))
+
+
+def local_time_steps(mesh: TetMesh, N: int, c_elem: np.ndarray, cfl: float = CFL_DEFAULT) -> np.ndarray:
+    """Per-element step cfl * inradius_k / (c_k (N+1)^2), the recipe of
+    ``time_step`` element by element (c_k: the element's fastest speed)."""
+    return cfl * inradius(mesh) / (np.asarray(c_elem, dtype=float) * (N + 1) ** 2)
+
+
+def two_rate_classes(mesh: TetMesh, N: int, c_elem: np.ndarray, cfl: float = CFL_DEFAULT):
+    """(fast mask, macro step): the macro step is twice the smallest local
+    step, and an element is fast when its local step is below the macro
+    step (it then takes two half steps)."""
+    dtk = local_time_steps(mesh, N, c_elem, cfl)
+    dt = 2.0 * float(dtk.min())
+    return dtk < dt, dt
+
+
+def element_wave_speeds(coef: np.ndarray, physics: str) -> np.ndarray:
+    """Fastest wave speed of every element (c, or c_p = sqrt((lam + 2 mu)/rho))."""
+    coef = np.asarray(coef, dtype=float)
+    if physics == "acoustic":
+        return coef[:, 1]
+    return np.sqrt((coef[:, 1] + 2.0 * coef[:, 2]) / coef[:, 0])
 
 
 def n_nodes(N: int) -> int:
