@@ -51,7 +51,7 @@ if ROOT not in sys.path:
 
 import dginputs as di  # noqa: E402
 
-FP32_VARIANTS = ("valu", "mfma", "elem")  # candidates of the FP32 autotuned path
+FP32_VARIANTS = ("valu", "mfma", "elem", "mfma_wide")  # candidates of the FP32 autotuned path (kernels and tile shapes)
 METRIC = "DG node-updates/s and % roofline, acoustic+elastic N=1..8: FP32 vs mixed/batched"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 FP32_PEAK = 157.3e12  # flop/s, MI355X FP32 vector / matrix
@@ -95,6 +95,9 @@ def kernel_name(physics: str, N: int, variant: str) -> str:
         return f"dg_step_kernel<N={N},{physics}>"
     if variant == "elem":
         return f"dg_step_elem_kernel<N={N},{physics}>"
+    if physics == "acoustic":
+        cfg = {"mfma": 0, "mfma_bf16": 1, "mfma_f16": 2, "mfma_wide": 4}[variant]
+        return f"dg_step_mfma_acoustic<N={N},CFG={cfg}>"
     prec = {"mfma": 0, "mfma_bf16": 1, "mfma_f16": 2}[variant]
     return f"dg_step_mfma_{physics}<N={N},PREC={prec}>"
 

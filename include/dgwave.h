@@ -36,7 +36,16 @@
  *             without a partner are reflecting walls (mirror ghost state:
  *             rigid wall for acoustics, traction-free for elasticity).
  *             Periodic boxes identify vertices through elem_topo while
- *             elem_xyz keeps unwrapped coordinates.
+ *             elem_xyz keeps unwrapped coordinates.  dg_set_boundary turns
+ *             chosen unpaired faces into absorbing ones.
+ *
+ * Device memory: the library allocates none.  A solver, a batch and a misfit
+ * each live in one caller-owned device buffer, the workspace, whose size the
+ * matching *_workspace_bytes query gives (host-side, no GPU work); the buffer
+ * must start on a 256-byte boundary (torch and hipMalloc allocations do),
+ * must outlive the handle, and is used only by that handle.  The autotuner
+ * takes a caller scratch array for its timed steps.  This follows the
+ * paper's model of allocating everything once at start (Sec. 3.1).
  *
  * Pointers named "device" must point to GPU memory of the device current when
  * the solver was created; they are used stream-ordered on the solver's
@@ -120,20 +129,33 @@ dg_status dg_mesh_connectivity(int64_t K, const int64_t* elem_topo, int64_t* e2e
 /* Solver (needs a GPU).                                                    */
 /* ------------------------------------------------------------------------ */
 
+/* Bytes of device workspace a solver of this physics, degree and element
+ * count needs (*bytes, host): fields, the AB3 ring of eq. (4), trace
+ * buffers, geometry and coefficient arrays and the operator tables of
+ * eqs. (5)-(6) in every kernel layout.  Host-only; no GPU needed.  Errors:
+ * DG_E_ARG (unknown physics, K outside [1, 2^26), null output),
+ * DG_E_UNSUPPORTED (order outside [1, 8]).                                  */
+dg_status dg_workspace_bytes(int physics, int order, int64_t K, size_t* bytes);
+
 /* Create a solver for `K` elements of degree `order`.  elem_xyz (host
  * float64 [K][4][3]) and elem_topo (host int64 [K][4]) are copied; the
  * geometry (per-element inverse Jacobian G[i][j] = d r_j / d x_i, the volume
  * factor of eq. (3); face normals and Fscale = sJ/J, the surface factor) and
- * connectivity are built on the host in float64 and uploaded.  `stream` is a
- * hipStream_t (NULL = default stream) used by every later call.  Device
- * memory is allocated here and freed by dg_destroy.  K must lie in
- * [1, 2^26) (the per-face connectivity word packs the neighbour index in 26
- * bits).  Errors: DG_E_ARG (K out of range, null arrays), DG_E_UNSUPPORTED,
- * DG_E_MESH (J <= 0, inconsistent face pairing), DG_E_HIP.                    */
+ * connectivity are built on the host in float64 and uploaded, together with
+ * the reference operators (uploaded once, Sec. 3.1), into `workspace`
+ * (device, workspace_bytes >= dg_workspace_bytes, 256-byte aligned, owned by
+ * the caller, outliving the solver).  `stream` is a hipStream_t (NULL =
+ * default stream) used by every later call; the call synchronises it.  K must
+ * lie in [1, 2^26) (the per-face connectivity word packs the neighbour index
+ * in 26 bits).  Errors: DG_E_ARG (K out of range, null or misaligned arrays),
+ * DG_E_SHAPE (workspace too small), DG_E_UNSUPPORTED, DG_E_MESH (J <= 0,
+ * inconsistent face pairing), DG_E_HIP.                                     */
 dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz,
-                    const int64_t* elem_topo, void* stream, dg_solver** out);
+                    const int64_t* elem_topo, void* workspace, size_t workspace_bytes, void* stream,
+                    dg_solver** out);
 
-/* Release the solver and its device memory (synchronises its stream). */
+/* Release the solver (synchronises its stream); its workspace is the
+ * caller's to free afterwards. */
 void dg_destroy(dg_solver* s);
 
 /* Replace the stream used by later calls (hipStream_t, NULL = default). */
@@ -149,7 +171,13 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
  *                         D_hi x_hi + D_hi x_lo + D_lo x_hi;
  *   DG_VARIANT_MFMA_F16   the same with FP16 halves;
  *   DG_VARIANT_ELEM       one element per thread, all in registers
- *                         (acoustic N = 1, 2; elastic N = 1).
+ *                         (acoustic N = 1, 2; elastic N = 1);
+ *   DG_VARIANT_MFMA_WIDE  FP32 matrix cores with the other acoustic tile
+ *                         shape: twice the elements and wavefronts per
+ *                         workgroup from N = 4, half the elements below
+ *                         (acoustic only), a tile-shape candidate for
+ *                         dg_autotune (the paper tunes its elements per
+ *                         block per degree, Sec. 3.2 and Table 5).
  * The VALU and MFMA variants are built for both physics and N = 1..8.
  * Fields, r and the update stay FP32 in every variant.  Returns
  * DG_E_UNSUPPORTED for a combination that is not built.                    */
@@ -158,6 +186,7 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
 #define DG_VARIANT_MFMA_BF16 2
 #define DG_VARIANT_MFMA_F16 3
 #define DG_VARIANT_ELEM 4
+#define DG_VARIANT_MFMA_WIDE 5
 dg_status dg_set_variant(dg_solver* s, int variant);
 dg_status dg_get_variant(dg_solver* s, int* variant);
 
@@ -169,9 +198,27 @@ dg_status dg_node_coordinates(dg_solver* s, double* xyz);
 
 /* Material coefficients per element, device float32: acoustic [K][2]
  * (rho, c); elastic [K][3] (rho, lambda, mu), all > 0 (mu > 0 is required by
- * the elastic flux).  Derived per-face impedances of the neighbours are
- * computed on the device.  Must precede dg_step/dg_rhs.                     */
+ * the elastic flux).  Validated on the device (synchronises); derived
+ * per-face impedances of the neighbours are computed on the device.  Must
+ * precede dg_step/dg_rhs.  Errors: DG_E_ARG (null, or a value that is not
+ * positive and finite: the solver then has no coefficients until the next
+ * successful call), DG_E_HIP.                                               */
 dg_status dg_set_coefficients(dg_solver* s, const float* coef);
+
+/* Kind of each unpaired face, host int32 [K][4]: DG_BC_REFLECT (the default
+ * of dg_create: mirror ghost state, rigid wall for acoustics, traction-free
+ * for elasticity) or DG_BC_ABSORB.  Sec. 5 lists artificial boundary
+ * conditions as future work; the reading here: an absorbing face sees a
+ * zero exterior state with the element's own coefficients, so that the
+ * upwind flux of Sec. 2.1 lets no characteristic enter (acoustic alpha
+ * becomes -(p - Z v.n)/2 of the element's own trace).  Entries of faces that
+ * have a neighbour must be DG_BC_REFLECT.  May be called at any time (the
+ * next step uses it); the misfit gradient supports both kinds.  Synchronises
+ * the solver's stream.  Errors: DG_E_ARG (null, an unknown kind, an
+ * absorbing face that has a neighbour), DG_E_HIP.                           */
+#define DG_BC_REFLECT 0
+#define DG_BC_ABSORB 1
+dg_status dg_set_boundary(dg_solver* s, const int32_t* kind);
 
 /* Set the fields (device float32 [K][Nfields][Np]); resets the step counter
  * to 0 so that the next steps use the Euler / two-step start-up.            */
@@ -182,7 +229,7 @@ dg_status dg_get_fields(dg_solver* s, float* q);
 
 /* Full AB3 state for checkpoint / resume: q^m, r^{m-1}, r^{m-2} (device
  * float32, each [K][Nfields][Np]; r1/r2 ignored when step_index < 1 / < 2)
- * and the step index m.                                                     */
+ * and the step index m.  DG_E_UNSUPPORTED on a two-rate solver.             */
 dg_status dg_set_state(dg_solver* s, const float* q, const float* r1, const float* r2,
                        int64_t step_index);
 dg_status dg_get_state(dg_solver* s, float* q, float* r1, float* r2, int64_t* step_index);
@@ -191,8 +238,29 @@ dg_status dg_get_state(dg_solver* s, float* q, float* r1, float* r2, int64_t* st
 dg_status dg_step_index(dg_solver* s, int64_t* m);
 
 /* Advance `nsteps` steps of size dt (eq. (4)); one fused kernel per step,
- * asynchronous on the solver's stream.                                      */
+ * asynchronous on the solver's stream.  Errors: DG_E_ARG, DG_E_STATE (no
+ * coefficients or fields, or a fast class set: see dg_step_multirate).      */
 dg_status dg_step(dg_solver* s, int nsteps, double dt);
+
+/* Two-rate (local) time stepping, which Sec. 1 names as an advantage of DG
+ * and Sec. 5 calls essential for large meshes without giving a scheme; the
+ * reading here: elements [0, k_fast) form a fast class that takes two steps
+ * of dt/2 per step dt of the slow class [k_fast, K) (the caller orders the
+ * elements so, e.g. by local CFL step).  Each class runs eq. (4) with its
+ * own right-hand-side history and Euler / two-step start-up.  Per macro
+ * step: (1) fast half step from t_n; (2) slow full step from t_n; (3) the
+ * traces at t_n + dt/2 of the slow elements next to fast ones, from the
+ * integral of their Adams-Bashforth history polynomial over the half step
+ * (17/24, -7/24, 1/12 in AB3, the half-step analogue of eq. (4)'s
+ * weights); (4) fast half step from t_n + dt/2.  dg_set_rate_classes sets
+ * the split (k_fast in [0, K]; 0 = single rate) and restarts the start-up;
+ * it synchronises.  A solver with k_fast > 0 steps only with
+ * dg_step_multirate (dg_step, dg_set_state, dg_get_state and batches refuse
+ * it: its history is per class); dg_step_multirate with k_fast = 0 is
+ * dg_step.  The step index counts macro steps.  Errors: DG_E_ARG,
+ * DG_E_STATE (no coefficients or fields), DG_E_HIP.                         */
+dg_status dg_set_rate_classes(dg_solver* s, int64_t k_fast);
+dg_status dg_step_multirate(dg_solver* s, int nsteps, double dt);
 
 /* One evaluation of the right-hand side r(q) of eqs. (2)-(3): q and r are
  * device float32 [K][Nfields][Np]; does not touch the solver's state.       */
@@ -248,20 +316,24 @@ dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* byt
 /* ------------------------------------------------------------------------ */
 
 /* Time the kernel variants built for the solver's physics and degree on the
- * solver's own mesh: `steps` steps of size dt each, after one untimed step,
- * timed with HIP events on the solver's stream.  `candidates` is a bit mask
- * of the variants to consider (bit v for variant v; 0 = all of them).  The state (fields, AB3
- * history, traces, step index) is saved to temporary device memory before
- * and restored after, so the call does not advance the solution; it
- * synchronises.  The fastest variant becomes the solver's variant.
+ * solver's own mesh: `steps` steps of size dt each with the AB3 weights of
+ * eq. (4), after one untimed step, timed with HIP events on the solver's
+ * stream.  `candidates` is a bit mask of the variants to consider (bit v for
+ * variant v; 0 = all of them).  Every timed step reads the current state
+ * and writes its fields into `scratch` (device, scratch_bytes >= K*Nfields*Np
+ * float32), its r into the ring slot of r^{m-3} and its traces into the
+ * buffer the next step overwrites, so the state (fields, AB3 history,
+ * traces, step index) does not change; the call synchronises.  The fastest
+ * variant becomes the solver's variant.
  * us_per_step (host float64 [DG_NUM_VARIANTS], may be NULL) receives the
  * microseconds per step of each variant, -1 where not built or not a
  * candidate.  The choice of
  * kernel per degree and mesh follows the observation of Sec. 4 that the best
  * implementation strategy depends on the degree.  Errors: DG_E_STATE (no
  * coefficients or fields), DG_E_ARG, DG_E_HIP.                              */
-#define DG_NUM_VARIANTS 5
-dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, double* us_per_step);
+#define DG_NUM_VARIANTS 6
+dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, void* scratch,
+                      size_t scratch_bytes, double* us_per_step);
 
 typedef struct dg_batch dg_batch;
 
@@ -272,18 +344,28 @@ typedef struct dg_batch dg_batch;
  * the batch keeps the pointers (not ownership): every member must outlive
  * the batch.  Each member keeps its own buffers, coefficients and variant
  * (the groups are rebuilt when a member's variant changes).  `stream` is the
- * hipStream_t all batched work runs on (NULL = default stream).  Device
- * memory for the work lists and argument tables is allocated here.  Errors:
- * DG_E_ARG (null, repeated or mixed-physics members), DG_E_HIP.             */
-dg_status dg_batch_create(dg_solver* const* members, int count, void* stream, dg_batch** out);
+ * hipStream_t the batched work is ordered on (NULL = default stream): with
+ * more than one group, each step forks onto one library-owned stream per
+ * group (default priority) and joins back, so that the groups' launches
+ * overlap; the members are independent meshes.  The work
+ * lists and argument tables live in `workspace` (device, workspace_bytes >=
+ * dg_batch_workspace_bytes, 256-byte aligned, owned by the caller and
+ * outliving the batch).  Errors: DG_E_ARG (null, repeated or mixed-physics
+ * members, bad workspace), DG_E_SHAPE (workspace too small), DG_E_HIP.      */
+dg_status dg_batch_create(dg_solver* const* members, int count, void* workspace, size_t workspace_bytes,
+                          void* stream, dg_batch** out);
+
+/* Workspace bytes of a batch of these members (*bytes, host): enough for
+ * every choice of their kernel variants.  Errors: DG_E_ARG.                 */
+dg_status dg_batch_workspace_bytes(dg_solver* const* members, int count, size_t* bytes);
 
 /* Release the batch (synchronises its stream; members are untouched). */
 void dg_batch_destroy(dg_batch* b);
 
 /* Record six consecutive batched steps in a HIP graph and replay it for
  * whole runs of six steps (enable = 1), or launch kernel by kernel (0, the
- * default).  The graph holds kernel nodes only; it needs a non-NULL stream
- * (DG_E_STATE otherwise).                                                    */
+ * default).  The graph holds kernel nodes only, one independent chain of six
+ * per launch group; it needs a non-NULL stream (DG_E_STATE otherwise).      */
 dg_status dg_batch_set_graph(dg_batch* b, int enable);
 
 /* Advance every member by `nsteps` steps of eq. (4); dt is host float64
@@ -324,14 +406,24 @@ typedef struct dg_misfit dg_misfit;
  *   misfit: J = 1/2 dt sum_{m=1..nsteps} sum_channels (u - d)^2.
  * src_xyz / rec_xyz are host float64 [n][3].  The forward states are kept
  * every checkpoint_every steps; the gradient recomputes the steps between
- * checkpoints.  Device memory: about (checkpoint_every + 3 nsteps /
- * checkpoint_every + 9) field arrays.  The solver must outlive the misfit;
- * the misfit uses its own state buffers (the solver's fields are not
- * touched).  Errors: DG_E_ARG (bad sizes, a point outside the mesh),
- * DG_E_HIP.                                                                  */
+ * checkpoints.  Its device arrays, about (checkpoint_every + 3 nsteps /
+ * checkpoint_every + 9) field arrays, live in `workspace` (device,
+ * workspace_bytes >= dg_misfit_workspace_bytes of the same arguments,
+ * 256-byte aligned, owned by the caller and outliving the misfit).  The
+ * solver must outlive the misfit; the misfit uses its own state buffers (the
+ * solver's fields are not touched).  Errors: DG_E_ARG (bad sizes, a point
+ * outside the mesh, bad workspace), DG_E_SHAPE (workspace too small),
+ * DG_E_HIP.                                                                 */
 dg_status dg_misfit_create(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
                            const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
-                           dg_misfit** out);
+                           void* workspace, size_t workspace_bytes, dg_misfit** out);
+
+/* Workspace bytes of dg_misfit_create with the same arguments (*bytes,
+ * host; locates the points on the host, no GPU work).  Errors as
+ * dg_misfit_create's argument checks.                                       */
+dg_status dg_misfit_workspace_bytes(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
+                                    const double* src_xyz, const double* wavelet, int nrec,
+                                    const double* rec_xyz, size_t* bytes);
 void dg_misfit_destroy(dg_misfit* f);
 
 /* Number of receiver channels, or -1 for a NULL misfit. */

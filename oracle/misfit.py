@@ -75,9 +75,10 @@ class MisfitProblem:
     """Forward solve with a point source and receivers, and the misfit."""
 
     def __init__(self, physics: str, mesh: MeshGeometry, elem_xyz: np.ndarray, dt: float, nsteps: int,
-                 src_xyz, rec_xyz, f0: float, t0: float | None = None):
+                 src_xyz, rec_xyz, f0: float, t0: float | None = None, absorbing=None):
         self.physics = physics
         self.mesh = mesh
+        self.absorbing = absorbing  # optional (K, 4) mask of absorbing unpaired faces
         self.ref = mesh.ref
         self.dt = float(dt)
         self.nsteps = int(nsteps)
@@ -116,7 +117,7 @@ class MisfitProblem:
         """Receiver traces (nsteps + 1, channels) from the zero state; the
         arithmetic follows the coefficients' dtype (complex for the complex
         step)."""
-        o = make_oracle(self.physics, self.mesh, coef)
+        o = make_oracle(self.physics, self.mesh, coef, absorbing=self.absorbing)
         dtype = np.result_type(np.asarray(coef).dtype, float)
         q = np.zeros((self.mesh.K, self.nfields, self.ref.Np), dtype=dtype)
         traces = [self.record(q)]

@@ -28,7 +28,10 @@ DG_VARIANT_MFMA = 1
 DG_VARIANT_MFMA_BF16 = 2
 DG_VARIANT_MFMA_F16 = 3
 DG_VARIANT_ELEM = 4
-DG_NUM_VARIANTS = 5
+DG_VARIANT_MFMA_WIDE = 5
+DG_NUM_VARIANTS = 6
+DG_BC_REFLECT = 0
+DG_BC_ABSORB = 1
 
 STATUS_NAMES = {
     DG_OK: "DG_OK",
@@ -60,6 +63,7 @@ _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
+_szp = C.POINTER(C.c_size_t)
 
 # name -> (restype, argtypes); mirrors include/dgwave.h
 SIGNATURES = {
@@ -70,7 +74,8 @@ SIGNATURES = {
     "dg_reference_operators": (C.c_int, [C.c_int, _dp, _dp, _dp, _dp, _i32p]),
     "dg_face_permutations": (C.c_int, [C.c_int, _i32p]),
     "dg_mesh_connectivity": (C.c_int, [_i64, _i64p, _i64p, _i32p, _i32p]),
-    "dg_create": (C.c_int, [C.c_int, C.c_int, _i64, _dp, _i64p, _p, C.POINTER(_p)]),
+    "dg_workspace_bytes": (C.c_int, [C.c_int, C.c_int, _i64, _szp]),
+    "dg_create": (C.c_int, [C.c_int, C.c_int, _i64, _dp, _i64p, _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dg_destroy": (None, [_p]),
     "dg_set_stream": (C.c_int, [_p, _p]),
     "dg_synchronize": (C.c_int, [_p]),
@@ -78,26 +83,33 @@ SIGNATURES = {
     "dg_get_variant": (C.c_int, [_p, _ip]),
     "dg_node_coordinates": (C.c_int, [_p, _dp]),
     "dg_set_coefficients": (C.c_int, [_p, _p]),
+    "dg_set_boundary": (C.c_int, [_p, _i32p]),
     "dg_set_fields": (C.c_int, [_p, _p]),
     "dg_get_fields": (C.c_int, [_p, _p]),
     "dg_set_state": (C.c_int, [_p, _p, _p, _p, _i64]),
     "dg_get_state": (C.c_int, [_p, _p, _p, _p, _i64p]),
     "dg_step_index": (C.c_int, [_p, _i64p]),
     "dg_step": (C.c_int, [_p, C.c_int, C.c_double]),
+    "dg_set_rate_classes": (C.c_int, [_p, _i64]),
+    "dg_step_multirate": (C.c_int, [_p, C.c_int, C.c_double]),
     "dg_rhs": (C.c_int, [_p, _p, _p]),
     "dg_energy": (C.c_int, [_p, _dp]),
     "dg_energy_noalloc": (C.c_int, [_p, _p]),
     "dg_set_energy_tolerance": (C.c_int, [_p, C.c_double]),
     "dg_debug_buffer": (C.c_int, [_p, C.c_char_p, _p, C.POINTER(C.c_size_t)]),
-    "dg_autotune": (C.c_int, [_p, C.c_int, C.c_double, C.c_uint, _dp]),
-    "dg_batch_create": (C.c_int, [C.POINTER(_p), C.c_int, _p, C.POINTER(_p)]),
+    "dg_autotune": (C.c_int, [_p, C.c_int, C.c_double, C.c_uint, _p, C.c_size_t, _dp]),
+    "dg_batch_workspace_bytes": (C.c_int, [C.POINTER(_p), C.c_int, _szp]),
+    "dg_batch_create": (C.c_int, [C.POINTER(_p), C.c_int, _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dg_batch_destroy": (None, [_p]),
     "dg_batch_set_graph": (C.c_int, [_p, C.c_int]),
     "dg_batch_step": (C.c_int, [_p, C.c_int, _dp]),
     "dg_batch_groups": (C.c_int, [_p, _ip, _i32p, _i32p, _i64p]),
     "dg_locate_points": (C.c_int, [_p, _i64, _dp, _i64p, _dp]),
+    "dg_misfit_workspace_bytes": (
+        C.c_int, [_p, _i64, C.c_double, C.c_int, C.c_int, _dp, _dp, C.c_int, _dp, _szp]
+    ),
     "dg_misfit_create": (
-        C.c_int, [_p, _i64, C.c_double, C.c_int, C.c_int, _dp, _dp, C.c_int, _dp, C.POINTER(_p)]
+        C.c_int, [_p, _i64, C.c_double, C.c_int, C.c_int, _dp, _dp, C.c_int, _dp, _p, C.c_size_t, C.POINTER(_p)]
     ),
     "dg_misfit_destroy": (None, [_p]),
     "dg_misfit_channels": (_i64, [_p]),

@@ -7,6 +7,7 @@ from __future__ import annotations
 import ctypes as C
 
 import numpy as np
+import torch
 
 from ._native import check, lib
 from .solver import DGSolver, _dptr, _require_torch_device_tensor
@@ -35,13 +36,18 @@ class DGMisfit:
         wav = np.ascontiguousarray(wavelet, dtype=np.float64) if src is not None else None
         if wav is not None and wav.shape != (self.nsteps + 1,):
             raise ValueError("wavelet must hold nsteps + 1 values")
+        args = (
+            solver._h, self.nsteps, self.dt, int(checkpoint_every),
+            0 if src is None else len(src), None if src is None else _dptr(src),
+            None if wav is None else _dptr(wav), len(rec), _dptr(rec),
+        )
+        nbytes = C.c_size_t(0)
+        check(lib.dg_misfit_workspace_bytes(*args, C.byref(nbytes)), "dg_misfit_workspace_bytes")
+        with torch.cuda.stream(solver._stream):
+            self._workspace = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
         h = C.c_void_p()
         check(
-            lib.dg_misfit_create(
-                solver._h, self.nsteps, self.dt, int(checkpoint_every),
-                0 if src is None else len(src), None if src is None else _dptr(src),
-                None if wav is None else _dptr(wav), len(rec), _dptr(rec), C.byref(h),
-            ),
+            lib.dg_misfit_create(*args, C.c_void_p(self._workspace.data_ptr()), nbytes, C.byref(h)),
             "dg_misfit_create",
         )
         self._h = h
@@ -58,6 +64,7 @@ class DGMisfit:
         if getattr(self, "_h", None):
             lib.dg_misfit_destroy(self._h)
             self._h = None
+        self._workspace = None
 
     def __del__(self):
         try:

@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "mfma_pack.hpp"
 #include "solver_state.hpp"
+#include "workspace.hpp"
 
 namespace dgw {
 
@@ -30,11 +31,6 @@ using dgw::set_error;
 
 namespace {
 
-template <class T>
-hipError_t dev_alloc(T** p, size_t count) {
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T) + (count == 0 ? 16 : 0));
-}
-
 dg_status check_solver(const dg_solver* s) {
   if (!s) {
     set_error("null solver");
@@ -43,21 +39,111 @@ dg_status check_solver(const dg_solver* s) {
   return DG_OK;
 }
 
-void free_all(dg_solver* s) {
-  void* ptrs[] = {s->q,  s->r[0], s->r[1], s->r[2], s->qf[0], s->qf[1], s->qf_tmp, s->geo,
-                  s->cf, s->coef, s->DT,   s->LT,   s->conn,  s->fmask, s->perm,   s->nodeface, s->J,
-                  s->mass, s->partial, s->e_out, s->flag, s->Dpack, s->Lpack};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+size_t field_count(const dg_solver* s) { return static_cast<size_t>(s->K) * s->NF * s->Np; }
+size_t trace_count(const dg_solver* s) { return static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp; }
+
+// Operator tables of one (physics, degree) in the kernels' layouts, built on
+// the host: D_j and LIFT transposed (node-per-thread kernel), in FP32 MFMA
+// fragment order, and as BF16 / FP16 hi + lo splits.
+struct HostTables {
+  std::vector<float> DT, LT, Dpack, Lpack;
+  std::vector<uint16_t> D16[2][2], L16[2][2];  // [bf16, f16][hi, lo]
+};
+
+HostTables make_tables(int physics, const dgw::RefElement* ref) {
+  HostTables t;
+  const int order = ref->N, Np = ref->Np, Nfp = ref->Nfp;
+  const dgw::MfmaPacking p32 = dgw::mfma_packing(physics, order, dgw::kVariantMfma);
+  const dgw::ColMap c32 = dgw::face_block_columns(Nfp, p32.KF);
+  for (int j = 0; j < 3; ++j)
+    dgw::pack_fp32(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p32.MB, p32.KP, t.Dpack);
+  dgw::pack_fp32(ref->lift.data(), Np, 4 * Nfp, p32.MB, p32.KL, t.Lpack, p32.KF > 0 ? &c32 : nullptr);
+  const int vars[2] = {dgw::kVariantMfmaBf16, dgw::kVariantMfmaF16};
+  for (int v = 0; v < 2; ++v) {
+    const dgw::MfmaPacking p16 = dgw::mfma_packing(physics, order, vars[v]);
+    const dgw::ColMap c16 = dgw::face_block_columns(Nfp, p16.KF);
+    const int kw = p16.KS / 4;  // k per lane group: 4 (16x16x16) or 8 (16x16x32)
+    for (int j = 0; j < 3; ++j)
+      dgw::pack_split16(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p16.MB, p16.KP, kw, v == 0,
+                        t.D16[v][0], t.D16[v][1]);
+    dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, kw, v == 0, t.L16[v][0], t.L16[v][1],
+                      p16.KF > 0 ? &c16 : nullptr);
+  }
+  t.DT.resize(3 * static_cast<size_t>(Np) * Np);
+  t.LT.resize(static_cast<size_t>(4) * Nfp * Np);
+  for (int j = 0; j < 3; ++j)
+    for (int n = 0; n < Np; ++n)
+      for (int mm = 0; mm < Np; ++mm)
+        t.DT[(static_cast<size_t>(j) * Np + mm) * Np + n] =
+            static_cast<float>(ref->D[(static_cast<size_t>(j) * Np + n) * Np + mm]);
+  for (int n = 0; n < Np; ++n)
+    for (int fm = 0; fm < 4 * Nfp; ++fm)
+      t.LT[static_cast<size_t>(fm) * Np + n] = static_cast<float>(ref->lift[static_cast<size_t>(n) * 4 * Nfp + fm]);
+  return t;
+}
+
+// Sizes of a solver that do not depend on the mesh's geometry.
+void set_sizes(dg_solver* s, int physics, int order, int64_t K, const dgw::RefElement* ref) {
+  s->physics = physics;
+  s->N = order;
+  s->Np = ref->Np;
+  s->Nfp = ref->Nfp;
+  s->NF = dg_num_fields(physics);
+  s->NT = dgw::num_traces(physics);
+  s->CB = dgw::coef_block(physics);
+  s->ncoef = physics == DG_ACOUSTIC ? 2 : 3;
+  s->K = K;
+}
+
+// Every device array of a solver, in one workspace (measuring when the arena
+// has no base).
+void layout(dg_solver* s, const HostTables& t, const dgw::RefElement* ref, dgw::Arena& a) {
+  const size_t K = static_cast<size_t>(s->K);
+  const size_t nq = K * s->NF * s->Np, nt = K * 4 * s->NT * s->Nfp;
+  s->q = a.take<float>(nq);
+  for (int i = 0; i < 3; ++i) s->r[i] = a.take<float>(nq);
+  for (int i = 0; i < 2; ++i) s->qf[i] = a.take<float>(nt);
+  s->qf_tmp = a.take<float>(nt);
+  s->geo = a.take<float>(K * 9);
+  s->cf = a.take<float>(K * s->CB);
+  s->coef = a.take<float>(K * s->ncoef);
+  s->DT = a.take<float>(t.DT.size());
+  s->LT = a.take<float>(t.LT.size());
+  s->conn = a.take<int32_t>(K * 4);
+  s->fmask = a.take<int32_t>(ref->fmask.size());
+  s->perm = a.take<int32_t>(ref->perm.size());
+  s->nodeface = a.take<int32_t>(ref->nodeface.size());
+  s->J = a.take<double>(K);
+  s->mass = a.take<double>(ref->mass.size());
+  s->partial = a.take<double>(static_cast<size_t>(dgw::energy_blocks(s->physics, s->N, s->K)));
+  s->e_out = a.take<double>(1);
+  s->flag = a.take<int>(1);
+  s->iface = a.take<int32_t>(K);
+  s->Dpack = a.take<float>(t.Dpack.size());
+  s->Lpack = a.take<float>(t.Lpack.size());
   for (int v = 0; v < 2; ++v)
     for (int h = 0; h < 2; ++h) {
-      if (s->D16[v][h]) (void)hipFree(s->D16[v][h]);
-      if (s->L16[v][h]) (void)hipFree(s->L16[v][h]);
+      s->D16[v][h] = a.take<uint16_t>(t.D16[v][h].size());
+      s->L16[v][h] = a.take<uint16_t>(t.L16[v][h].size());
     }
 }
 
-size_t field_count(const dg_solver* s) { return static_cast<size_t>(s->K) * s->NF * s->Np; }
-size_t trace_count(const dg_solver* s) { return static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp; }
+dg_status check_create_args(int physics, int order, int64_t K, const dgw::RefElement** ref) {
+  if (physics != DG_ACOUSTIC && physics != DG_ELASTIC) {
+    set_error("unknown physics");
+    return DG_E_ARG;
+  }
+  *ref = (order >= 1 && order <= dgw::kMaxOrder) ? dgw::reference_element(order) : nullptr;
+  if (!*ref) {
+    set_error("order must be in [1, 8]");
+    return DG_E_UNSUPPORTED;
+  }
+  if (K <= 0 || K >= (int64_t(1) << 26)) {
+    set_error("K must be in [1, 2^26)");
+    return DG_E_ARG;
+  }
+  return DG_OK;
+}
 
 }  // namespace
 
@@ -107,7 +193,7 @@ StepArgs step_args(const dg_solver* s, int64_t m, int cur, double dt) {
 
 extern "C" {
 
-int dg_abi_version(void) { return 1; }
+int dg_abi_version(void) { return 2; }
 
 const char* dg_last_error(void) { return dgw::last_error(); }
 
@@ -176,27 +262,38 @@ dg_status dg_mesh_connectivity(int64_t K, const int64_t* elem_topo, int64_t* e2e
   return DG_OK;
 }
 
+dg_status dg_workspace_bytes(int physics, int order, int64_t K, size_t* bytes) {
+  if (!bytes) {
+    set_error("null output");
+    return DG_E_ARG;
+  }
+  const dgw::RefElement* ref = nullptr;
+  if (dg_status st = check_create_args(physics, order, K, &ref)) return st;
+  dg_solver probe;
+  set_sizes(&probe, physics, order, K, ref);
+  dgw::Arena arena(nullptr, 0);
+  layout(&probe, make_tables(physics, ref), ref, arena);
+  *bytes = arena.used();
+  return DG_OK;
+}
+
 dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, const int64_t* elem_topo,
-                    void* stream, dg_solver** out) {
+                    void* workspace, size_t workspace_bytes, void* stream, dg_solver** out) {
   if (!out) {
     set_error("null output handle");
     return DG_E_ARG;
   }
   *out = nullptr;
-  if (physics != DG_ACOUSTIC && physics != DG_ELASTIC) {
-    set_error("unknown physics");
+  const dgw::RefElement* ref = nullptr;
+  if (dg_status st = check_create_args(physics, order, K, &ref)) return st;
+  if (!elem_xyz || !elem_topo) {
+    set_error("the mesh arrays must be non-null");
     return DG_E_ARG;
   }
-  const dgw::RefElement* ref = (order >= 1 && order <= dgw::kMaxOrder) ? dgw::reference_element(order) : nullptr;
-  if (!ref) {
-    set_error("order must be in [1, 8]");
-    return DG_E_UNSUPPORTED;
-  }
-  if (K <= 0 || K >= (int64_t(1) << 26) || !elem_xyz || !elem_topo) {
-    set_error("K must be in [1, 2^26) and the mesh arrays non-null");
+  if (!workspace || !dgw::workspace_aligned(workspace)) {
+    set_error("the workspace must be a non-null device pointer aligned to 256 bytes");
     return DG_E_ARG;
   }
-  const int Np = ref->Np, Nfp = ref->Nfp;
 
   // ---- host geometry (float64) ----
   std::vector<float> geo(static_cast<size_t>(K) * 9);
@@ -271,127 +368,76 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
       conn[s] = static_cast<int32_t>((kn << 5) | (static_cast<int64_t>(fn) << 3) | o);
     }
 
-  // ---- MFMA fragment packing (FP32, and the BF16 / FP16 hi + lo splits) ----
-  std::vector<float> Dpack, Lpack;
-  std::vector<uint16_t> D16[2][2], L16[2][2];  // [bf16, f16][hi, lo]
-  {
-    const dgw::MfmaPacking p32 = dgw::mfma_packing(physics, order, dgw::kVariantMfma);
-    const dgw::ColMap c32 = dgw::face_block_columns(Nfp, p32.KF);
-    for (int j = 0; j < 3; ++j) dgw::pack_fp32(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p32.MB, p32.KP, Dpack);
-    dgw::pack_fp32(ref->lift.data(), Np, 4 * Nfp, p32.MB, p32.KL, Lpack, p32.KF > 0 ? &c32 : nullptr);
-    const int vars[2] = {dgw::kVariantMfmaBf16, dgw::kVariantMfmaF16};
-    for (int v = 0; v < 2; ++v) {
-      const dgw::MfmaPacking p16 = dgw::mfma_packing(physics, order, vars[v]);
-      const dgw::ColMap c16 = dgw::face_block_columns(Nfp, p16.KF);
-      const int kw = p16.KS / 4;  // k per lane group: 4 (16x16x16) or 8 (16x16x32)
-      for (int j = 0; j < 3; ++j)
-        dgw::pack_split16(ref->D.data() + static_cast<size_t>(j) * Np * Np, Np, Np, p16.MB, p16.KP, kw, v == 0,
-                          D16[v][0], D16[v][1]);
-      dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, kw, v == 0, L16[v][0], L16[v][1],
-                        p16.KF > 0 ? &c16 : nullptr);
-    }
-  }
-
-  // ---- operators in the kernels' layouts (float32) ----
-  std::vector<float> DT(3 * static_cast<size_t>(Np) * Np), LT(static_cast<size_t>(4) * Nfp * Np);
-  for (int j = 0; j < 3; ++j)
-    for (int n = 0; n < Np; ++n)
-      for (int mm = 0; mm < Np; ++mm)
-        DT[(static_cast<size_t>(j) * Np + mm) * Np + n] = static_cast<float>(ref->D[(static_cast<size_t>(j) * Np + n) * Np + mm]);
-  for (int n = 0; n < Np; ++n)
-    for (int fm = 0; fm < 4 * Nfp; ++fm)
-      LT[static_cast<size_t>(fm) * Np + n] = static_cast<float>(ref->lift[static_cast<size_t>(n) * 4 * Nfp + fm]);
-
+  // ---- operator tables and the layout in the caller's workspace ----
+  const HostTables t = make_tables(physics, ref);
   dg_solver* s = new dg_solver();
-  s->physics = physics;
-  s->N = order;
-  s->Np = Np;
-  s->Nfp = Nfp;
-  s->NF = dg_num_fields(physics);
-  s->NT = dgw::num_traces(physics);
-  s->CB = dgw::coef_block(physics);
-  s->ncoef = physics == DG_ACOUSTIC ? 2 : 3;
-  s->K = K;
+  set_sizes(s, physics, order, K, ref);
   s->stream = static_cast<hipStream_t>(stream);
   s->elem_xyz.assign(elem_xyz, elem_xyz + 12 * K);
+  s->conn_h = conn;
   (void)hipGetDevice(&s->device);
   if (const char* env = std::getenv("DGWAVE_XCD_REMAP")) s->xcd_remap = (std::atoi(env) != 0);
-
-  auto fail = [&](hipError_t err, const char* what) {
+  dgw::Arena arena(workspace, workspace_bytes);
+  layout(s, t, ref, arena);
+  if (!arena.fits()) {
     std::ostringstream os;
-    os << what << ": " << hipGetErrorString(err);
+    os << "workspace holds " << workspace_bytes << " bytes, the solver needs " << arena.used()
+       << " (dg_workspace_bytes)";
     set_error(os.str());
-    free_all(s);
     delete s;
-    return DG_E_HIP;
-  };
-  hipError_t err;
-  const size_t nq = field_count(s), nt = trace_count(s);
-  if ((err = dev_alloc(&s->q, nq)) != hipSuccess) return fail(err, "alloc q");
-  for (int i = 0; i < 3; ++i)
-    if ((err = dev_alloc(&s->r[i], nq)) != hipSuccess) return fail(err, "alloc r");
-  for (int i = 0; i < 2; ++i)
-    if ((err = dev_alloc(&s->qf[i], nt)) != hipSuccess) return fail(err, "alloc qf");
-  if ((err = dev_alloc(&s->qf_tmp, nt)) != hipSuccess) return fail(err, "alloc qf_tmp");
-  if ((err = dev_alloc(&s->geo, geo.size())) != hipSuccess) return fail(err, "alloc geo");
-  if ((err = dev_alloc(&s->cf, static_cast<size_t>(K) * s->CB)) != hipSuccess) return fail(err, "alloc cf");
-  if ((err = dev_alloc(&s->coef, static_cast<size_t>(K) * s->ncoef)) != hipSuccess) return fail(err, "alloc coef");
-  if ((err = dev_alloc(&s->DT, DT.size())) != hipSuccess) return fail(err, "alloc DT");
-  if ((err = dev_alloc(&s->LT, LT.size())) != hipSuccess) return fail(err, "alloc LT");
-  if ((err = dev_alloc(&s->conn, conn.size())) != hipSuccess) return fail(err, "alloc conn");
-  if ((err = dev_alloc(&s->fmask, ref->fmask.size())) != hipSuccess) return fail(err, "alloc fmask");
-  if ((err = dev_alloc(&s->perm, ref->perm.size())) != hipSuccess) return fail(err, "alloc perm");
-  if ((err = dev_alloc(&s->nodeface, ref->nodeface.size())) != hipSuccess) return fail(err, "alloc nodeface");
-  if ((err = dev_alloc(&s->J, J.size())) != hipSuccess) return fail(err, "alloc J");
-  if ((err = dev_alloc(&s->mass, ref->mass.size())) != hipSuccess) return fail(err, "alloc mass");
-  const int64_t eb = dgw::energy_blocks(physics, order, K);
-  if ((err = dev_alloc(&s->partial, static_cast<size_t>(eb))) != hipSuccess) return fail(err, "alloc partial");
-  if ((err = dev_alloc(&s->e_out, 1)) != hipSuccess) return fail(err, "alloc e_out");
-  if ((err = dev_alloc(&s->flag, 1)) != hipSuccess) return fail(err, "alloc flag");
-  if ((err = dev_alloc(&s->Dpack, Dpack.size())) != hipSuccess) return fail(err, "alloc Dpack");
-  if ((err = dev_alloc(&s->Lpack, Lpack.size())) != hipSuccess) return fail(err, "alloc Lpack");
-  for (int v = 0; v < 2; ++v)
-    for (int h = 0; h < 2; ++h) {
-      if ((err = dev_alloc(&s->D16[v][h], D16[v][h].size())) != hipSuccess) return fail(err, "alloc D16");
-      if ((err = dev_alloc(&s->L16[v][h], L16[v][h].size())) != hipSuccess) return fail(err, "alloc L16");
-      if ((err = hipMemcpy(s->D16[v][h], D16[v][h].data(), D16[v][h].size() * sizeof(uint16_t),
-                           hipMemcpyHostToDevice)) != hipSuccess)
-        return fail(err, "upload D16");
-      if ((err = hipMemcpy(s->L16[v][h], L16[v][h].data(), L16[v][h].size() * sizeof(uint16_t),
-                           hipMemcpyHostToDevice)) != hipSuccess)
-        return fail(err, "upload L16");
-    }
+    return DG_E_SHAPE;
+  }
 
+  // uploads on the solver's stream; the host arrays live until the sync below
   struct Up {
     void* dst;
     const void* src;
     size_t bytes;
   } ups[] = {
       {s->geo, geo.data(), geo.size() * sizeof(float)},
-      {s->DT, DT.data(), DT.size() * sizeof(float)},
-      {s->LT, LT.data(), LT.size() * sizeof(float)},
+      {s->DT, t.DT.data(), t.DT.size() * sizeof(float)},
+      {s->LT, t.LT.data(), t.LT.size() * sizeof(float)},
       {s->conn, conn.data(), conn.size() * sizeof(int32_t)},
       {s->fmask, ref->fmask.data(), ref->fmask.size() * sizeof(int32_t)},
       {s->perm, ref->perm.data(), ref->perm.size() * sizeof(int32_t)},
       {s->nodeface, ref->nodeface.data(), ref->nodeface.size() * sizeof(int32_t)},
       {s->J, J.data(), J.size() * sizeof(double)},
       {s->mass, ref->mass.data(), ref->mass.size() * sizeof(double)},
-      {s->Dpack, Dpack.data(), Dpack.size() * sizeof(float)},
-      {s->Lpack, Lpack.data(), Lpack.size() * sizeof(float)},
+      {s->Dpack, t.Dpack.data(), t.Dpack.size() * sizeof(float)},
+      {s->Lpack, t.Lpack.data(), t.Lpack.size() * sizeof(float)},
+      {s->D16[0][0], t.D16[0][0].data(), t.D16[0][0].size() * sizeof(uint16_t)},
+      {s->D16[0][1], t.D16[0][1].data(), t.D16[0][1].size() * sizeof(uint16_t)},
+      {s->D16[1][0], t.D16[1][0].data(), t.D16[1][0].size() * sizeof(uint16_t)},
+      {s->D16[1][1], t.D16[1][1].data(), t.D16[1][1].size() * sizeof(uint16_t)},
+      {s->L16[0][0], t.L16[0][0].data(), t.L16[0][0].size() * sizeof(uint16_t)},
+      {s->L16[0][1], t.L16[0][1].data(), t.L16[0][1].size() * sizeof(uint16_t)},
+      {s->L16[1][0], t.L16[1][0].data(), t.L16[1][0].size() * sizeof(uint16_t)},
+      {s->L16[1][1], t.L16[1][1].data(), t.L16[1][1].size() * sizeof(uint16_t)},
   };
+  hipError_t err = hipSuccess;
   for (const auto& u : ups)
-    if ((err = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice)) != hipSuccess)
-      return fail(err, "upload");
-  for (int i = 0; i < 3; ++i)
-    if ((err = hipMemset(s->r[i], 0, nq * sizeof(float))) != hipSuccess) return fail(err, "clear r");
+    if (err == hipSuccess && u.bytes > 0)
+      err = hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, s->stream);
+  // the AB3 ring starts at zero (a fill kernel, so that no memset node ever
+  // enters a captured graph)
+  const int64_t nq = s->K * s->NF * s->Np;
+  for (int i = 0; i < 3 && err == hipSuccess; ++i) err = dgw::launch_fill_zero_f32(nq, s->r[i], s->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(s->stream);
+  if (err != hipSuccess) {
+    std::ostringstream os;
+    os << "dg_create: upload: " << hipGetErrorString(err);
+    set_error(os.str());
+    delete s;
+    return DG_E_HIP;
+  }
   *out = s;
   return DG_OK;
 }
 
 void dg_destroy(dg_solver* s) {
   if (!s) return;
+  // the device arrays belong to the caller's workspace
   (void)hipStreamSynchronize(s->stream);
-  free_all(s);
   delete s;
 }
 
@@ -455,22 +501,54 @@ dg_status dg_set_coefficients(dg_solver* s, const float* coef) {
     set_error("null coefficients");
     return DG_E_ARG;
   }
-  const size_t n = static_cast<size_t>(s->K) * s->ncoef;
-  DG_HIP(hipMemcpyAsync(s->coef, coef, n * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
-  // validate on the host copy: set-up call, a synchronisation is acceptable
-  std::vector<float> h(n);
-  DG_HIP(hipMemcpyAsync(h.data(), s->coef, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+  const int64_t n = s->K * s->ncoef;
+  DG_HIP(hipMemcpyAsync(s->coef, coef, static_cast<size_t>(n) * sizeof(float), hipMemcpyDeviceToDevice,
+                        s->stream));
+  // validated on the device (set-up call: one synchronisation, one int back)
+  int bad = -1;
+  DG_HIP(dgw::launch_first_nonpositive(n, s->coef, s->flag, s->stream));
+  DG_HIP(hipMemcpyAsync(&bad, s->flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   DG_HIP(hipStreamSynchronize(s->stream));
-  for (size_t i = 0; i < n; ++i)
-    if (!(h[i] > 0.0f) || !std::isfinite(h[i])) {
-      std::ostringstream os;
-      os << "coefficient " << i % s->ncoef << " of element " << i / s->ncoef << " is not positive and finite";
-      set_error(os.str());
-      return DG_E_ARG;
-    }
+  if (bad >= 0) {
+    std::ostringstream os;
+    os << "coefficient " << bad % s->ncoef << " of element " << bad / s->ncoef << " is not positive and finite";
+    set_error(os.str());
+    s->have_coef = false;
+    return DG_E_ARG;
+  }
   DG_HIP(dgw::launch_coef_prep(s->physics, s->K, s->coef, s->conn, s->cf, s->stream));
   s->have_coef = true;
   s->coef_gen += 1;
+  return DG_OK;
+}
+
+dg_status dg_set_boundary(dg_solver* s, const int32_t* kind) {
+  if (dg_status st = check_solver(s)) return st;
+  if (!kind) {
+    set_error("null boundary kinds");
+    return DG_E_ARG;
+  }
+  std::vector<int32_t> conn = s->conn_h;
+  for (int64_t i = 0; i < 4 * s->K; ++i) {
+    const bool wall = (conn[i] & 7) == 7;
+    if (kind[i] != DG_BC_REFLECT && kind[i] != DG_BC_ABSORB) {
+      std::ostringstream os;
+      os << "unknown boundary kind " << kind[i] << " at face " << i % 4 << " of element " << i / 4;
+      set_error(os.str());
+      return DG_E_ARG;
+    }
+    if (!wall && kind[i] != DG_BC_REFLECT) {
+      std::ostringstream os;
+      os << "face " << i % 4 << " of element " << i / 4 << " has a neighbour: only unpaired faces absorb";
+      set_error(os.str());
+      return DG_E_ARG;
+    }
+    // a wall's word: own index, bit 3 set for an absorbing face
+    if (wall) conn[i] = static_cast<int32_t>(((i / 4) << 5) | (kind[i] == DG_BC_ABSORB ? 8 : 0) | 7);
+  }
+  DG_HIP(hipMemcpyAsync(s->conn, conn.data(), conn.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+  DG_HIP(hipStreamSynchronize(s->stream));
+  s->conn_h.swap(conn);
   return DG_OK;
 }
 
@@ -506,6 +584,10 @@ dg_status dg_get_fields(dg_solver* s, float* q) {
 
 dg_status dg_set_state(dg_solver* s, const float* q, const float* r1, const float* r2, int64_t step_index) {
   if (dg_status st = check_solver(s)) return st;
+  if (s->k_fast > 0) {
+    set_error("the AB3 state of a two-rate solver is per class: dg_set_state is single-rate only");
+    return DG_E_UNSUPPORTED;
+  }
   if (!q || step_index < 0 || (step_index >= 1 && !r1) || (step_index >= 2 && !r2)) {
     set_error("dg_set_state: bad arguments");
     return DG_E_ARG;
@@ -527,6 +609,10 @@ dg_status dg_set_state(dg_solver* s, const float* q, const float* r1, const floa
 
 dg_status dg_get_state(dg_solver* s, float* q, float* r1, float* r2, int64_t* step_index) {
   if (dg_status st = check_solver(s)) return st;
+  if (s->k_fast > 0) {
+    set_error("the AB3 state of a two-rate solver is per class: dg_get_state is single-rate only");
+    return DG_E_UNSUPPORTED;
+  }
   if (!s->have_fields) {
     set_error("fields not set");
     return DG_E_STATE;
@@ -561,9 +647,103 @@ dg_status dg_step(dg_solver* s, int nsteps, double dt) {
     set_error("set coefficients and fields before stepping");
     return DG_E_STATE;
   }
+  if (s->k_fast > 0) {
+    set_error("this solver has a fast class: step it with dg_step_multirate");
+    return DG_E_STATE;
+  }
   for (int i = 0; i < nsteps; ++i) {
     const dgw::StepArgs a = dgw::step_args(s, s->m, s->cur, dt);
     DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, s->stream));
+    s->cur ^= 1;
+    s->m += 1;
+  }
+  return DG_OK;
+}
+
+dg_status dg_set_rate_classes(dg_solver* s, int64_t k_fast) {
+  if (dg_status st = check_solver(s)) return st;
+  if (k_fast < 0 || k_fast > s->K) {
+    set_error("k_fast must lie in [0, K]");
+    return DG_E_ARG;
+  }
+  // slow elements that read a fast neighbour's traces
+  std::vector<int32_t> iface;
+  for (int64_t k = k_fast; k < s->K; ++k)
+    for (int f = 0; f < 4; ++f) {
+      const int32_t w = s->conn_h[4 * k + f];
+      if ((w & 7) != 7 && static_cast<int64_t>(w >> 5) < k_fast) {
+        iface.push_back(static_cast<int32_t>(k));
+        break;
+      }
+    }
+  if (!iface.empty()) {
+    DG_HIP(hipMemcpyAsync(s->iface, iface.data(), iface.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          s->stream));
+    DG_HIP(hipStreamSynchronize(s->stream));
+  }
+  s->k_fast = k_fast;
+  s->n_iface = static_cast<int64_t>(iface.size());
+  s->m = 0;  // both classes restart with the Euler / two-step start-up
+  s->e_prev = -1.0;
+  s->e_prev_m = -1;
+  return DG_OK;
+}
+
+dg_status dg_step_multirate(dg_solver* s, int nsteps, double dt) {
+  if (dg_status st = check_solver(s)) return st;
+  if (nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) {
+    set_error("nsteps must be >= 0 and dt > 0");
+    return DG_E_ARG;
+  }
+  if (!s->have_coef || !s->have_fields) {
+    set_error("set coefficients and fields before stepping");
+    return DG_E_STATE;
+  }
+  const double h = 0.5 * dt;
+  const int64_t K = s->K, KF = s->k_fast;
+  for (int i = 0; i < nsteps; ++i) {
+    const int64_t ms = s->m, mf = 2 * s->m;  // coarse and fine steps taken so far
+    float* A = s->qf[s->cur];                // every trace at t_n
+    float* B = s->qf_tmp;                    // traces at t_n + h (fast; slow next to fast)
+    float* C = s->qf[s->cur ^ 1];            // every trace at t_n + dt
+    // 1. fast elements: first half step, traces at t_n + h into B
+    if (KF > 0) {
+      dgw::StepArgs a = dgw::step_args(s, mf, s->cur, h);
+      a.K = KF;
+      a.qf_in = A;
+      a.qf_out = B;
+      DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, s->stream));
+    }
+    // 2. slow elements: full step, traces at t_n + dt into C
+    if (KF < K) {
+      dgw::StepArgs a = dgw::step_args(s, ms, s->cur, dt);
+      a.e_begin = KF;
+      a.qf_in = A;
+      a.qf_out = C;
+      DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, s->stream));
+      // 3. slow elements next to fast ones: traces of their state at t_n + h,
+      // q(t_n + h) = q(t_n + dt) + dt sum_i (w_half - w_full)_i r^{n-i} with
+      // w the integrals of the history polynomial over half and full steps
+      if (KF > 0 && s->n_iface > 0) {
+        static const double d[3][3] = {{-0.5, 0.0, 0.0},
+                                       {5.0 / 8.0 - 1.5, -1.0 / 8.0 + 0.5, 0.0},
+                                       {17.0 / 24.0 - 23.0 / 12.0, -7.0 / 24.0 + 16.0 / 12.0,
+                                        1.0 / 12.0 - 5.0 / 12.0}};
+        const int st = ms < 2 ? static_cast<int>(ms) : 2;
+        DG_HIP(dgw::launch_trace_comb(s->physics, s->N, s->n_iface, s->iface, s->q, s->r[ms % 3],
+                                      s->r[(ms + 2) % 3], s->r[(ms + 1) % 3], static_cast<float>(dt * d[st][0]),
+                                      static_cast<float>(dt * d[st][1]), static_cast<float>(dt * d[st][2]),
+                                      s->geo, s->fmask, B, s->stream));
+      }
+    }
+    // 4. fast elements: second half step from B, traces at t_n + dt into C
+    if (KF > 0) {
+      dgw::StepArgs a = dgw::step_args(s, mf + 1, s->cur, h);
+      a.K = KF;
+      a.qf_in = B;
+      a.qf_out = C;
+      DG_HIP(dgw::launch_step(s->physics, s->N, s->variant, a, s->stream));
+    }
     s->cur ^= 1;
     s->m += 1;
   }

@@ -13,29 +13,21 @@
 #include "dgwave.h"
 #include "kernels.hpp"
 #include "solver_state.hpp"
+#include "workspace.hpp"
 
 using dgw::set_error;
 
 namespace {
 
 size_t field_floats(const dg_solver* s) { return static_cast<size_t>(s->K) * s->NF * s->Np; }
-size_t trace_floats(const dg_solver* s) { return static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp; }
-
-// Device copies of the solver state, released on scope exit.
-struct SavedState {
-  float* buf = nullptr;
-  ~SavedState() {
-    if (buf) (void)hipFree(buf);
-  }
-};
 
 }  // namespace
 
 struct dg_batch_group {
   int N = 0, variant = 0;
   std::vector<int> members;           // indices into dg_batch::members
-  dgw::StepArgs* args = nullptr;      // device [members][kBatchPhases]
-  int2* work = nullptr;               // device [nwork] (member slot, tile)
+  dgw::StepArgs* args = nullptr;      // device [members][kBatchPhases], in the workspace
+  int2* work = nullptr;               // device [nwork] (member slot, tile), in the workspace
   int64_t tiles = 0;                  // real work items
   int64_t nwork = 0;                  // launched workgroups (padded to 8)
 };
@@ -44,6 +36,8 @@ struct dg_batch {
   std::vector<dg_solver*> members;
   int physics = 0;
   hipStream_t stream = nullptr;
+  void* ws = nullptr;                 // caller-owned device workspace
+  size_t ws_bytes = 0;
   std::vector<dg_batch_group> groups;
   std::vector<int> group_variant;     // member variants the groups were built for
   // argument tables: valid for member i at step m0[i] + p with trace buffer
@@ -56,16 +50,39 @@ struct dg_batch {
   bool use_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // one side stream per launch group (default priority): the groups' members
+  // are independent meshes, so their launches run concurrently, forked from
+  // and joined back to the batch's stream
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
 
-void free_groups(dg_batch* b) {
-  for (dg_batch_group& g : b->groups) {
-    if (g.args) (void)hipFree(g.args);
-    if (g.work) (void)hipFree(g.work);
+void free_groups(dg_batch* b) { b->groups.clear(); }
+
+// Most work items a member can contribute: its tile count under the variant
+// with the most tiles (the groups are rebuilt when a variant changes).
+int64_t max_member_tiles(int physics, const dg_solver* s) {
+  int64_t most = 0;
+  for (int v = 0; v < dgw::kNumVariants; ++v)
+    if (dgw::variant_supported(physics, s->N, v)) most = std::max(most, dgw::tiles_for(physics, s->N, v, s->K));
+  return most;
+}
+
+// Workspace bytes that cover every grouping of the members: at most one group
+// per member, each group's work list padded to a multiple of 8 workgroups,
+// plus the alignment of every array.
+size_t batch_bytes(int physics, dg_solver* const* members, int count) {
+  size_t bytes = 0;
+  for (int i = 0; i < count; ++i) {
+    const int64_t t = max_member_tiles(physics, members[i]);
+    bytes += dgw::align_up(dgw::kBatchPhases * sizeof(dgw::StepArgs));
+    bytes += dgw::align_up(static_cast<size_t>((t + 7) / 8 * 8) * sizeof(int2));
+    bytes += 2 * dgw::kWorkspaceAlign;
   }
-  b->groups.clear();
+  return bytes;
 }
 
 void drop_graph(dg_batch* b) {
@@ -103,6 +120,7 @@ dg_status build_groups(dg_batch* b) {
     if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
   }
   std::sort(keys.begin(), keys.end());
+  dgw::Arena arena(b->ws, b->ws_bytes);
   for (const auto& key : keys) {
     dg_batch_group g;
     g.N = key.first;
@@ -135,11 +153,19 @@ dg_status build_groups(dg_batch* b) {
     }
     b->groups.push_back(g);
     dg_batch_group& gg = b->groups.back();
-    DG_HIP(hipMalloc(reinterpret_cast<void**>(&gg.work), std::max<size_t>(work.size(), 1) * sizeof(int2)));
-    DG_HIP(hipMalloc(reinterpret_cast<void**>(&gg.args),
-                     gg.members.size() * dgw::kBatchPhases * sizeof(dgw::StepArgs)));
-    if (!work.empty())
-      DG_HIP(hipMemcpy(gg.work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
+    gg.args = arena.take<dgw::StepArgs>(gg.members.size() * dgw::kBatchPhases);
+    gg.work = arena.take<int2>(work.size());
+    if (!arena.fits()) {
+      std::ostringstream os;
+      os << "batch workspace of " << b->ws_bytes << " bytes is too small (dg_batch_workspace_bytes)";
+      set_error(os.str());
+      free_groups(b);
+      return DG_E_SHAPE;
+    }
+    if (!work.empty()) {
+      DG_HIP(hipMemcpyAsync(gg.work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+      DG_HIP(hipStreamSynchronize(b->stream));
+    }
   }
   return DG_OK;
 }
@@ -182,10 +208,49 @@ bool tables_match(const dg_batch* b, const double* dt) {
   return true;
 }
 
-dg_status launch_groups(dg_batch* b, int phase) {
-  for (const dg_batch_group& g : b->groups)
-    DG_HIP(dgw::launch_step_batch(b->physics, g.N, g.variant, g.args, g.work, g.nwork, phase, b->stream));
+dg_status ensure_side_streams(dg_batch* b) {
+  if (!b->fork) DG_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  while (b->side.size() < b->groups.size()) {
+    hipStream_t st = nullptr;
+    DG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b->side.push_back(st);
+    hipEvent_t ev = nullptr;
+    DG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->join.push_back(ev);
+  }
   return DG_OK;
+}
+
+// Phases [ph0, ph1) of every group.  One group launches on the batch's stream;
+// several fork onto their own streams (each group's phases in order) and
+// join back, so that one group's launch tail overlaps another's work.
+dg_status launch_groups(dg_batch* b, int ph0, int ph1) {
+  if (b->groups.size() == 1) {
+    const dg_batch_group& g = b->groups[0];
+    for (int ph = ph0; ph < ph1; ++ph)
+      DG_HIP(dgw::launch_step_batch(b->physics, g.N, g.variant, g.args, g.work, g.nwork, ph, b->stream));
+    return DG_OK;
+  }
+  if (dg_status st = ensure_side_streams(b)) return st;
+  DG_HIP(hipEventRecord(b->fork, b->stream));
+  for (size_t i = 0; i < b->groups.size(); ++i) {
+    const dg_batch_group& g = b->groups[i];
+    DG_HIP(hipStreamWaitEvent(b->side[i], b->fork, 0));
+    for (int ph = ph0; ph < ph1; ++ph)
+      DG_HIP(dgw::launch_step_batch(b->physics, g.N, g.variant, g.args, g.work, g.nwork, ph, b->side[i]));
+    DG_HIP(hipEventRecord(b->join[i], b->side[i]));
+    DG_HIP(hipStreamWaitEvent(b->stream, b->join[i], 0));
+  }
+  return DG_OK;
+}
+
+void release_streams(dg_batch* b) {
+  for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  b->side.clear();
+  b->join.clear();
+  b->fork = nullptr;
 }
 
 void advance_members(dg_batch* b, int steps) {
@@ -200,7 +265,8 @@ void advance_members(dg_batch* b, int steps) {
 
 extern "C" {
 
-dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, double* us_per_step) {
+dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, void* scratch,
+                      size_t scratch_bytes, double* us_per_step) {
   if (!s) {
     set_error("null solver");
     return DG_E_ARG;
@@ -213,22 +279,33 @@ dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, d
     set_error("set coefficients and fields before tuning");
     return DG_E_STATE;
   }
-  const size_t nq = field_floats(s), nt = trace_floats(s);
-  SavedState saved;
-  DG_HIP(hipMalloc(reinterpret_cast<void**>(&saved.buf), (4 * nq + nt) * sizeof(float)));
-  const size_t fb = nq * sizeof(float);
-  DG_HIP(hipMemcpyAsync(saved.buf, s->q, fb, hipMemcpyDeviceToDevice, s->stream));
-  for (int i = 0; i < 3; ++i)
-    DG_HIP(hipMemcpyAsync(saved.buf + (1 + i) * nq, s->r[i], fb, hipMemcpyDeviceToDevice, s->stream));
-  DG_HIP(hipMemcpyAsync(saved.buf + 4 * nq, s->qf[s->cur], nt * sizeof(float), hipMemcpyDeviceToDevice,
-                        s->stream));
-  const int64_t m_saved = s->m;
-  const int cur_saved = s->cur;
+  const size_t need = field_floats(s) * sizeof(float);
+  if (!scratch || scratch_bytes < need) {
+    std::ostringstream os;
+    os << "dg_autotune: scratch must hold one field array (" << need << " bytes)";
+    set_error(os.str());
+    return DG_E_ARG;
+  }
+  // Every timed step reads the current state and writes only memory that
+  // holds nothing the state needs: the updated fields go to the caller's
+  // scratch, r^m to the ring slot of r^{m-3} and the traces to the buffer the
+  // next step would overwrite.  The state is untouched, so there is nothing
+  // to restore.  Every step uses the AB3 weights (the start-up steps read
+  // less history and would time short).
+  dgw::StepArgs a = dgw::step_args(s, s->m, s->cur, dt);
+  a.q_out = static_cast<float*>(scratch);
+  a.c0 = static_cast<float>(dt * 23.0 / 12.0);
+  a.c1 = static_cast<float>(dt * -16.0 / 12.0);
+  a.c2 = static_cast<float>(dt * 5.0 / 12.0);
   const int variant_saved = s->variant;
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   DG_HIP(hipEventCreate(&e0));
-  DG_HIP(hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("dg_autotune: hipEventCreate failed");
+    return DG_E_HIP;
+  }
   double best = -1.0;
   int best_variant = variant_saved;
   dg_status st = DG_OK;
@@ -237,15 +314,16 @@ dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, d
     const bool wanted = candidates == 0u || ((candidates >> v) & 1u);
     if (wanted && dgw::variant_supported(s->physics, s->N, v)) {
       s->variant = v;
+      const dgw::StepArgs base = dgw::base_args(s);  // the variant's operator tables
+      dgw::StepArgs av = a;
+      av.D16h = base.D16h;
+      av.D16l = base.D16l;
+      av.L16h = base.L16h;
+      av.L16l = base.L16l;
       hipError_t err = hipSuccess;
       for (int i = 0; i <= steps && err == hipSuccess; ++i) {
         if (i == 1) err = hipEventRecord(e0, s->stream);
-        if (err == hipSuccess) {
-          const dgw::StepArgs a = dgw::step_args(s, s->m, s->cur, dt);
-          err = dgw::launch_step(s->physics, s->N, v, a, s->stream);
-          s->cur ^= 1;
-          s->m += 1;
-        }
+        if (err == hipSuccess) err = dgw::launch_step(s->physics, s->N, v, av, s->stream);
       }
       if (err == hipSuccess) err = hipEventRecord(e1, s->stream);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -260,20 +338,6 @@ dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, d
         best = us;
         best_variant = v;
       }
-      // restore the state before the next candidate (and at the end)
-      s->m = m_saved;
-      s->cur = cur_saved;
-      hipError_t rerr = hipMemcpyAsync(s->q, saved.buf, fb, hipMemcpyDeviceToDevice, s->stream);
-      for (int i = 0; i < 3 && rerr == hipSuccess; ++i)
-        rerr = hipMemcpyAsync(s->r[i], saved.buf + (1 + i) * nq, fb, hipMemcpyDeviceToDevice, s->stream);
-      if (rerr == hipSuccess)
-        rerr = hipMemcpyAsync(s->qf[s->cur], saved.buf + 4 * nq, nt * sizeof(float), hipMemcpyDeviceToDevice,
-                              s->stream);
-      if (rerr == hipSuccess) rerr = hipStreamSynchronize(s->stream);
-      if (rerr != hipSuccess && st == DG_OK) {
-        set_error(std::string("autotune restore: ") + hipGetErrorString(rerr));
-        st = DG_E_HIP;
-      }
     }
     if (us_per_step) us_per_step[v] = us;
   }
@@ -283,9 +347,28 @@ dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, d
   return st;
 }
 
-dg_status dg_batch_create(dg_solver* const* members, int count, void* stream, dg_batch** out) {
+dg_status dg_batch_workspace_bytes(dg_solver* const* members, int count, size_t* bytes) {
+  if (!members || !bytes || count < 1) {
+    set_error("dg_batch_workspace_bytes: need members, a count >= 1 and an output");
+    return DG_E_ARG;
+  }
+  for (int i = 0; i < count; ++i)
+    if (!members[i]) {
+      set_error("dg_batch_workspace_bytes: null member");
+      return DG_E_ARG;
+    }
+  *bytes = batch_bytes(members[0]->physics, members, count);
+  return DG_OK;
+}
+
+dg_status dg_batch_create(dg_solver* const* members, int count, void* workspace, size_t workspace_bytes,
+                          void* stream, dg_batch** out) {
   if (!members || !out || count < 1) {
     set_error("dg_batch_create: need an output pointer and at least one member");
+    return DG_E_ARG;
+  }
+  if (!workspace || !dgw::workspace_aligned(workspace)) {
+    set_error("dg_batch_create: the workspace must be a non-null device pointer aligned to 256 bytes");
     return DG_E_ARG;
   }
   *out = nullptr;
@@ -304,10 +387,19 @@ dg_status dg_batch_create(dg_solver* const* members, int count, void* stream, dg
         return DG_E_ARG;
       }
   }
+  const size_t need = batch_bytes(members[0]->physics, members, count);
+  if (workspace_bytes < need) {
+    std::ostringstream os;
+    os << "dg_batch_create: workspace holds " << workspace_bytes << " bytes, the batch needs " << need;
+    set_error(os.str());
+    return DG_E_SHAPE;
+  }
   dg_batch* b = new dg_batch;
   b->members.assign(members, members + count);
   b->physics = members[0]->physics;
   b->stream = static_cast<hipStream_t>(stream);
+  b->ws = workspace;
+  b->ws_bytes = workspace_bytes;
   if (dg_status st = build_groups(b)) {
     free_groups(b);
     delete b;
@@ -322,6 +414,7 @@ void dg_batch_destroy(dg_batch* b) {
   (void)hipStreamSynchronize(b->stream);
   drop_graph(b);
   free_groups(b);
+  release_streams(b);
   delete b;
 }
 
@@ -355,6 +448,10 @@ dg_status dg_batch_step(dg_batch* b, int nsteps, const double* dt) {
       set_error("dg_batch_step: a member has no coefficients or fields");
       return DG_E_STATE;
     }
+    if (s->k_fast > 0) {
+      set_error("dg_batch_step: a member has a fast class (two-rate members step with dg_step_multirate)");
+      return DG_E_STATE;
+    }
   }
   for (size_t i = 0; i < n; ++i)
     if (b->members[i]->variant != b->group_variant[i]) {
@@ -385,7 +482,7 @@ dg_status dg_batch_step(dg_batch* b, int nsteps, const double* dt) {
       if (!b->exec) {
         DG_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         dg_status st = DG_OK;
-        for (int ph = 0; ph < dgw::kBatchPhases && st == DG_OK; ++ph) st = launch_groups(b, ph);
+        st = launch_groups(b, 0, dgw::kBatchPhases);
         hipGraph_t graph = nullptr;
         const hipError_t cerr = hipStreamEndCapture(b->stream, &graph);
         if (st != DG_OK) {
@@ -401,7 +498,7 @@ dg_status dg_batch_step(dg_batch* b, int nsteps, const double* dt) {
       done += dgw::kBatchPhases;
       continue;
     }
-    if (dg_status st = launch_groups(b, phase)) return st;
+    if (dg_status st = launch_groups(b, phase, phase + 1)) return st;
     advance_members(b, 1);
     ++done;
   }

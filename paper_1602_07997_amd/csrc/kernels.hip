@@ -87,7 +87,7 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
   constexpr int NDT = 3 * NP * NP, NLT = NFN * NP;
   __shared__ float s_ops[OPS_LDS ? NDT + NLT : 1];
 
-  const int64_t e0 = tile * KT;
+  const int64_t e0 = a.e_begin + tile * KT;
   if (e0 >= a.K) return;  // whole workgroup exits together
   const int ne = static_cast<int>((a.K - e0) < KT ? (a.K - e0) : KT);
   const int tid = threadIdx.x;
@@ -286,13 +286,16 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
     const int vn = vnode[t];
     const float* qe = s_q + e * NF * NP;
     const bool wall = (word[t] & 7) == 7;
+    // reflecting wall: mirror ghost state (gw = 1); absorbing wall (bit 3 of
+    // a wall's word): zero exterior state (gw = 0)
+    const float gw = (word[t] & 8) ? 0.0f : 1.0f;
     float* lf = s_lift + e * NL * NFN + fn;
     if constexpr (PHYS == 0) {
       const float pM = qe[vn];
       const float vnM = nrm[0] * qe[NP + vn] + nrm[1] * qe[2 * NP + vn] + nrm[2] * qe[3 * NP + vn];
       // rigid wall: mirror state p+ = p-, v.n+ = -v.n-
-      const float pP = wall ? pM : nbt[t][0];
-      const float vnP = wall ? -vnM : -nbt[t][1];  // neighbour stored v.n with its own normal
+      const float pP = wall ? gw * pM : nbt[t][0];
+      const float vnP = wall ? -gw * vnM : -nbt[t][1];  // neighbour stored v.n with its own normal
       const float alpha = 0.5f * (pP - pM) - rec[3] * 0.5f * (vnP - vnM);
       lf[0] = rec[4] * alpha;    // lifted into r^p
       lf[NFN] = rec[5] * alpha;  // lifted, then times n, into r^v
@@ -307,8 +310,8 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
       // traction-free wall: mirror state v+ = v-, (s n)+ = -(s n)-
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
-        vP[ii] = wall ? vM[ii] : nbt[t][ii];
-        tP[ii] = wall ? -tM[ii] : -nbt[t][3 + ii];  // neighbour stored s n with its own normal
+        vP[ii] = wall ? gw * vM[ii] : nbt[t][ii];
+        tP[ii] = wall ? -gw * tM[ii] : -nbt[t][3 + ii];  // neighbour stored s n with its own normal
       }
       const float ZpP = rec[3], ZsP = rec[4], fs = rec[5];
       float jv[3], jt[3];
@@ -529,6 +532,52 @@ dg_trace_kernel(int64_t K, const float* __restrict__ q, const float* __restrict_
   }
 }
 
+// Traces of q + c0 r0 + c1 r1 + c2 r2 for the elements of a list (the slow
+// elements next to fast ones in two-rate stepping: their state at the fast
+// class's half step, from their own Adams-Bashforth history).  A term whose
+// coefficient is zero is not read.
+template <int N, int PHYS>
+__global__ void __launch_bounds__(kThreads)
+dg_trace_comb_kernel(int64_t nlist, const int32_t* __restrict__ list, const float* __restrict__ q,
+                     const float* __restrict__ r0, const float* __restrict__ r1, const float* __restrict__ r2,
+                     float c0, float c1, float c2, const float* __restrict__ geo,
+                     const int32_t* __restrict__ fmask, float* __restrict__ qf) {
+  constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP, NFN = 4 * NFP;
+  constexpr int NF = Phys<PHYS>::NF, NT = Phys<PHYS>::NT;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= nlist * NFN) return;
+  const int64_t item = i / NFN;
+  const int fn = static_cast<int>(i - item * NFN);
+  const int64_t k = list[item];
+  const int f = fn / NFP, j = fn - f * NFP;
+  float G[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) G[t] = geo[k * 9 + t];
+  float nrm[3], fs;
+  face_normal(G, f, nrm, fs);
+  const int vn = fmask[f * NFP + j];
+  const int64_t base = k * NF * NP + vn;
+  auto val = [&](int c) {
+    const int64_t at = base + static_cast<int64_t>(c) * NP;
+    float v = q[at] + c0 * r0[at];
+    if (c1 != 0.0f) v += c1 * r1[at];
+    if (c2 != 0.0f) v += c2 * r2[at];
+    return v;
+  };
+  float* tr = qf + (k * 4 + f) * NT * NFP;
+  if constexpr (PHYS == 0) {
+    tr[j] = val(0);
+    tr[NFP + j] = nrm[0] * val(1) + nrm[1] * val(2) + nrm[2] * val(3);
+  } else {
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) tr[ii * NFP + j] = val(ii);
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+      tr[(3 + ii) * NFP + j] = val(3 + voigt(ii, 0)) * nrm[0] + val(3 + voigt(ii, 1)) * nrm[1] +
+                               val(3 + voigt(ii, 2)) * nrm[2];
+  }
+}
+
 // Derived coefficients per element, including the neighbours' impedances on
 // each face (own values on walls).
 //   acoustic cf = [rho c^2, 1/rho, Z, c, Z+_0..3]
@@ -571,6 +620,27 @@ dg_coef_kernel(int64_t K, const float* __restrict__ coef, const int32_t* __restr
       o[12 + f] = rn * sqrtf(mn / rn);
     }
   }
+}
+
+// Coefficient validation on the device: the smallest index of a value that
+// is not positive and finite (int32: at most 3 * 2^26 coefficients).
+constexpr int kNoIndex = 0x7fffffff;
+
+__global__ void dg_flag_set_kernel(int* flag, int value) {
+  if (threadIdx.x == 0) flag[0] = value;
+}
+
+__global__ void __launch_bounds__(kThreads)
+dg_first_nonpositive_kernel(int64_t n, const float* __restrict__ x, int* flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) {
+    const float v = x[i];
+    if (!(v > 0.0f) || !(v <= 3.402823466e38f)) atomicMin(flag, static_cast<int>(i));
+  }
+}
+
+__global__ void dg_flag_none_kernel(int* flag) {
+  if (threadIdx.x == 0 && flag[0] == kNoIndex) flag[0] = -1;
 }
 
 // FP64 discrete energy, partial sums per workgroup.  A workgroup takes a tile
@@ -692,7 +762,7 @@ dg_sum_kernel(int64_t n, const double* __restrict__ partial, double* __restrict_
 template <int N, int PHYS>
 hipError_t step_impl(const StepArgs& a, hipStream_t s) {
   constexpr int KT = Tile<N, PHYS>::KT;
-  int64_t tiles = (a.K + KT - 1) / KT;
+  int64_t tiles = (a.K - a.e_begin + KT - 1) / KT;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((dg_step_kernel<N, PHYS>), dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, s,
@@ -716,6 +786,18 @@ hipError_t trace_impl(int64_t K, const float* q, const float* geo, const int32_t
   const int64_t blocks = (items + kThreads - 1) / kThreads;
   hipLaunchKernelGGL((dg_trace_kernel<N, PHYS>), dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
                      s, K, q, geo, fmask, qf);
+  return hipGetLastError();
+}
+
+template <int N, int PHYS>
+hipError_t trace_comb_impl(int64_t nlist, const int32_t* list, const float* q, const float* r0, const float* r1,
+                           const float* r2, float c0, float c1, float c2, const float* geo, const int32_t* fmask,
+                           float* qf, hipStream_t s) {
+  if (nlist <= 0) return hipSuccess;
+  const int64_t blocks = (nlist * 4 * Deg<N>::NFP + kThreads - 1) / kThreads;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_trace_comb_kernel<N, PHYS>), dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s,
+                     nlist, list, q, r0, r1, r2, c0, c1, c2, geo, fmask, qf);
   return hipGetLastError();
 }
 
@@ -759,6 +841,7 @@ static bool is_mfma(int variant) { return mfma_precision(variant) >= 0; }
 bool variant_supported(int physics, int N, int variant) {
   if (N < 1 || N > 8 || (physics != 0 && physics != 1)) return false;
   if (variant == kVariantValu) return true;
+  if (variant == kVariantMfmaWide) return physics == 0;  // acoustic tile shapes only
   if (is_mfma(variant)) return true;
   if (variant == kVariantElem) return elem_supported(physics, N);
   return false;
@@ -876,6 +959,16 @@ hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const fl
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_first_nonpositive(int64_t n, const float* x, int* flag, hipStream_t s) {
+  if (n < 0 || n > kNoIndex) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dg_flag_set_kernel, dim3(1), dim3(64), 0, s, flag, kNoIndex);
+  if (n > 0)
+    hipLaunchKernelGGL(dg_first_nonpositive_kernel, dim3(static_cast<unsigned>((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, n, x, flag);
+  hipLaunchKernelGGL(dg_flag_none_kernel, dim3(1), dim3(64), 0, s, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int32_t* conn, float* cf,
                             hipStream_t s) {
   const int64_t blocks = (K + kThreads - 1) / kThreads;
@@ -914,6 +1007,37 @@ hipError_t static_energy_partials(int device, double** ptr) {
   }
   *ptr = g_scratch_ptr[device];
   return hipSuccess;
+}
+
+hipError_t launch_trace_comb(int physics, int N, int64_t nlist, const int32_t* list, const float* q,
+                             const float* r0, const float* r1, const float* r2, float c0, float c1, float c2,
+                             const float* geo, const int32_t* fmask, float* qf, hipStream_t s) {
+#define CALL(n, p) trace_comb_impl<n, p>(nlist, list, q, r0, r1, r2, c0, c1, c2, geo, fmask, qf, s)
+  if (physics == 0) {
+    switch (N) {
+      case 1: return CALL(1, 0);
+      case 2: return CALL(2, 0);
+      case 3: return CALL(3, 0);
+      case 4: return CALL(4, 0);
+      case 5: return CALL(5, 0);
+      case 6: return CALL(6, 0);
+      case 7: return CALL(7, 0);
+      case 8: return CALL(8, 0);
+    }
+  } else {
+    switch (N) {
+      case 1: return CALL(1, 1);
+      case 2: return CALL(2, 1);
+      case 3: return CALL(3, 1);
+      case 4: return CALL(4, 1);
+      case 5: return CALL(5, 1);
+      case 6: return CALL(6, 1);
+      case 7: return CALL(7, 1);
+      case 8: return CALL(8, 1);
+    }
+  }
+#undef CALL
+  return hipErrorInvalidValue;
 }
 
 int64_t energy_blocks(int physics, int N, int64_t K) {

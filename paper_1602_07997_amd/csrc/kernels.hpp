@@ -9,7 +9,8 @@ namespace dgw {
 
 // Per-step kernel arguments.  All pointers are device pointers.
 struct StepArgs {
-  int64_t K;
+  int64_t K;             // end (exclusive) of the element range of the launch
+  int64_t e_begin;       // first element of the range (0: the whole mesh)
   const float* q_in;     // fields read this step [K][NF][NP]
   float* q_out;          // fields written (step mode; may equal q_in)
   const float* r1;       // r^{m-1} (read when c1 != 0)
@@ -50,7 +51,8 @@ constexpr int kVariantMfma = 1;      // element tiles, FP32 MFMA contractions
 constexpr int kVariantMfmaBf16 = 2;  // BF16 MFMA, three split products, FP32 accumulation
 constexpr int kVariantMfmaF16 = 3;   // FP16 MFMA, three split products, FP32 accumulation
 constexpr int kVariantElem = 4;      // element per thread (acoustic N = 1, 2; elastic N = 1)
-constexpr int kNumVariants = 5;
+constexpr int kVariantMfmaWide = 5;  // FP32 MFMA, the alternative acoustic tile shape
+constexpr int kNumVariants = 6;
 bool variant_supported(int physics, int N, int variant);
 
 // Fragment packing of the MFMA variants: node blocks MB, padded volume K (KP)
@@ -135,10 +137,17 @@ hipError_t launch_grad_accum(int physics, int N, const GradArgs& a, hipStream_t 
 hipError_t launch_grad_finalize(int physics, int64_t K, const double* gacc, const int32_t* conn, const float* coef,
                                 float* grad, hipStream_t s);
 hipError_t launch_fill_zero_f64(int64_t n, double* p, hipStream_t s);
+// flag[0] = smallest i < n with x[i] not positive and finite, or -1.
+hipError_t launch_first_nonpositive(int64_t n, const float* x, int* flag, hipStream_t s);
 hipError_t launch_fill_zero_f32(int64_t n, float* p, hipStream_t s);
 
 hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const float* geo,
                          const int32_t* fmask, float* qf, hipStream_t s);
+// Traces of q + c0 r0 + c1 r1 + c2 r2 for the elements list[0 .. nlist)
+// (terms with a zero coefficient are not read).
+hipError_t launch_trace_comb(int physics, int N, int64_t nlist, const int32_t* list, const float* q,
+                             const float* r0, const float* r1, const float* r2, float c0, float c1, float c2,
+                             const float* geo, const int32_t* fmask, float* qf, hipStream_t s);
 hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int32_t* conn,
                             float* cf, hipStream_t s);
 // Energy: partial sums per block into `partial` (size energy_blocks), then

@@ -205,11 +205,12 @@ dg_grad_accum_kernel(const GradArgs a) {
     if (i >= 4 * NFP) continue;
     const int f = i / NFP, j = i - f * NFP;
     const bool wall = (word[t] & 7) == 7;
+    const float gw = (word[t] & 8) ? 0.0f : 1.0f;  // absorbing wall: zero exterior state
     float* sj = s_jump + f * NJ * NFP;
     if constexpr (PHYS == 0) {
       const float pM = own[t][0], vnM = own[t][1];
-      const float pP = wall ? pM : nbv[t][0];
-      const float vnP = wall ? -vnM : -nbv[t][1];
+      const float pP = wall ? gw * pM : nbv[t][0];
+      const float vnP = wall ? -gw * vnM : -nbv[t][1];
       const float jp = 0.5f * (pP - pM), jv = 0.5f * (vnP - vnM);
       sj[j] = jp - cf[4 + f] * jv;  // alpha, Z+ of this face
       sj[NFP + j] = jv;
@@ -217,8 +218,8 @@ dg_grad_accum_kernel(const GradArgs a) {
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
         const float vM = own[t][ii], tM = own[t][3 + ii];
-        const float vP = wall ? vM : nbv[t][ii];
-        const float tP = wall ? -tM : -nbv[t][3 + ii];
+        const float vP = wall ? gw * vM : nbv[t][ii];
+        const float tP = wall ? -gw * tM : -nbv[t][3 + ii];
         sj[ii * NFP + j] = 0.5f * (vP - vM);
         sj[(3 + ii) * NFP + j] = 0.5f * (tP - tM);
       }

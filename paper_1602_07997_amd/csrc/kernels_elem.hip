@@ -182,6 +182,7 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
     float fs;
     face_normal(G, f, nrm[f], fs);
     const bool wall = (word[f] & 7) == 7;
+    const float gw = (word[f] & 8) ? 0.0f : 1.0f;  // absorbing wall: zero exterior state
     const int o = word[f] & 7;
     // neighbour trace at own face node j: sum over orientations
     float nb[NT][NFP];
@@ -204,8 +205,8 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
         const int vn = face_node(N, f, j);
         const float pM = q[vn];
         const float vnM = nrm[f][0] * q[NP + vn] + nrm[f][1] * q[2 * NP + vn] + nrm[f][2] * q[3 * NP + vn];
-        const float pP = wall ? pM : nb[0][j];
-        const float vnP = wall ? -vnM : -nb[1][j];  // neighbour stored v.n with its own normal
+        const float pP = wall ? gw * pM : nb[0][j];
+        const float vnP = wall ? -gw * vnM : -nb[1][j];  // neighbour stored v.n with its own normal
         const float alpha = 0.5f * (pP - pM) - ZP * 0.5f * (vnP - vnM);
         pen[f][0][j] = fp * alpha;
         pen[f][1][j] = fv * alpha;
@@ -227,8 +228,8 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
                    q[(3 + voigt(ii, 2)) * NP + vn] * nrm[f][2];
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii) {
-          const float vP = wall ? vM[ii] : nb[ii][j];
-          const float tP = wall ? -tM[ii] : -nb[3 + ii][j];  // neighbour stored s n with its own normal
+          const float vP = wall ? gw * vM[ii] : nb[ii][j];
+          const float tP = wall ? -gw * tM[ii] : -nb[3 + ii][j];  // neighbour stored s n with its own normal
           jv[ii] = 0.5f * (vP - vM[ii]);
           jt[ii] = 0.5f * (tP - tM[ii]);
         }
@@ -396,7 +397,7 @@ __device__ __forceinline__ void step_elem(const StepArgs& a, int64_t k) {
 template <int N, int PHYS>
 __global__ void __launch_bounds__(kElemThreads)
 dg_step_elem_kernel(StepArgs a) {
-  const int64_t k = tile_of_block(a.xcd_remap) * kElemThreads + threadIdx.x;
+  const int64_t k = a.e_begin + tile_of_block(a.xcd_remap) * kElemThreads + threadIdx.x;
   if (k >= a.K) return;  // no barrier in this kernel
   step_elem<N, PHYS>(a, k);
 }
@@ -407,14 +408,14 @@ dg_step_elem_kernel_batch(const StepArgs* __restrict__ args, const int2* __restr
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
   const StepArgs a = args[w.x * kBatchPhases + phase];
-  const int64_t k = static_cast<int64_t>(w.y) * kElemThreads + threadIdx.x;
+  const int64_t k = a.e_begin + static_cast<int64_t>(w.y) * kElemThreads + threadIdx.x;
   if (k >= a.K) return;
   step_elem<N, PHYS>(a, k);
 }
 
 template <int N, int PHYS>
 hipError_t elem_impl(const StepArgs& a, hipStream_t s) {
-  int64_t tiles = (a.K + kElemThreads - 1) / kElemThreads;
+  int64_t tiles = (a.K - a.e_begin + kElemThreads - 1) / kElemThreads;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((dg_step_elem_kernel<N, PHYS>), dim3(static_cast<unsigned>(tiles)), dim3(kElemThreads), 0, s,

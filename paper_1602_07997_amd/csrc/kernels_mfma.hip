@@ -74,18 +74,27 @@ constexpr int acoustic_min_waves(int N, int PREC) {
   return (N == 4 && PREC == 0) ? 6 : ((N == 4 || N == 5) && PREC != 2 ? 5 : 1);
 }
 
-template <int N, int PREC>
+// Tile configuration CFG = precision (0 FP32, 1 BF16, 2 FP16) + 4 for the
+// alternative FP32 tile that the autotuner may pick per mesh: twice the
+// elements per tile and twice the wavefronts from N = 4 (pairs per wavefront
+// unchanged), half the elements per tile below (more, smaller tiles).
+constexpr int cfg_prec(int CFG) { return CFG & 3; }
+constexpr bool cfg_wide(int CFG) { return CFG >= 4; }
+
+template <int N, int CFG>
 struct MShape {
+  static constexpr int P = cfg_prec(CFG);        // precision of the products
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
-  static constexpr int KS = PREC == 0 ? 4 : 32;  // k per instruction
+  static constexpr int KS = P == 0 ? 4 : 32;     // k per instruction
   static constexpr int MB = (NP + 15) / 16;      // 16-row node blocks
   static constexpr int KP = rup(NP, KS);         // volume K, zero padded
   static constexpr int KF = rup(NFP, KS);        // LIFT K of one face, zero padded
   static constexpr int KL = 4 * KF;              // LIFT K, face blocks of KF
-  static constexpr int NBLK = (N <= 2) ? 4 : (N == 3 ? 2 : 1);
+  static constexpr int NBLK0 = (N <= 2) ? 4 : (N == 3 ? 2 : 1);
+  static constexpr int NBLK = !cfg_wide(CFG) ? NBLK0 : (N <= 3 ? NBLK0 / 2 : 2);
   static constexpr int E = 16 * NBLK;            // elements per tile
   static constexpr int PAIRS = MB * NBLK;
-  static constexpr int NW = acoustic_waves(N, PREC);  // wavefronts per workgroup
+  static constexpr int NW = acoustic_waves(N, P) * ((cfg_wide(CFG) && N >= 4) ? 2 : 1);  // wavefronts per workgroup
   static constexpr int THREADS = 64 * NW;
   // 4-byte words of B operands: four volume sets of KP rows, then (reused)
   // two penalty sets of KL rows
@@ -96,17 +105,17 @@ struct MShape {
 // the penalties): set s, row k, column e.
 //   FP32:   word (s*STRIDE + k)*E + swz(k, e)
 //   16-bit: hi at unit s*STRIDE*E + ((k/8)*E + e)*8 + k%8, lo REGION units later
-template <int N, int PREC, int STRIDE>
+template <int N, int CFG, int STRIDE>
 struct BRegion {
-  using S = MShape<N, PREC>;
+  using S = MShape<N, CFG>;
   float* w;
   __device__ __forceinline__ void put(int s, int k, int e, float x) const {
-    if constexpr (PREC == 0) {
+    if constexpr (S::P == 0) {
       w[(s * STRIDE + k) * S::E + swz<S::E>(k, e)] = x;
     } else {
       uint16_t* u = reinterpret_cast<uint16_t*>(w);
       uint16_t hi, lo;
-      split16<PREC>(x, hi, lo);
+      split16<S::P>(x, hi, lo);
       const int idx = s * STRIDE * S::E + ((k >> 3) * S::E + e) * 8 + (k & 7);
       u[idx] = hi;
       u[S::REGION + idx] = lo;
@@ -114,9 +123,10 @@ struct BRegion {
   }
 };
 
-template <int N, int PREC>
+template <int N, int CFG>
 __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) {
-  using S = MShape<N, PREC>;
+  using S = MShape<N, CFG>;
+  constexpr int PREC = S::P;
   constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
   constexpr int NF = 4, NT = 2, CB = 8;
   constexpr int FW = FaceRec<0>::W;
@@ -132,14 +142,14 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   __shared__ float s_face[E * 4 * FW];
   __shared__ float s_scr[NW * SCR];
 
-  const int64_t e0 = tile * E;
+  const int64_t e0 = a.e_begin + tile * E;
   if (e0 >= a.K) return;  // whole workgroup exits together
   const int ne = static_cast<int>((a.K - e0) < E ? (a.K - e0) : E);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const bool step = (a.mode == kStepMode);
-  const BRegion<N, PREC, KP> breg{s_B};   // volume operands
-  const BRegion<N, PREC, KL> lreg{s_B};   // penalty operands (after the volume products)
+  const BRegion<N, CFG, KP> breg{s_B};   // volume operands
+  const BRegion<N, CFG, KL> lreg{s_B};    // penalty operands (after the volume products)
   // tile-local arrays: uniform 64-bit bases, 32-bit offsets within the tile
   const float* tq = a.q_in + e0 * NF * NP;
   const float* ttr = a.qf_in + e0 * 4 * NT * NFP;
@@ -252,7 +262,8 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 #pragma unroll
   for (int t = NIT1; t < NIT; ++t) load_node(t);
   // upwind alpha at the face slots from the own and neighbour traces
-  // (rigid wall: mirror state p+ = p-, v.n+ = -v.n-; Z+ = Z- there)
+  // (rigid wall: mirror state p+ = p-, v.n+ = -v.n-; absorbing wall: zero
+  // exterior state; Z+ = Z- on both)
   float alpha[FIT];
   constexpr int FCH = LATE_OWN ? (FIT + 1) / 2 : FIT;  // items per round (register budget)
 #pragma unroll
@@ -277,8 +288,10 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
     const float pP = tr[0];
     const float vnP = -tr[NFP];  // the neighbour stored v.n with its own normal
     const float ZP = wall ? s_cf[ec * CB + 2] : s_cf[ec * CB + 4 + f];
-    const float pp = wall ? pM[t] : pP;
-    const float vp = wall ? -vnM[t] : vnP;
+    // absorbing wall (bit 3 of a wall's word): zero exterior state
+    const float gw = (w & 8) ? 0.0f : 1.0f;
+    const float pp = wall ? gw * pM[t] : pP;
+    const float vp = wall ? -gw * vnM[t] : vnP;
     alpha[t] = ok ? 0.5f * (pp - pM[t]) - ZP * 0.5f * (vp - vnM[t]) : 0.0f;
   }
   // materialise alpha here: otherwise the compiler sinks its arithmetic to
@@ -587,54 +600,59 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   }
 }
 
-template <int N, int PREC>
-__global__ void __launch_bounds__((MShape<N, PREC>::THREADS), (acoustic_min_waves(N, PREC)))
+template <int N, int CFG>
+__global__ void __launch_bounds__((MShape<N, CFG>::THREADS), (acoustic_min_waves(N, cfg_prec(CFG))))
 dg_step_mfma_acoustic(StepArgs a) {
-  step_mfma_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
+  step_mfma_tile<N, CFG>(a, tile_of_block(a.xcd_remap));
 }
 
-template <int N, int PREC>
-__global__ void __launch_bounds__((MShape<N, PREC>::THREADS), (acoustic_min_waves(N, PREC)))
+template <int N, int CFG>
+__global__ void __launch_bounds__((MShape<N, CFG>::THREADS), (acoustic_min_waves(N, cfg_prec(CFG))))
 dg_step_mfma_acoustic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
   const StepArgs a = args[w.x * kBatchPhases + phase];
-  step_mfma_tile<N, PREC>(a, w.y);
+  step_mfma_tile<N, CFG>(a, w.y);
 }
 
-template <int N, int PREC>
+template <int N, int CFG>
 hipError_t mfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(MShape<N, PREC>::THREADS), 0,
+  hipLaunchKernelGGL((dg_step_mfma_acoustic_batch<N, CFG>), dim3(static_cast<unsigned>(ntiles)), dim3(MShape<N, CFG>::THREADS), 0,
                      s, args, work, phase);
   return hipGetLastError();
 }
 
-template <int N, int PREC>
+template <int N, int CFG>
 hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
-  constexpr int E = MShape<N, PREC>::E;
-  int64_t tiles = (a.K + E - 1) / E;
+  constexpr int E = MShape<N, CFG>::E;
+  int64_t tiles = (a.K - a.e_begin + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(MShape<N, PREC>::THREADS), 0, s, a);
+  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, CFG>), dim3(static_cast<unsigned>(tiles)), dim3(MShape<N, CFG>::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-template <int N, int PREC>
+template <int N, int CFG>
 MfmaPacking packing_of() {
-  using S = MShape<N, PREC>;
+  using S = MShape<N, CFG>;
   return MfmaPacking{S::MB, S::KP, S::KL, S::KS, S::E, S::KF};
 }
 
 }  // namespace
 
 int mfma_precision(int variant) {
-  return variant == kVariantMfma ? 0 : (variant == kVariantMfmaBf16 ? 1 : (variant == kVariantMfmaF16 ? 2 : -1));
+  return (variant == kVariantMfma || variant == kVariantMfmaWide)
+             ? 0
+             : (variant == kVariantMfmaBf16 ? 1 : (variant == kVariantMfmaF16 ? 2 : -1));
 }
 
+// tile configuration of an acoustic MFMA variant (see MShape)
+static int mfma_config(int variant) { return variant == kVariantMfmaWide ? 4 : mfma_precision(variant); }
+
 #define DGW_MFMA_DISPATCH(CALL)                                                          \
-  switch (mfma_precision(variant)) {                                                     \
+  switch (mfma_config(variant)) {                                                        \
     case 0:                                                                              \
       switch (N) {                                                                       \
         case 1: return CALL(1, 0); case 2: return CALL(2, 0); case 3: return CALL(3, 0); \
@@ -654,6 +672,13 @@ int mfma_precision(int variant) {
         case 1: return CALL(1, 2); case 2: return CALL(2, 2); case 3: return CALL(3, 2); \
         case 4: return CALL(4, 2); case 5: return CALL(5, 2); case 6: return CALL(6, 2); \
         case 7: return CALL(7, 2); case 8: return CALL(8, 2);                            \
+      }                                                                                  \
+      break;                                                                             \
+    case 4:                                                                              \
+      switch (N) {                                                                       \
+        case 1: return CALL(1, 4); case 2: return CALL(2, 4); case 3: return CALL(3, 4); \
+        case 4: return CALL(4, 4); case 5: return CALL(5, 4); case 6: return CALL(6, 4); \
+        case 7: return CALL(7, 4); case 8: return CALL(8, 4);                            \
       }                                                                                  \
       break;                                                                             \
   }

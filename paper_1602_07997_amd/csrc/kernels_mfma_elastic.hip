@@ -140,7 +140,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   __shared__ float s_face[E * 4 * FW];
   __shared__ float s_scr[NW * SCR];
 
-  const int64_t e0 = tile * E;
+  const int64_t e0 = a.e_begin + tile * E;
   if (e0 >= a.K) return;  // whole workgroup exits together
   const int ne = static_cast<int>((a.K - e0) < E ? (a.K - e0) : E);
   const int tid = threadIdx.x;
@@ -250,6 +250,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
       const float* rec = s_face + (e * 4 + f) * FW;
       const float n0 = rec[0], n1 = rec[1], n2 = rec[2];
       const bool wall = (cw[t] & 7) == 7;
+      const float gw = (cw[t] & 8) ? 0.0f : 1.0f;  // absorbing wall: zero exterior state
       float vM[3], tM[3], vP[3], tP[3];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
@@ -257,8 +258,8 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
         tM[ii] = ot[t][3 + ii];
         // traction-free wall: mirror state v+ = v-, (s n)+ = -(s n)-;
         // otherwise the neighbour stored s n with its own normal
-        vP[ii] = wall ? vM[ii] : nt[t][ii];
-        tP[ii] = wall ? -tM[ii] : -nt[t][3 + ii];
+        vP[ii] = wall ? gw * vM[ii] : nt[t][ii];
+        tP[ii] = wall ? -gw * tM[ii] : -nt[t][3 + ii];
       }
       float jv[3], jt[3];
 #pragma unroll
@@ -617,7 +618,7 @@ dg_step_mfma_elastic_batch(const StepArgs* __restrict__ args, const int2* __rest
 template <int N, int PREC>
 hipError_t emfma_impl(const StepArgs& a, hipStream_t s) {
   constexpr int E = EShape<N, PREC>::E;
-  int64_t tiles = (a.K + E - 1) / E;
+  int64_t tiles = (a.K - a.e_begin + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(elastic_threads<N, PREC>()), 0, s, a);

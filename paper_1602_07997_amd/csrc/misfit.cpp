@@ -17,6 +17,7 @@
 #include "dgwave.h"
 #include "kernels.hpp"
 #include "solver_state.hpp"
+#include "workspace.hpp"
 
 using dgw::set_error;
 
@@ -29,29 +30,21 @@ const int kSrcElastic[] = {3, 4, 5};
 const int kRecAcoustic[] = {0};
 const int kRecElastic[] = {0, 1, 2};
 
-// Device buffer released on destruction.
+// A device array carved from the misfit's workspace (not owned).
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-  hipError_t alloc(size_t count) {
-    release();
+  void carve(dgw::Arena& a, size_t count) {
     n = count;
-    return hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(count, 1) * sizeof(T));
+    p = a.take<T>(count);
   }
-  hipError_t upload(const std::vector<T>& h) {
-    hipError_t e = alloc(h.size());
-    if (e != hipSuccess || h.empty()) return e;
-    return hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  // Stream-ordered copy of a host array of exactly n entries; the caller
+  // keeps `h` alive until the stream has passed the copy.
+  hipError_t upload(const std::vector<T>& h, hipStream_t st) {
+    if (h.size() != n) return hipErrorInvalidValue;
+    if (h.empty()) return hipSuccess;
+    return hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st);
   }
 };
 
@@ -129,14 +122,24 @@ struct DevInject {
   DevBuf<int32_t> start, field, chan;
   DevBuf<float> vec;
   int nelem = 0;
-  hipError_t upload(const HostInject& h) {
+  // arrays sized for h (an injection list of the same shape may be uploaded
+  // later with other values)
+  void carve(dgw::Arena& a, const HostInject& h) {
     nelem = static_cast<int>(h.elem.size());
+    elem.carve(a, h.elem.size());
+    start.carve(a, h.start.size());
+    field.carve(a, h.field.size());
+    chan.carve(a, h.chan.size());
+    vec.carve(a, h.vec.size());
+  }
+  hipError_t upload(const HostInject& h, hipStream_t st) {
+    if (static_cast<int>(h.elem.size()) != nelem) return hipErrorInvalidValue;
     hipError_t e;
-    if ((e = elem.upload(h.elem)) != hipSuccess) return e;
-    if ((e = start.upload(h.start)) != hipSuccess) return e;
-    if ((e = field.upload(h.field)) != hipSuccess) return e;
-    if ((e = chan.upload(h.chan)) != hipSuccess) return e;
-    return vec.upload(h.vec);
+    if ((e = elem.upload(h.elem, st)) != hipSuccess) return e;
+    if ((e = start.upload(h.start, st)) != hipSuccess) return e;
+    if ((e = field.upload(h.field, st)) != hipSuccess) return e;
+    if ((e = chan.upload(h.chan, st)) != hipSuccess) return e;
+    return vec.upload(h.vec, st);
   }
 };
 
@@ -243,6 +246,51 @@ dg_status load_segment_start(dg_misfit* f, int64_t seg) {
   return DG_OK;
 }
 
+// Adjoint source vectors s = P W^{-1} g per receiver channel:
+// dt P_c (C^{-1})_cc / J_k M^{-1} l(xi_r) with the coefficients `coef`
+// (host [K][ncoef]).  The list's shape depends only on the receivers.
+HostInject adjoint_entries(const dg_misfit* f, const std::vector<float>& coef) {
+  const dg_solver* s = f->s;
+  const dgw::RefElement* ref = dgw::reference_element(s->N);
+  const int Np = ref->Np;
+  std::vector<Entry> entries;
+  const int* rf = s->physics == DG_ACOUSTIC ? kRecAcoustic : kRecElastic;
+  const int nrf = s->physics == DG_ACOUSTIC ? 1 : 3;
+  for (int i = 0; i < f->nrec; ++i) {
+    const int64_t k = f->rec_elem_h[static_cast<size_t>(i)];
+    const double* v = s->elem_xyz.data() + 12 * k;
+    double F[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) F[a][b] = 0.5 * (v[3 * (b + 1) + a] - v[a]);
+    const double Jk = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                      F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                      F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+    std::vector<double> mw(static_cast<size_t>(Np), 0.0);
+    for (int n = 0; n < Np; ++n)
+      for (int m = 0; m < Np; ++m) mw[n] += ref->minv[n * Np + m] * f->rec_w[static_cast<size_t>(i)][m];
+    for (int c = 0; c < nrf; ++c) {
+      const int field = rf[c];
+      double scale;
+      if (s->physics == DG_ACOUSTIC) {
+        const double rho = coef[2 * k], cc = coef[2 * k + 1];
+        scale = field == 0 ? rho * cc * cc : -1.0 / rho;
+      } else {
+        scale = -1.0 / coef[3 * k];  // velocity receivers
+      }
+      std::vector<double> vec(static_cast<size_t>(Np));
+      for (int n = 0; n < Np; ++n) vec[n] = f->dt * scale / Jk * mw[n];
+      entries.push_back(Entry{k, field, i * nrf + c, vec});
+    }
+  }
+  return group_entries(entries);
+}
+
+// Builds a misfit in `workspace` (device, ws_bytes); with a null workspace
+// only the bytes it needs are computed (*need), nothing is returned.
+dg_status misfit_build(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
+                       const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
+                       void* workspace, size_t ws_bytes, size_t* need, dg_misfit** out);
+
 }  // namespace
 
 extern "C" {
@@ -267,96 +315,32 @@ dg_status dg_locate_points(dg_solver* s, int64_t n, const double* xyz, int64_t* 
   return DG_OK;
 }
 
+dg_status dg_misfit_workspace_bytes(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
+                                    const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
+                                    size_t* bytes) {
+  if (!bytes) {
+    set_error("dg_misfit_workspace_bytes: null output");
+    return DG_E_ARG;
+  }
+  return misfit_build(s, nsteps, dt, checkpoint_every, nsrc, src_xyz, wavelet, nrec, rec_xyz, nullptr, 0, bytes,
+                      nullptr);
+}
+
 dg_status dg_misfit_create(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
                            const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
-                           dg_misfit** out) {
-  if (!s || !out || nsteps < 1 || !(dt > 0.0) || checkpoint_every < 1 || nsrc < 0 || nrec < 1 ||
-      (nsrc > 0 && (!src_xyz || !wavelet)) || !rec_xyz) {
-    set_error("dg_misfit_create: bad arguments");
+                           void* workspace, size_t workspace_bytes, dg_misfit** out) {
+  if (!out) {
+    set_error("dg_misfit_create: null output");
     return DG_E_ARG;
   }
   *out = nullptr;
-  std::unique_ptr<dg_misfit> f(new dg_misfit);
-  f->s = s;
-  f->M = nsteps;
-  f->C = static_cast<int>(std::min<int64_t>(checkpoint_every, nsteps));
-  f->dt = dt;
-  f->nrec = nrec;
-  const dgw::RefElement* ref = dgw::reference_element(s->N);
-  const int Np = ref->Np;
-  const int* sf = s->physics == DG_ACOUSTIC ? kSrcAcoustic : kSrcElastic;
-  const int nsf = s->physics == DG_ACOUSTIC ? 1 : 3;
-  const int* rf = s->physics == DG_ACOUSTIC ? kRecAcoustic : kRecElastic;
-  const int nrf = s->physics == DG_ACOUSTIC ? 1 : 3;
-  f->R = nrec * nrf;
-  f->wavelet.assign(static_cast<size_t>(nsteps + 1), 0.0);
-  if (nsrc > 0) std::copy(wavelet, wavelet + nsteps + 1, f->wavelet.begin());
-
-  // host geometry for J_k
-  auto jac = [&](int64_t k) {
-    const double* v = s->elem_xyz.data() + 12 * k;
-    double F[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) F[i][j] = 0.5 * (v[3 * (j + 1) + i] - v[i]);
-    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-  };
-  // sources: b = (1/J_k) M^{-1} l(xi_s) in every source field
-  std::vector<Entry> src_entries;
-  std::vector<int64_t> pe(static_cast<size_t>(std::max(nsrc, nrec)));
-  std::vector<double> pw(static_cast<size_t>(std::max(nsrc, nrec)) * Np);
-  if (nsrc > 0) {
-    if (dg_status st = dg_locate_points(s, nsrc, src_xyz, pe.data(), pw.data())) return st;
-    for (int i = 0; i < nsrc; ++i) {
-      std::vector<double> b(static_cast<size_t>(Np), 0.0);
-      const double Jk = jac(pe[i]);
-      for (int n = 0; n < Np; ++n)
-        for (int m = 0; m < Np; ++m) b[n] += ref->minv[n * Np + m] * pw[i * Np + m] / Jk;
-      for (int c = 0; c < nsf; ++c) src_entries.push_back(Entry{pe[i], sf[c], -1, b});
-    }
+  if (!workspace || !dgw::workspace_aligned(workspace)) {
+    set_error("dg_misfit_create: the workspace must be a non-null device pointer aligned to 256 bytes");
+    return DG_E_ARG;
   }
-  // receivers: channel ch = (receiver, field)
-  if (dg_status st = dg_locate_points(s, nrec, rec_xyz, pe.data(), pw.data())) return st;
-  std::vector<int64_t> che;
-  std::vector<int32_t> chf;
-  std::vector<float> chw;
-  for (int i = 0; i < nrec; ++i) {
-    f->rec_elem_h.push_back(pe[i]);
-    f->rec_w.emplace_back(pw.begin() + i * Np, pw.begin() + (i + 1) * Np);
-    for (int c = 0; c < nrf; ++c) {
-      che.push_back(pe[i]);
-      chf.push_back(rf[c]);
-      for (int n = 0; n < Np; ++n) chw.push_back(static_cast<float>(pw[i * Np + n]));
-    }
-  }
-  hipError_t err;
-  auto fail = [&](hipError_t e, const char* what) {
-    std::ostringstream os;
-    os << "dg_misfit_create: " << what << ": " << hipGetErrorString(e);
-    set_error(os.str());
-    return DG_E_HIP;
-  };
-  if ((err = f->src.upload(group_entries(src_entries))) != hipSuccess) return fail(err, "source upload");
-  if ((err = f->ch_elem.upload(che)) != hipSuccess || (err = f->ch_field.upload(chf)) != hipSuccess ||
-      (err = f->ch_w.upload(chw)) != hipSuccess)
-    return fail(err, "receiver upload");
-  f->nq = static_cast<size_t>(s->K) * s->NF * s->Np;
-  f->ntr = static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp;
-  const size_t nseg = static_cast<size_t>(num_segments(f.get()));
-  if ((err = f->traces.alloc(static_cast<size_t>(nsteps + 1) * f->R)) != hipSuccess ||
-      (err = f->data.alloc(static_cast<size_t>(nsteps + 1) * f->R)) != hipSuccess ||
-      (err = f->seg_q.alloc((f->C + 1) * f->nq)) != hipSuccess ||
-      (err = f->seg_tr.alloc((f->C + 1) * f->ntr)) != hipSuccess ||
-      (err = f->seg_r.alloc(f->C * f->nq)) != hipSuccess || (err = f->ck.alloc(3 * nseg * f->nq)) != hipSuccess ||
-      (err = f->phi.alloc(4 * f->nq)) != hipSuccess || (err = f->aring.alloc(3 * f->nq)) != hipSuccess ||
-      (err = f->atr.alloc(2 * f->ntr)) != hipSuccess ||
-      (err = f->gacc.alloc(static_cast<size_t>(s->K) * dgw::kGradAccStride)) != hipSuccess)
-    return fail(err, "allocation");
-  std::vector<float> mf(ref->mass.begin(), ref->mass.end()), fmf(ref->face_mass.begin(), ref->face_mass.end());
-  if ((err = f->mass_f.upload(mf)) != hipSuccess || (err = f->face_mass_f.upload(fmf)) != hipSuccess)
-    return fail(err, "operator upload");
-  *out = f.release();
-  return DG_OK;
+  size_t need = 0;
+  return misfit_build(s, nsteps, dt, checkpoint_every, nsrc, src_xyz, wavelet, nrec, rec_xyz, workspace,
+                      workspace_bytes, &need, out);
 }
 
 void dg_misfit_destroy(dg_misfit* f) {
@@ -439,47 +423,13 @@ dg_status dg_misfit_gradient(dg_misfit* f, float* grad) {
     set_error("dg_misfit_gradient: the coefficients changed after the last dg_misfit_forward");
     return DG_E_STATE;
   }
-  const dgw::RefElement* ref = dgw::reference_element(s->N);
-  const int Np = ref->Np;
-  // adjoint source vectors s = P W^{-1} g: per channel
-  // dt P_c (C^{-1})_cc / J_k M^{-1} l(xi_r), with the current coefficients
+  // adjoint source vectors with the current coefficients
   std::vector<float> coef(static_cast<size_t>(s->K) * s->ncoef);
   DG_HIP(hipMemcpyAsync(coef.data(), s->coef, coef.size() * sizeof(float), hipMemcpyDeviceToHost, s->stream));
   DG_HIP(hipStreamSynchronize(s->stream));
-  std::vector<Entry> entries;
-  const int* rf = s->physics == DG_ACOUSTIC ? kRecAcoustic : kRecElastic;
-  const int nrf = s->physics == DG_ACOUSTIC ? 1 : 3;
-  for (int i = 0; i < f->nrec; ++i) {
-    const int64_t k = f->rec_elem_h[static_cast<size_t>(i)];
-    const double* v = s->elem_xyz.data() + 12 * k;
-    double F[3][3];
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) F[a][b] = 0.5 * (v[3 * (b + 1) + a] - v[a]);
-    const double Jk = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
-                      F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-                      F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-    std::vector<double> mw(static_cast<size_t>(Np), 0.0);
-    for (int n = 0; n < Np; ++n)
-      for (int m = 0; m < Np; ++m) mw[n] += ref->minv[n * Np + m] * f->rec_w[static_cast<size_t>(i)][m];
-    for (int c = 0; c < nrf; ++c) {
-      const int field = rf[c];
-      double scale;
-      if (s->physics == DG_ACOUSTIC) {
-        const double rho = coef[2 * k], cc = coef[2 * k + 1];
-        scale = field == 0 ? rho * cc * cc : -1.0 / rho;
-      } else {
-        scale = -1.0 / coef[3 * k];  // velocity receivers
-      }
-      std::vector<double> vec(static_cast<size_t>(Np));
-      for (int n = 0; n < Np; ++n) vec[n] = f->dt * scale / Jk * mw[n];
-      entries.push_back(Entry{k, field, i * nrf + c, vec});
-    }
-  }
-  hipError_t err = f->adj.upload(group_entries(entries));
-  if (err != hipSuccess) {
-    set_error(std::string("adjoint source upload: ") + hipGetErrorString(err));
-    return DG_E_HIP;
-  }
+  const HostInject adj_h = adjoint_entries(f, coef);
+  DG_HIP(f->adj.upload(adj_h, s->stream));
+  DG_HIP(hipStreamSynchronize(s->stream));  // adj_h dies at return
 
   auto phi = [&](int64_t j) { return f->phi.p + (j % 4) * f->nq; };
   auto aring = [&](int64_t j) { return f->aring.p + (j % 3) * f->nq; };
@@ -557,3 +507,120 @@ dg_status dg_misfit_gradient(dg_misfit* f, float* grad) {
 }
 
 }  // extern "C"
+
+namespace {
+
+dg_status misfit_build(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
+                       const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
+                       void* workspace, size_t ws_bytes, size_t* need, dg_misfit** out) {
+  if (!s || nsteps < 1 || !(dt > 0.0) || checkpoint_every < 1 || nsrc < 0 || nrec < 1 ||
+      (nsrc > 0 && (!src_xyz || !wavelet)) || !rec_xyz) {
+    set_error("dg_misfit_create: bad arguments");
+    return DG_E_ARG;
+  }
+  std::unique_ptr<dg_misfit> f(new dg_misfit);
+  f->s = s;
+  f->M = nsteps;
+  f->C = static_cast<int>(std::min<int64_t>(checkpoint_every, nsteps));
+  f->dt = dt;
+  f->nrec = nrec;
+  const dgw::RefElement* ref = dgw::reference_element(s->N);
+  const int Np = ref->Np;
+  const int* sf = s->physics == DG_ACOUSTIC ? kSrcAcoustic : kSrcElastic;
+  const int nsf = s->physics == DG_ACOUSTIC ? 1 : 3;
+  const int* rf = s->physics == DG_ACOUSTIC ? kRecAcoustic : kRecElastic;
+  const int nrf = s->physics == DG_ACOUSTIC ? 1 : 3;
+  f->R = nrec * nrf;
+  f->wavelet.assign(static_cast<size_t>(nsteps + 1), 0.0);
+  if (nsrc > 0) std::copy(wavelet, wavelet + nsteps + 1, f->wavelet.begin());
+
+  // host geometry for J_k
+  auto jac = [&](int64_t k) {
+    const double* v = s->elem_xyz.data() + 12 * k;
+    double F[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) F[i][j] = 0.5 * (v[3 * (j + 1) + i] - v[i]);
+    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  };
+  // sources: b = (1/J_k) M^{-1} l(xi_s) in every source field
+  std::vector<Entry> src_entries;
+  std::vector<int64_t> pe(static_cast<size_t>(std::max(nsrc, nrec)));
+  std::vector<double> pw(static_cast<size_t>(std::max(nsrc, nrec)) * Np);
+  if (nsrc > 0) {
+    if (dg_status st = dg_locate_points(s, nsrc, src_xyz, pe.data(), pw.data())) return st;
+    for (int i = 0; i < nsrc; ++i) {
+      std::vector<double> b(static_cast<size_t>(Np), 0.0);
+      const double Jk = jac(pe[i]);
+      for (int n = 0; n < Np; ++n)
+        for (int m = 0; m < Np; ++m) b[n] += ref->minv[n * Np + m] * pw[i * Np + m] / Jk;
+      for (int c = 0; c < nsf; ++c) src_entries.push_back(Entry{pe[i], sf[c], -1, b});
+    }
+  }
+  // receivers: channel ch = (receiver, field)
+  if (dg_status st = dg_locate_points(s, nrec, rec_xyz, pe.data(), pw.data())) return st;
+  std::vector<int64_t> che;
+  std::vector<int32_t> chf;
+  std::vector<float> chw;
+  for (int i = 0; i < nrec; ++i) {
+    f->rec_elem_h.push_back(pe[i]);
+    f->rec_w.emplace_back(pw.begin() + i * Np, pw.begin() + (i + 1) * Np);
+    for (int c = 0; c < nrf; ++c) {
+      che.push_back(pe[i]);
+      chf.push_back(rf[c]);
+      for (int n = 0; n < Np; ++n) chw.push_back(static_cast<float>(pw[i * Np + n]));
+    }
+  }
+  f->nq = static_cast<size_t>(s->K) * s->NF * s->Np;
+  f->ntr = static_cast<size_t>(s->K) * 4 * s->NT * s->Nfp;
+  const size_t nseg = static_cast<size_t>(num_segments(f.get()));
+  const HostInject src_h = group_entries(src_entries);
+  // the adjoint source list has the receivers' shape; its values follow the
+  // coefficients and are written by each gradient call
+  const HostInject adj_h = adjoint_entries(f.get(), std::vector<float>(static_cast<size_t>(s->K) * s->ncoef, 1.0f));
+  std::vector<float> mf(ref->mass.begin(), ref->mass.end()), fmf(ref->face_mass.begin(), ref->face_mass.end());
+
+  // ---- layout in the workspace ----
+  dgw::Arena arena(workspace, ws_bytes);
+  f->src.carve(arena, src_h);
+  f->adj.carve(arena, adj_h);
+  f->ch_elem.carve(arena, che.size());
+  f->ch_field.carve(arena, chf.size());
+  f->ch_w.carve(arena, chw.size());
+  f->traces.carve(arena, static_cast<size_t>(nsteps + 1) * f->R);
+  f->data.carve(arena, static_cast<size_t>(nsteps + 1) * f->R);
+  f->seg_q.carve(arena, (f->C + 1) * f->nq);
+  f->seg_tr.carve(arena, (f->C + 1) * f->ntr);
+  f->seg_r.carve(arena, f->C * f->nq);
+  f->ck.carve(arena, 3 * nseg * f->nq);
+  f->phi.carve(arena, 4 * f->nq);
+  f->aring.carve(arena, 3 * f->nq);
+  f->atr.carve(arena, 2 * f->ntr);
+  f->gacc.carve(arena, static_cast<size_t>(s->K) * dgw::kGradAccStride);
+  f->mass_f.carve(arena, mf.size());
+  f->face_mass_f.carve(arena, fmf.size());
+  if (need) *need = arena.used();
+  if (!workspace) return DG_OK;
+  if (!arena.fits()) {
+    std::ostringstream os;
+    os << "dg_misfit_create: workspace holds " << ws_bytes << " bytes, the misfit needs " << arena.used();
+    set_error(os.str());
+    return DG_E_SHAPE;
+  }
+  hipError_t err = f->src.upload(src_h, s->stream);
+  if (err == hipSuccess) err = f->adj.upload(adj_h, s->stream);
+  if (err == hipSuccess) err = f->ch_elem.upload(che, s->stream);
+  if (err == hipSuccess) err = f->ch_field.upload(chf, s->stream);
+  if (err == hipSuccess) err = f->ch_w.upload(chw, s->stream);
+  if (err == hipSuccess) err = f->mass_f.upload(mf, s->stream);
+  if (err == hipSuccess) err = f->face_mass_f.upload(fmf, s->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(s->stream);  // the host arrays die here
+  if (err != hipSuccess) {
+    set_error(std::string("dg_misfit_create: upload: ") + hipGetErrorString(err));
+    return DG_E_HIP;
+  }
+  *out = f.release();
+  return DG_OK;
+}
+
+}  // namespace

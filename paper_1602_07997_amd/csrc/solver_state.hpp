@@ -23,6 +23,8 @@
     }                                                  \
   } while (0)
 
+// Every device pointer below points into the caller's workspace (see
+// dg_workspace_bytes); the solver owns none of them.
 struct dg_solver {
   int physics = 0, N = 0, Np = 0, Nfp = 0, NF = 0, NT = 0, CB = 0, ncoef = 0;
   int64_t K = 0;
@@ -46,6 +48,9 @@ struct dg_solver {
   double* partial = nullptr;
   double* e_out = nullptr;
   int* flag = nullptr;
+  int32_t* iface = nullptr;  // [K] slow elements with a fast neighbour (two-rate stepping)
+  int64_t k_fast = 0;        // elements [0, k_fast) take two half steps (0: single rate)
+  int64_t n_iface = 0;
   int cur = 0;     // trace buffer holding the traces of q
   int64_t m = 0;   // step index
   bool have_coef = false, have_fields = false;
@@ -62,6 +67,7 @@ struct dg_solver {
   uint16_t* D16[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [bf16, f16][hi, lo]
   uint16_t* L16[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   std::vector<double> elem_xyz;  // host copy for node coordinates
+  std::vector<int32_t> conn_h;   // host copy of the packed face words
 };
 
 namespace dgw {

@@ -1,8 +1,9 @@
 """Python front end of the dgwave C ABI.
 
 Marshals numpy / torch arrays into the C calls; every step of the hot path
-runs in the library's HIP kernels.  Torch supplies device memory and the
-stream only.
+runs in the library's HIP kernels.  Torch supplies the device memory (one
+uint8 workspace per solver, batch and misfit, sized by the library's
+*_workspace_bytes queries) and the stream; the library allocates none.
 """
 
 from __future__ import annotations
@@ -100,21 +101,31 @@ class DGSolver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
+        # every device array of the solver lives in one torch-owned buffer
+        nbytes = C.c_size_t(0)
+        check(lib.dg_workspace_bytes(PHYSICS[physics], order, self.K, C.byref(nbytes)), "dg_workspace_bytes")
+        with torch.cuda.stream(stream):
+            self._workspace = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
         h = C.c_void_p()
         check(
             lib.dg_create(
                 PHYSICS[physics], order, self.K, _dptr(self.xyz), _i64ptr(self.topo),
-                C.c_void_p(stream.cuda_stream), C.byref(h),
+                C.c_void_p(self._workspace.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream), C.byref(h),
             ),
             "dg_create",
         )
         self._h = h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._workspace.numel())
 
     # lifecycle ---------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None):
             lib.dg_destroy(self._h)
             self._h = None
+        self._workspace = None
 
     def __del__(self):
         try:
@@ -143,6 +154,15 @@ class DGSolver:
         check(lib.dg_set_coefficients(self._h, p), "dg_set_coefficients")
         self.coef_generation = getattr(self, "coef_generation", 0) + 1
         self.last_coefficients = coef.detach().clone()
+
+    def set_boundary(self, absorbing):
+        """Absorbing unpaired faces: ``absorbing`` is a bool [K, 4] mask (True
+        = absorbing; False = reflecting wall; faces with a neighbour must be
+        False)."""
+        kind = np.ascontiguousarray(np.asarray(absorbing, dtype=bool).astype(np.int32))
+        if kind.shape != (self.K, 4):
+            raise ValueError(f"absorbing mask has shape {kind.shape}, expected ({self.K}, 4)")
+        check(lib.dg_set_boundary(self._h, _i32ptr(kind)), "dg_set_boundary")
 
     def set_fields(self, q):
         check(lib.dg_set_fields(self._h, _require_torch_device_tensor(q, self.field_shape, "q")), "dg_set_fields")
@@ -179,6 +199,7 @@ class DGSolver:
         "mfma_bf16": nat.DG_VARIANT_MFMA_BF16,
         "mfma_f16": nat.DG_VARIANT_MFMA_F16,
         "elem": nat.DG_VARIANT_ELEM,
+        "mfma_wide": nat.DG_VARIANT_MFMA_WIDE,
     }
 
     @property
@@ -200,20 +221,38 @@ class DGSolver:
     def step(self, nsteps: int, dt: float):
         check(lib.dg_step(self._h, int(nsteps), float(dt)), "dg_step")
 
+    def set_rate_classes(self, k_fast: int):
+        """Elements [0, k_fast) take two half steps per step (two-rate
+        stepping; 0 = single rate).  Restarts the Adams-Bashforth start-up."""
+        check(lib.dg_set_rate_classes(self._h, int(k_fast)), "dg_set_rate_classes")
+
+    def step_multirate(self, nsteps: int, dt: float):
+        """``nsteps`` macro steps of size dt (the fast class takes 2 nsteps
+        steps of dt/2)."""
+        check(lib.dg_step_multirate(self._h, int(nsteps), float(dt)), "dg_step_multirate")
+
     def autotune(self, steps: int, dt: float, candidates=None) -> dict:
         """Times the built variants (all, or the names in ``candidates``) on
         this mesh and keeps the fastest.
 
         Returns microseconds per step by variant name (None where not built
-        or not a candidate).  The solver's state is restored, so the solution
-        does not advance.
+        or not a candidate).  The timed steps write their fields into a
+        scratch array, so the solver's state does not change.
         """
+        import torch
+
         mask = 0
         if candidates is not None:
             for name in candidates:
                 mask |= 1 << self.VARIANTS[name]
         us = np.zeros(nat.DG_NUM_VARIANTS)
-        check(lib.dg_autotune(self._h, int(steps), float(dt), mask, _dptr(us)), "dg_autotune")
+        with torch.cuda.stream(self._stream):
+            scratch = self.empty_fields()
+        nbytes = scratch.numel() * scratch.element_size()
+        check(
+            lib.dg_autotune(self._h, int(steps), float(dt), mask, C.c_void_p(scratch.data_ptr()), nbytes, _dptr(us)),
+            "dg_autotune",
+        )
         names = {b: a for a, b in self.VARIANTS.items()}
         return {names[v]: (float(us[v]) if us[v] >= 0 else None) for v in range(nat.DG_NUM_VARIANTS)}
 
@@ -278,10 +317,16 @@ class DGBatch:
             stream = torch.cuda.current_stream()
         self._stream = stream
         arr = (C.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        members = C.cast(arr, C.POINTER(C.c_void_p))
+        nbytes = C.c_size_t(0)
+        check(lib.dg_batch_workspace_bytes(members, len(self.members), C.byref(nbytes)), "dg_batch_workspace_bytes")
+        with torch.cuda.stream(stream):
+            self._workspace = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
         h = C.c_void_p()
         check(
             lib.dg_batch_create(
-                C.cast(arr, C.POINTER(C.c_void_p)), len(self.members), C.c_void_p(stream.cuda_stream), C.byref(h)
+                members, len(self.members), C.c_void_p(self._workspace.data_ptr()), nbytes,
+                C.c_void_p(stream.cuda_stream), C.byref(h),
             ),
             "dg_batch_create",
         )
@@ -293,6 +338,7 @@ class DGBatch:
         if getattr(self, "_h", None):
             lib.dg_batch_destroy(self._h)
             self._h = None
+        self._workspace = None
 
     def __del__(self):
         try:

@@ -59,7 +59,9 @@ class Case:
     """One mesh / physics / degree, set up on both the GPU and the oracle."""
 
     def __init__(self, physics, N, n, jitter=0.1, seed=0, coef_kind="random", periodic=False,
-                 init="gaussian", dims=None, mesh=None):
+                 init="gaussian", dims=None, mesh=None, absorbing=None):
+        """``absorbing``: None (reflecting walls), "all" or "half" (a seeded
+        random half of the unpaired faces absorb), or a (K, 4) bool mask."""
         import torch
 
         from paper_1602_07997_amd import DGSolver
@@ -74,7 +76,15 @@ class Case:
         self.solver.set_coefficients(torch.tensor(self.coef, dtype=torch.float32, device="cuda"))
         self.q0_gpu = initial_fields(physics, self.solver.node_coordinates(), init)
         self.geo = build_mesh(N, mesh.elem_xyz, mesh.elem_topo, mesh.period)
-        self.oracle = make_oracle(physics, self.geo, self.coef)
+        if isinstance(absorbing, str):
+            if absorbing == "all":
+                absorbing = self.geo.wall.copy()
+            else:
+                absorbing = self.geo.wall & (np.random.default_rng(seed + 99).random(self.geo.wall.shape) < 0.5)
+        self.absorbing = absorbing
+        if absorbing is not None:
+            self.solver.set_boundary(absorbing)
+        self.oracle = make_oracle(physics, self.geo, self.coef, absorbing=absorbing)
         self.q0 = initial_fields(physics, self.geo.xyz, init)
         self.dt = di.time_step(mesh, N, di.max_wave_speed(self.coef, physics))
 

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported_and_bound():
         assert hasattr(nat.lib, name), name
         assert name in nat.SIGNATURES, name
     assert set(nat.SIGNATURES) == set(names)
-    assert nat.lib.dg_abi_version() == 1
+    assert nat.lib.dg_abi_version() == 2
     assert nat.lib.dg_num_fields(0) == 4 and nat.lib.dg_num_fields(1) == 9
     assert nat.lib.dg_num_fields(7) == -1
 
@@ -114,15 +114,81 @@ def test_host_validation_errors():
         mesh_connectivity(topo)
 
 
-def _create(physics, order, xyz, topo):
+# A stand-in workspace address: 256-byte aligned, never dereferenced, since
+# every check below fails (or the size check refuses it) before device work.
+FAKE_WS = C.c_void_p(1 << 20)
+
+
+def _create(physics, order, xyz, topo, ws=FAKE_WS, ws_bytes=0):
     h = C.c_void_p()
     xyz = np.ascontiguousarray(xyz, dtype=np.float64)
     topo = np.ascontiguousarray(topo, dtype=np.int64)
     st = nat.lib.dg_create(
         physics, order, xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)),
-        topo.ctypes.data_as(C.POINTER(C.c_int64)), None, C.byref(h),
+        topo.ctypes.data_as(C.POINTER(C.c_int64)), ws, ws_bytes, None, C.byref(h),
     )
     return st, h
+
+
+def _ws_bytes(physics, order, K):
+    n = C.c_size_t(0)
+    st = nat.lib.dg_workspace_bytes(physics, order, K, C.byref(n))
+    return st, n.value
+
+
+@pytest.mark.parametrize("physics", [0, 1])
+@pytest.mark.parametrize("N", [1, 4, 8])
+def test_workspace_bytes_cover_every_array(physics, N):
+    """The workspace holds q, the three-slot AB3 ring, three trace buffers and
+    the per-element and operator tables, each 256-byte aligned."""
+    Np, Nfp = (N + 1) * (N + 2) * (N + 3) // 6, (N + 1) * (N + 2) // 2
+    NF, NT = (4, 2) if physics == 0 else (9, 6)
+    for K in (1, 48, 1000):
+        st, n = _ws_bytes(physics, N, K)
+        assert st == nat.DG_OK
+        assert n % 256 == 0
+        floor = 4 * (4 * K * NF * Np + 3 * K * 4 * NT * Nfp + 9 * K) + 8 * K
+        assert n >= floor
+    # the operator tables do not grow with K; per element: q and three ring
+    # slots, three trace buffers, G, derived and raw coefficients, four face
+    # words, J and at most one energy partial sum
+    CB, ncoef = (8, 2) if physics == 0 else (16, 3)
+    per_elem = 4 * (4 * NF * Np + 3 * 4 * NT * Nfp + 9 + CB + ncoef + 4) + 8
+    _, n1 = _ws_bytes(physics, N, 1000)
+    _, n2 = _ws_bytes(physics, N, 2000)
+    delta = (n2 - n1) - 1000 * per_elem
+    assert -32 * 256 <= delta <= 1000 * 8 + 32 * 256  # alignment of each array, energy partial sums
+
+
+def test_workspace_bytes_argument_errors():
+    assert _ws_bytes(0, 2, 0)[0] == nat.DG_E_ARG
+    assert _ws_bytes(0, 2, 1 << 26)[0] == nat.DG_E_ARG
+    assert _ws_bytes(3, 2, 10)[0] == nat.DG_E_ARG
+    assert _ws_bytes(0, 9, 10)[0] == nat.DG_E_UNSUPPORTED
+    assert nat.lib.dg_workspace_bytes(0, 2, 10, None) == nat.DG_E_ARG
+
+
+def test_create_checks_the_workspace_before_device_work():
+    m = di.kuhn_box(2)
+    _, need = _ws_bytes(0, 2, m.K)
+    st, h = _create(0, 2, m.elem_xyz, m.elem_topo, ws=FAKE_WS, ws_bytes=need - 1)
+    assert st == nat.DG_E_SHAPE and not h.value
+    assert str(need) in nat.lib.dg_last_error().decode()
+    st, h = _create(0, 2, m.elem_xyz, m.elem_topo, ws=C.c_void_p((1 << 20) + 64), ws_bytes=need)
+    assert st == nat.DG_E_ARG and "aligned" in nat.lib.dg_last_error().decode()
+    st, h = _create(0, 2, m.elem_xyz, m.elem_topo, ws=None, ws_bytes=need)
+    assert st == nat.DG_E_ARG
+
+
+def test_library_never_allocates_device_memory():
+    """Device memory comes from the caller: no allocation call in the sources
+    (the static array of the allocation-free energy entry point is not one)."""
+    csrc = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1602_07997_amd", "csrc")
+    pat = re.compile(r"\b(hipMalloc\w*|hipFree\w*|hipExtMalloc\w*|hipHostMalloc|hipMallocManaged)\s*\(")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".cpp", ".hip", ".hpp", ".h")):
+            text = re.sub(r"//[^\n]*", "", open(os.path.join(csrc, name)).read())
+            assert not pat.search(text), name
 
 
 def test_create_rejects_bad_meshes_before_device_work():
@@ -160,17 +226,21 @@ def test_empty_and_oversized_meshes_rejected():
     h = C.c_void_p()
     st = nat.lib.dg_create(
         0, 2, 1 << 26, one.elem_xyz.ctypes.data_as(C.POINTER(C.c_double)),
-        one.elem_topo.ctypes.data_as(C.POINTER(C.c_int64)), None, C.byref(h),
+        one.elem_topo.ctypes.data_as(C.POINTER(C.c_int64)), FAKE_WS, 1 << 40, None, C.byref(h),
     )
     assert st == nat.DG_E_ARG and not h.value
 
 
 def test_batch_and_misfit_entry_points_reject_null_arguments():
     out = C.c_void_p()
-    assert nat.lib.dg_batch_create(None, 0, None, C.byref(out)) == nat.DG_E_ARG
+    nb = C.c_size_t(0)
+    assert nat.lib.dg_batch_create(None, 0, FAKE_WS, 0, None, C.byref(out)) == nat.DG_E_ARG
+    assert nat.lib.dg_batch_workspace_bytes(None, 0, C.byref(nb)) == nat.DG_E_ARG
     assert nat.lib.dg_batch_step(None, 1, None) == nat.DG_E_ARG
-    assert nat.lib.dg_autotune(None, 1, 1.0, 0, None) == nat.DG_E_ARG
-    assert nat.lib.dg_misfit_create(None, 10, 0.1, 5, 0, None, None, 1, None, C.byref(out)) == nat.DG_E_ARG
+    assert nat.lib.dg_autotune(None, 1, 1.0, 0, None, 0, None) == nat.DG_E_ARG
+    assert nat.lib.dg_misfit_create(None, 10, 0.1, 5, 0, None, None, 1, None, FAKE_WS, 0,
+                                    C.byref(out)) == nat.DG_E_ARG
+    assert nat.lib.dg_misfit_workspace_bytes(None, 10, 0.1, 5, 0, None, None, 1, None, C.byref(nb)) == nat.DG_E_ARG
     assert nat.lib.dg_misfit_forward(None, None, None, None) == nat.DG_E_ARG
     assert nat.lib.dg_misfit_gradient(None, None) == nat.DG_E_ARG
     assert nat.lib.dg_misfit_channels(None) == -1

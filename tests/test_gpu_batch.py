@@ -49,7 +49,8 @@ def _rel(a: torch.Tensor, b: torch.Tensor) -> float:
 
 
 ACOUSTIC_SPECS = [(1, (3, 2, 2), "valu"), (2, (2, 3, 2), "valu"), (3, (3, 3, 2), "mfma"),
-                  (3, (2, 2, 2), "valu"), (5, (2, 2, 3), "mfma"), (2, (4, 3, 3), "mfma")]
+                  (3, (2, 2, 2), "valu"), (5, (2, 2, 3), "mfma"), (2, (4, 3, 3), "mfma"),
+                  (4, (3, 2, 3), "mfma_wide"), (2, (3, 3, 2), "mfma_wide")]
 ELASTIC_SPECS = [(1, (3, 2, 2), "valu"), (2, (2, 3, 2), "valu"), (4, (2, 2, 2), "valu"),
                  (2, (3, 3, 2), "valu"), (6, (3, 2, 3), "mfma"), (1, (3, 3, 2), "elem")]
 

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import dginputs as di
 from oracle.dg import AB3Stepper
 from tests._cases import Case, log
 
@@ -240,6 +241,32 @@ def test_mfma_variant_parity(N, physics):
     c.solver.step(20, c.dt)
     q = c.to_host(c.solver.get_fields())
     c.check(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt), 1e-5, "20 steps")
+
+
+@pytest.mark.parametrize("N", DEGREES)
+def test_mfma_wide_tile_parity(N):
+    """The other acoustic FP32 tile shape (twice the elements and wavefronts
+    per workgroup from N = 4, half the elements below): one right-hand side
+    and 20 AB3 steps on 160 elements (several full tiles of 32 or 64 and a
+    ragged last one, or many small tiles), all six face orientations."""
+    log(f"mfma wide tile acoustic N={N}")
+    mesh = di.relabel_vertices(di.kuhn_box(3, 3, 2, jitter=0.1, seed=70 + N), seed=71 + N)
+    c = Case("acoustic", N, 0, coef_kind="random", init="smooth", mesh=mesh, seed=70 + N)
+    c.solver.variant = "mfma_wide"
+    assert c.solver.variant == "mfma_wide"
+    r = c.solver.rhs(c.to_gpu(c.q0_gpu))
+    torch.cuda.synchronize()
+    c.check(c.to_host(r), c.oracle.rhs(c.q0), 2e-6, "rhs")
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    c.solver.step(20, c.dt)
+    c.check(c.to_host(c.solver.get_fields()), AB3Stepper(c.oracle, c.q0).step(20, c.dt), 1e-5, "20 steps")
+
+
+def test_mfma_wide_is_acoustic_only():
+    from paper_1602_07997_amd._native import DG_E_UNSUPPORTED, DG_VARIANT_MFMA_WIDE, lib
+
+    c = Case("elastic", 2, 1, jitter=0.0, coef_kind="random", init="smooth")
+    assert lib.dg_set_variant(c.solver._h, DG_VARIANT_MFMA_WIDE) == DG_E_UNSUPPORTED
 
 
 def test_unknown_variant_rejected():
