@@ -267,9 +267,97 @@ def elastic_loguniform(mesh: TetMesh, seed: int, lo: float = 0.5, hi: float = 2.
     return np.exp(rng.uniform(math.log(lo), math.log(hi), size=(mesh.K, 3)))
 
 
+ANISO_UPPER6 = [(a, b) for a in range(6) for b in range(a, 6)]  # order of the 21 stiffness entries
+
+
+def anisotropic_random(mesh: TetMesh, seed: int, strength: float = 0.35) -> np.ndarray:
+    """Per element (rho, 21 upper-triangle entries of a symmetric positive
+    definite Voigt stiffness C): an isotropic stiffness with lambda, mu
+    log-uniform on [1/2, 2] plus a seeded symmetric perturbation of relative
+    size `strength`, redrawn until C is positive definite with its smallest
+    eigenvalue at least a tenth of mu; rho log-uniform on [1/2, 2]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((mesh.K, 22))
+    for k in range(mesh.K):
+        rho, lam, mu = np.exp(rng.uniform(np.log(0.5), np.log(2.0), 3))
+        while True:
+            C = np.zeros((6, 6))
+            C[:3, :3] = lam
+            C[np.arange(3), np.arange(3)] = lam + 2 * mu
+            C[np.arange(3, 6), np.arange(3, 6)] = mu
+            R = rng.standard_normal((6, 6))
+            C = C + strength * (lam + 2 * mu) * 0.5 * (R + R.T) / 6.0
+            if np.linalg.eigvalsh(C).min() >= 0.1 * mu:
+                break
+        out[k, 0] = rho
+        out[k, 1:] = [C[a, b] for a, b in ANISO_UPPER6]
+    return out
+
+
+def anisotropic_from_isotropic(coef_iso: np.ndarray) -> np.ndarray:
+    """(rho, lambda, mu) rows -> (rho, 21 stiffness entries) of the same medium."""
+    out = np.zeros((coef_iso.shape[0], 22))
+    for k, (rho, lam, mu) in enumerate(np.asarray(coef_iso, dtype=float)):
+        C = np.zeros((6, 6))
+        C[:3, :3] = lam
+        C[np.arange(3), np.arange(3)] = lam + 2 * mu
+        C[np.arange(3, 6), np.arange(3, 6)] = mu
+        out[k, 0] = rho
+        out[k, 1:] = [C[a, b] for a, b in ANISO_UPPER6]
+    return out
+
+
+def _stiffness(c21):
+    C = np.zeros((6, 6))
+    for i, (a, b) in enumerate(ANISO_UPPER6):
+        C[a, b] = C[b, a] = c21[i]
+    return C
+
+
+def anisotropic_speed_bound(coef: np.ndarray) -> np.ndarray:
+    """Per element sqrt(lambda_max(C in Mandel form) / rho), an upper bound of
+    every wave speed in every direction (for the time step)."""
+    D = np.diag([1, 1, 1, math.sqrt(2), math.sqrt(2), math.sqrt(2)])
+    return np.array([math.sqrt(np.linalg.eigvalsh(D @ _stiffness(row[1:]) @ D).max() / row[0])
+                     for row in np.asarray(coef, dtype=float)])
+
+
+def anisotropic_plane_wave(x, m, rho, c21, mode: int = 0, t: float = 0.0) -> np.ndarray:
+    """Fields [9, ...] of a plane wave along the integer vector m in a
+    homogeneous anisotropic medium: (c^2, d) the mode-th eigenpair (ascending)
+    of the Christoffel matrix G_ik = C_ijkl m_j m_l / rho for the unit m,
+    v = d f, s = -C : sym(m (x) d) f / c, f = cos(2 pi (m.x) - 2 pi |m| c t)."""
+    m = np.asarray(m, dtype=float)
+    km = np.linalg.norm(m)
+    mh = m / km
+    C = _stiffness(c21)
+    eps_basis = lambda d: np.array([mh[0] * d[0], mh[1] * d[1], mh[2] * d[2], mh[1] * d[2] + mh[2] * d[1],
+                                    mh[0] * d[2] + mh[2] * d[0], mh[0] * d[1] + mh[1] * d[0]])
+    Gam = np.zeros((3, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        sv = C @ eps_basis(e)  # stress (Voigt) of sym(m (x) e_k)
+        S = np.array([[sv[0], sv[5], sv[4]], [sv[5], sv[1], sv[3]], [sv[4], sv[3], sv[2]]])
+        Gam[:, k] = S @ mh / rho
+    w, V = np.linalg.eigh(0.5 * (Gam + Gam.T))
+    c = math.sqrt(w[mode])
+    d = V[:, mode]
+    f = np.cos(2.0 * math.pi * (x @ m) - 2.0 * math.pi * km * c * t)
+    out = np.zeros((9,) + f.shape)
+    for i in range(3):
+        out[i] = d[i] * f
+    sv = -(C @ eps_basis(d)) / c
+    for a in range(6):
+        out[3 + a] = sv[a] * f
+    return out
+
+
 def max_wave_speed(coef: np.ndarray, physics: str) -> float:
     if physics == "acoustic":
         return float(np.max(coef[:, 1]))
+    if physics == "anisotropic":
+        return float(np.max(anisotropic_speed_bound(coef)))
     rho, lam, mu = coef[:, 0], coef[:, 1], coef[:, 2]
     return float(np.max(np.sqrt((lam + 2.0 * mu) / rho)))
 
@@ -398,6 +486,8 @@ def element_wave_speeds(coef: np.ndarray, physics: str) -> np.ndarray:
     coef = np.asarray(coef, dtype=float)
     if physics == "acoustic":
         return coef[:, 1]
+    if physics == "anisotropic":
+        return anisotropic_speed_bound(coef)
     return np.sqrt((coef[:, 1] + 2.0 * coef[:, 2]) / coef[:, 0])
 
 

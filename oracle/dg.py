@@ -319,6 +319,134 @@ class ElasticOracle(_Base):
         return float(e.sum())
 
 
+# Upper triangle of the 6x6 Voigt stiffness, row by row: the order of the 21
+# stiffness coefficients after rho in an anisotropic coefficient row.
+UPPER6 = [(a, b) for a in range(6) for b in range(a, 6)]
+
+
+def stiffness_matrix(c21: np.ndarray) -> np.ndarray:
+    """(..., 21) upper-triangle entries -> (..., 6, 6) symmetric Voigt C."""
+    c21 = np.asarray(c21)
+    C = np.zeros(c21.shape[:-1] + (6, 6), dtype=c21.dtype)
+    for i, (a, b) in enumerate(UPPER6):
+        C[..., a, b] = c21[..., i]
+        C[..., b, a] = c21[..., i]
+    return C
+
+
+class AnisotropicElasticOracle(_Base):
+    """Linear elasticity with a general stiffness per element (an extension
+    the paper names as future work, Sec. 5; the reading is ours):
+
+      rho dv/dt = div s,   ds/dt = C e(v)
+
+    with Voigt s = (s11, s22, s33, s23, s13, s12), engineering strain
+    e = (e11, e22, e33, 2 e23, 2 e13, 2 e12) and C symmetric positive definite
+    (21 coefficients).  Volume terms as in the elastic right-hand side of
+    Sec. 3.2 with C in place of lambda, mu.  Surface: the Riemann solution of
+    a medium whose waves all travel with one impedance Z per side (the
+    acoustic-like solution applied to every traction / velocity component),
+      t* = (Z+ t- + Z- t+)/(Z- + Z+) + Z- Z+/(Z- + Z+) (v+ - v-),
+      v* = (Z- v- + Z+ v+)/(Z- + Z+) + (t+ - t-)/(Z- + Z+),
+    t = s n with the own normal n, entering as the strong-form corrections
+      r_v += LIFT((t* - t-)/rho),   r_s += LIFT(C e(n (x) (v* - v-))),
+    with Z = sqrt(rho max_a C_aa) (for an isotropic C, max C_aa = lambda + 2 mu
+    and Z is the P impedance).  Per face the energy then changes by
+    -(Z- Z+/(Z- + Z+)) |[v]|^2 - |[t]|^2/(Z- + Z+) <= 0 for any Z > 0.
+    Walls: traction-free mirror state (t+ = -t-, v+ = v-, Z+ = Z-); absorbing
+    faces: zero exterior state.
+
+    Coefficients per element: (rho, then the 21 upper-triangle entries of C
+    in the row order of UPPER6).
+    """
+
+    nfields = 9
+    ncoef = 22
+
+    def __init__(self, mesh, coef, absorbing=None):
+        super().__init__(mesh, coef, absorbing)
+        self.rho = self.coef[:, 0]
+        self.C = stiffness_matrix(self.coef[:, 1:])
+        diag = np.stack([self.C[:, a, a] for a in range(6)], axis=1)
+        # largest diagonal stiffness (chosen on the real part, so that a
+        # complex-step perturbation keeps the same entry)
+        self.Z = np.sqrt(self.rho * diag[np.arange(self.K), np.argmax(np.real(diag), axis=1)])
+        w = self.mesh.wall
+        self.Znb = np.where(w, self.Z[:, None], self.Z[self.nb_elem])
+
+    @staticmethod
+    def strain_voigt(grad_v):
+        """grad_v (..., 3 i, 3 j, ...) = d v_i / d x_j -> engineering strain (..., 6, ...)."""
+        g = grad_v
+        return np.stack([g[:, 0, 0], g[:, 1, 1], g[:, 2, 2], g[:, 1, 2] + g[:, 2, 1],
+                         g[:, 0, 2] + g[:, 2, 0], g[:, 0, 1] + g[:, 1, 0]], axis=1)
+
+    def rhs(self, q: np.ndarray) -> np.ndarray:
+        mesh = self.mesh
+        G = mesh.G
+        v = q[:, 0:3]
+        rho = self.rho
+        Dv = self.ref_derivs(v)  # (K, 3 i, 3 l, Np)
+        grad_v = np.einsum("kjl,kiln->kijn", G, Dv)  # d v_i / d x_j
+        DS = self.ref_derivs(q[:, 3:9])[:, TENSOR_INDEX]  # (K, 3 i, 3 j, 3 l, Np)
+        div_s = np.einsum("kjl,kijln->kin", G, DS, optimize=True)
+        r = np.empty_like(q)
+        r[:, 0:3] = (1.0 / rho)[:, None, None] * div_s
+        r[:, 3:9] = np.einsum("kab,kbn->kan", self.C, self.strain_voigt(grad_v))
+        # surface terms
+        n = mesh.normals  # (K, 4, 3)
+        Fm = mesh.ref.Fmask
+        vM = v[:, :, Fm]  # (K, 3, 4, Nfp)
+        SM = ElasticOracle.tensor(q[:, 3:9])[:, :, :, Fm]
+        vP = np.stack([self.nbr_face(v[:, i]) for i in range(3)], axis=1)
+        SP = ElasticOracle.tensor(np.stack([self.nbr_face(q[:, 3 + a]) for a in range(6)], axis=1))
+        tM = np.einsum("kijfx,kfj->kifx", SM, n)
+        tP = np.einsum("kijfx,kfj->kifx", SP, n)
+        wall = mesh.wall[:, None, :, None]
+        vP = np.where(wall, vM, vP)
+        tP = np.where(wall, -tM, tP)
+        absorb = self.absorbing[:, None, :, None]
+        vP = np.where(absorb, 0.0, vP)
+        tP = np.where(absorb, 0.0, tP)
+        Zm = self.Z[:, None, None, None]
+        Zp = self.Znb[:, None, :, None]
+        S = Zm + Zp
+        t_star = (Zp * tM + Zm * tP) / S + (Zm * Zp / S) * (vP - vM)
+        v_star = (Zm * vM + Zp * vP) / S + (tP - tM) / S
+        Fs = mesh.Fscale[:, None, :, None]
+        r[:, 0:3] += self.lift(Fs * (t_star - tM) / rho[:, None, None, None])
+        w_ = Fs * (v_star - vM)  # (K, 3, 4, Nfp)
+        nn = n.transpose(0, 2, 1)[..., None]  # (K, 3, 4, 1)
+        ew = np.stack([nn[:, 0] * w_[:, 0], nn[:, 1] * w_[:, 1], nn[:, 2] * w_[:, 2],
+                       nn[:, 1] * w_[:, 2] + nn[:, 2] * w_[:, 1], nn[:, 0] * w_[:, 2] + nn[:, 2] * w_[:, 0],
+                       nn[:, 0] * w_[:, 1] + nn[:, 1] * w_[:, 0]], axis=1)  # (K, 6, 4, Nfp)
+        r[:, 3:9] += self.lift(np.einsum("kab,kbfx->kafx", self.C, ew))
+        return r
+
+    def _compliance(self):
+        return np.linalg.inv(self.C)
+
+    def energy_density(self, q: np.ndarray) -> np.ndarray:
+        """Per element 1/2 J_k [rho |v|^2 + s^T C^-1 s] with the mass matrix."""
+        e = np.zeros(self.K, dtype=np.result_type(q, self.coef))
+        for i in range(3):
+            e = e + self.rho * self.mass_norm2(q[:, i])
+        Sc = self._compliance()
+        J, M = self.mesh.J, self.ref.M
+        e = e + J * np.einsum("kan,nm,kab,kbm->k", q[:, 3:9], M, Sc, q[:, 3:9])
+        return 0.5 * e
+
+    def energy(self, q: np.ndarray) -> float:
+        return float(np.real(self.energy_density(q).sum()))
+
+    def energy_rate(self, q: np.ndarray) -> float:
+        r = self.rhs(q)
+        J, M = self.mesh.J, self.ref.M
+        e = np.einsum("k,kin,nm,kim->k", J * self.rho, q[:, 0:3], M, r[:, 0:3])
+        e = e + J * np.einsum("kan,nm,kab,kbm->k", q[:, 3:9], M, self._compliance(), r[:, 3:9])
+        return float(e.sum())
+
+
 def make_oracle(physics: str, mesh: MeshGeometry, coef: np.ndarray, absorbing=None):
     """``absorbing``: optional (K, 4) bool mask of unpaired faces that absorb
     instead of reflecting."""
@@ -326,6 +454,8 @@ def make_oracle(physics: str, mesh: MeshGeometry, coef: np.ndarray, absorbing=No
         return AcousticOracle(mesh, coef, absorbing)
     if physics == "elastic":
         return ElasticOracle(mesh, coef, absorbing)
+    if physics == "anisotropic":
+        return AnisotropicElasticOracle(mesh, coef, absorbing)
     raise ValueError(physics)
 
 
