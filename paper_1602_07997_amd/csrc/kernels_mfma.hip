@@ -69,9 +69,15 @@ constexpr int acoustic_waves(int N, int PREC) {
 // staging phases of N = 4, 5 are latency-bound, and the compiler fits them
 // in 78 / 96 registers without spilling when asked (six / five workgroups
 // per compute unit instead of four: 2-8% faster); the FP16 split products
-// would spill, so they keep the default
+// would spill, so they keep the default.  FP32 at N = 6 (six wavefronts per
+// workgroup) and the split products at N = 3 sit just above the 80 / 168
+// register edges of 6 / 3 waves and are held below them, without spilling
 constexpr int acoustic_min_waves(int N, int PREC) {
-  return (N == 4 && PREC == 0) ? 6 : ((N == 4 || N == 5) && PREC != 2 ? 5 : 1);
+  return (N == 4 && PREC == 0) ? 6
+         : ((N == 4 || N == 5) && PREC != 2) ? 5
+         : (N == 6 && PREC == 0) ? 6
+         : (N == 3 && PREC != 0) ? 3
+         : 1;
 }
 
 // Tile configuration CFG = precision (0 FP32, 1 BF16, 2 FP16) + 4 for the

@@ -57,6 +57,14 @@ constexpr int elastic_threads() {
   return (N == 5 && PREC != 0) ? 256 : (((N == 8 || N == 6) && PREC == 0) ? 768 : 512);
 }
 
+// Waves per SIMD the register allocation must allow.  The default follows
+// from the workgroup size (threads / 256); FP32 at N = 5 sits at the edge of
+// 168 VGPRs (3 waves) and is held there: at 2 waves it runs about 30% slower.
+template <int N, int PREC>
+constexpr int elastic_min_waves() {
+  return (N == 5 && PREC == 0) ? 3 : (elastic_threads<N, PREC>() + 255) / 256;
+}
+
 template <int N, int PREC>
 struct EShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
@@ -432,7 +440,12 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     if constexpr (PREC == 0) {
       const float* Dp = a.Dpack + static_cast<int64_t>(mb) * (KP / 4) * 64 + lane;
       constexpr int JS = MB * (KP / 4) * 64;
-      constexpr int NK = KP / 4, PD = NK < 4 ? NK : 4;
+      // prefetch depth 2 at N = 8 keeps the twelve-wavefront workgroup free
+      // of register spills (157 registers; 1% faster than depth 4 with 52
+      // bytes of scratch per lane); at N = 6 depth 4 with 16 bytes of spills
+      // measured 3% faster than the spill-free depth 2
+      constexpr int PDV = N == 8 ? 2 : 4;
+      constexpr int NK = KP / 4, PD = NK < PDV ? NK : PDV;
       using R = Ring<float, PD, 3>;
       auto load = [&](R& r, int g) {
 #pragma unroll
@@ -601,13 +614,13 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__((elastic_threads<N, PREC>()))
+__global__ void __launch_bounds__((elastic_threads<N, PREC>()), (elastic_min_waves<N, PREC>()))
 dg_step_mfma_elastic(StepArgs a) {
   step_mfma_elastic_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
 }
 
 template <int N, int PREC>
-__global__ void __launch_bounds__((elastic_threads<N, PREC>()))
+__global__ void __launch_bounds__((elastic_threads<N, PREC>()), (elastic_min_waves<N, PREC>()))
 dg_step_mfma_elastic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
