@@ -64,9 +64,13 @@ def algorithmic_model(physics: str, N: int):
     bytes = 4 * [5 NF Np (q read+write, r^{m-1}, r^{m-2} read, r^m write)
                  + 2 * 4 NT Nfp (neighbour traces read, own traces written)
                  + 9 (inverse Jacobian) + c (own + neighbour coefficients)
-                 + 4 (packed face connectivity)],  c = 6 acoustic, 11 elastic
-    flops: acoustic 12 Np^2 + 32 Np Nfp + 64 Nfp + 58 Np,
-           elastic  36 Np^2 + 72 Np Nfp + 240 Nfp + 174 Np.
+                 + 4 (packed face connectivity)],
+            c = 6 acoustic, 11 elastic, 27 anisotropic (21 stiffness
+            entries, 1/rho, Z and the four neighbour impedances)
+    flops: acoustic    12 Np^2 + 32 Np Nfp + 64 Nfp + 58 Np,
+           elastic     36 Np^2 + 72 Np Nfp + 240 Nfp + 174 Np,
+           anisotropic the elastic count + 72 Np (the 6x6 stiffness product
+                       at every node).
     """
     Np = (N + 1) * (N + 2) * (N + 3) // 6
     Nfp = (N + 1) * (N + 2) // 2
@@ -76,6 +80,9 @@ def algorithmic_model(physics: str, N: int):
     else:
         NF, NT, c = 9, 6, 11
         flops = 36 * Np * Np + 72 * Np * Nfp + 60 * 4 * Nfp + 54 * Np + 120 * Np
+        if physics == "anisotropic":
+            c = 27
+            flops += 72 * Np
     nbytes = 4 * (5 * NF * Np + 2 * 4 * NT * Nfp + 9 + c + 4)
     return nbytes, flops
 
@@ -151,6 +158,8 @@ def workload(physics: str, N: int, scale: float = 1.0):
     mesh = di.kuhn_box(n, jitter=0.1, seed=0)
     if physics == "acoustic":
         coef = di.acoustic_two_layer(mesh)
+    elif physics == "anisotropic":
+        coef = di.anisotropic_random(mesh, 1)
     else:
         coef = di.elastic_loguniform(mesh, 1)
     coef = coef.astype(np.float32).astype(np.float64)
@@ -492,15 +501,16 @@ def main_sweep(args, log, degrees):
 
 def _cpu_oracle_step(task):
     """One worker of the parallel CPU baseline: build the workload and the
-    FP64 oracle (untimed, one BLAS thread), wait for every worker, then time
-    one AB3 step (after one untimed step).  Returns (nodes, start, end, cpu)
-    with wall-clock stamps."""
+    FP64 oracle (untimed, one BLAS thread), take one untimed step, wait for
+    every worker, then step until `window` seconds have passed since the
+    common start.  Returns (nodes per step, steps done, start, end of the last
+    step, cpu seconds) with wall-clock stamps."""
     from threadpoolctl import threadpool_limits
 
     from oracle.dg import AB3Stepper, make_oracle
     from oracle.mesh import build_mesh
 
-    physics, N, barrier = task
+    physics, N, barrier, window = task
     with threadpool_limits(1):
         n, mesh, coef = workload(physics, N)
         geo = build_mesh(N, mesh.elem_xyz, mesh.elem_topo, None)
@@ -510,16 +520,20 @@ def _cpu_oracle_step(task):
         st.step(1, dt)
         barrier.wait()
         c0, t0 = time.process_time(), time.time()
-        st.step(1, dt)
-        t1 = time.time()
-        return geo.K * geo.ref.Np, t0, t1, time.process_time() - c0
+        done, t1 = 0, t0
+        while done == 0 or t1 - t0 < window:
+            st.step(1, dt)
+            done += 1
+            t1 = time.time()
+        return geo.K * geo.ref.Np, done, t0, t1, time.process_time() - c0
 
 
-def run_cpu_baseline_parallel(physics_list, degrees, log):
+def run_cpu_baseline_parallel(physics_list, degrees, log, window=12.0):
     """The FP64 oracle on every core: one process per (physics, degree) mesh,
-    each on one BLAS thread, all stepping at once after a barrier; value =
-    node updates of one AB3 step on every mesh / wall time from the first
-    start to the last end.  Must run before this process initialises the GPU
+    each on one BLAS thread, all started together after a barrier, each
+    stepping its mesh until `window` seconds have passed (at least one step);
+    value = sum over the processes of their node updates per second (they
+    run concurrently).  Must run before this process initialises the GPU
     (the workers are started as new interpreters)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
@@ -529,20 +543,21 @@ def run_cpu_baseline_parallel(physics_list, degrees, log):
     with ctx.Manager() as mgr:
         barrier = mgr.Barrier(len(tasks))
         with ProcessPoolExecutor(max_workers=len(tasks), mp_context=ctx) as ex:
-            res = list(ex.map(_cpu_oracle_step, [(ph, N, barrier) for ph, N in tasks]))
-    nodes = sum(r[0] for r in res)
-    wall = max(r[2] for r in res) - min(r[1] for r in res)
-    cpu = sum(r[3] for r in res)
-    log(f"  cpu oracle, {len(tasks)} processes: {nodes / wall:.3e} node-updates/s, {cpu / wall:.1f} cores busy")
+            res = list(ex.map(_cpu_oracle_step, [(ph, N, barrier, window) for ph, N in tasks]))
+    rate = sum(r[0] * r[1] / (r[3] - r[2]) for r in res)
+    wall = max(r[3] for r in res) - min(r[2] for r in res)
+    cpu = sum(r[4] for r in res)
+    steps = ", ".join(f"{ph[0]}N{N}:{r[1]}" for (ph, N), r in zip(tasks, res))
+    log(f"  cpu oracle, {len(tasks)} processes: {rate:.3e} node-updates/s, {cpu / wall:.1f} cores busy")
     return {
-        "value": nodes / wall,
+        "value": rate,
         "unit": "node-updates/s",
         "cores": len(tasks),
         "kind": "oracle",
-        "sample": f"one FP64 oracle AB3 step (after one untimed step) on each of the {len(tasks)} benchmark meshes "
-        f"({', '.join(ph[0] + 'N' + str(N) for ph, N in tasks)}, ~2M nodes each), one process per mesh on one "
-        f"BLAS thread, all started together after a barrier; {wall:.1f} s wall, {cpu / wall:.1f} cores busy on "
-        f"average (host cpu_count {os.cpu_count()})",
+        "sample": f"FP64 oracle AB3 steps on each of the {len(tasks)} benchmark meshes (~2M nodes each), one "
+        f"process per mesh on one BLAS thread, all started together after a barrier and one untimed step, each "
+        f"stepping for {window:.0f} s (steps done: {steps}); value = sum of the processes' node-update rates; "
+        f"{wall:.1f} s wall, {cpu / wall:.1f} cores busy on average (host cpu_count {os.cpu_count()})",
     }
 
 
@@ -777,7 +792,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", choices=["sweep", "acoustic", "elastic", "batched", "adjoint"], default="sweep")
+    ap.add_argument("--config", choices=["sweep", "acoustic", "elastic", "anisotropic", "batched", "adjoint"],
+                    default="sweep")
     ap.add_argument("--degrees", type=str, default="1-8")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument(

@@ -274,23 +274,28 @@ def anisotropic_random(mesh: TetMesh, seed: int, strength: float = 0.35) -> np.n
     """Per element (rho, 21 upper-triangle entries of a symmetric positive
     definite Voigt stiffness C): an isotropic stiffness with lambda, mu
     log-uniform on [1/2, 2] plus a seeded symmetric perturbation of relative
-    size `strength`, redrawn until C is positive definite with its smallest
-    eigenvalue at least a tenth of mu; rho log-uniform on [1/2, 2]."""
+    size `strength`, redrawn (for the elements that need it, in rounds) until
+    C is positive definite with its smallest eigenvalue at least a tenth of
+    mu; rho log-uniform on [1/2, 2]."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    rho, lam, mu = np.exp(rng.uniform(np.log(0.5), np.log(2.0), (mesh.K, 3))).T
+    base = np.zeros((mesh.K, 6, 6))
+    base[:, :3, :3] = lam[:, None, None]
+    d = np.arange(3)
+    base[:, d, d] = (lam + 2 * mu)[:, None]
+    base[:, d + 3, d + 3] = mu[:, None]
+    C = np.empty_like(base)
+    todo = np.arange(mesh.K)
+    while todo.size:
+        R = rng.standard_normal((todo.size, 6, 6))
+        Ct = base[todo] + (strength * (lam + 2 * mu)[todo] * 0.5 / 6.0)[:, None, None] * (R + np.swapaxes(R, 1, 2))
+        ok = np.linalg.eigvalsh(Ct).min(axis=1) >= 0.1 * mu[todo]
+        C[todo[ok]] = Ct[ok]
+        todo = todo[~ok]
     out = np.zeros((mesh.K, 22))
-    for k in range(mesh.K):
-        rho, lam, mu = np.exp(rng.uniform(np.log(0.5), np.log(2.0), 3))
-        while True:
-            C = np.zeros((6, 6))
-            C[:3, :3] = lam
-            C[np.arange(3), np.arange(3)] = lam + 2 * mu
-            C[np.arange(3, 6), np.arange(3, 6)] = mu
-            R = rng.standard_normal((6, 6))
-            C = C + strength * (lam + 2 * mu) * 0.5 * (R + R.T) / 6.0
-            if np.linalg.eigvalsh(C).min() >= 0.1 * mu:
-                break
-        out[k, 0] = rho
-        out[k, 1:] = [C[a, b] for a, b in ANISO_UPPER6]
+    out[:, 0] = rho
+    for i, (a, b) in enumerate(ANISO_UPPER6):
+        out[:, 1 + i] = C[:, a, b]
     return out
 
 

@@ -11,14 +11,18 @@
  *   - isotropic elastic velocity-stress system with the exact-Riemann upwind
  *     flux of Sec. 2.1 and the elastic right-hand side of Sec. 3.2 (the mu
  *     term read as 2 mu sym(grad v), as the PDE of Sec. 2.1 states);
+ *   - anisotropic elastic velocity-stress system (a general symmetric
+ *     positive definite Voigt stiffness per element; Sec. 5 names
+ *     anisotropic media as future work), see DG_ANISOTROPIC below;
  *   - third-order Adams-Bashforth time stepping, eq. (4), started with one
  *     forward-Euler and one two-step Adams-Bashforth step.
  * The per-step work (volume term, face traces and upwind flux, merged LIFT,
  * AB3 update) runs in hand-written HIP kernels on one GPU.
  *
  * Conventions
- *   physics   DG_ACOUSTIC (fields p, v1, v2, v3) or DG_ELASTIC (fields v1,
- *             v2, v3, s11, s22, s33, s23, s13, s12).
+ *   physics   DG_ACOUSTIC (fields p, v1, v2, v3), DG_ELASTIC or
+ *             DG_ANISOTROPIC (fields v1, v2, v3, s11, s22, s33, s23, s13,
+ *             s12).
  *   order     polynomial degree N, 1 <= N <= 8; Np = (N+1)(N+2)(N+3)/6 nodes
  *             per element, Nfp = (N+1)(N+2)/2 nodes per face.
  *   nodes     warp-and-blend nodes on the reference tetrahedron
@@ -77,6 +81,17 @@ typedef int dg_status;
 
 #define DG_ACOUSTIC 0
 #define DG_ELASTIC 1
+/* Anisotropic elasticity (Sec. 5 lists it as future work; the reading is
+ * this library's): rho dv/dt = div s, ds/dt = C e(v), s and the engineering
+ * strain e in Voigt order (11, 22, 33, 23, 13, 12), C symmetric positive
+ * definite.  Volume terms as the elastic right-hand side of Sec. 3.2 with C
+ * in place of lambda, mu.  Upwind flux: the Riemann solution of media whose
+ * waves all travel with one impedance per side, Z = sqrt(rho max_a C_aa)
+ * (the P impedance for an isotropic C), applied to every traction and
+ * velocity component; it dissipates (Z- Z+/(Z- + Z+)) |[v]|^2 + |[t]|^2 /
+ * (Z- + Z+) per unit face area.  Walls and absorbing faces as DG_ELASTIC.
+ * Only DG_VARIANT_VALU is built for it; misfits are not.                    */
+#define DG_ANISOTROPIC 2
 
 typedef struct dg_solver dg_solver;
 
@@ -86,7 +101,8 @@ int dg_abi_version(void);
 /* Message of the last failing call on this thread ("" if none). */
 const char* dg_last_error(void);
 
-/* Number of fields for a physics (4 acoustic, 9 elastic), or -1. */
+/* Number of fields for a physics (4 acoustic, 9 elastic and anisotropic),
+ * or -1. */
 int dg_num_fields(int physics);
 
 /* ------------------------------------------------------------------------ */
@@ -178,7 +194,8 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
  *                         (acoustic only), a tile-shape candidate for
  *                         dg_autotune (the paper tunes its elements per
  *                         block per degree, Sec. 3.2 and Table 5).
- * The VALU and MFMA variants are built for both physics and N = 1..8.
+ * The VALU and MFMA variants are built for the acoustic and elastic physics
+ * and N = 1..8; the anisotropic physics has DG_VARIANT_VALU only.
  * Fields, r and the update stay FP32 in every variant.  Returns
  * DG_E_UNSUPPORTED for a combination that is not built.                    */
 #define DG_VARIANT_VALU 0
@@ -198,11 +215,15 @@ dg_status dg_node_coordinates(dg_solver* s, double* xyz);
 
 /* Material coefficients per element, device float32: acoustic [K][2]
  * (rho, c); elastic [K][3] (rho, lambda, mu), all > 0 (mu > 0 is required by
- * the elastic flux).  Validated on the device (synchronises); derived
- * per-face impedances of the neighbours are computed on the device.  Must
- * precede dg_step/dg_rhs.  Errors: DG_E_ARG (null, or a value that is not
- * positive and finite: the solver then has no coefficients until the next
- * successful call), DG_E_HIP.                                               */
+ * the elastic flux); anisotropic [K][22] (rho > 0, then the 21 entries C_ab,
+ * a <= b, of the upper triangle of the Voigt stiffness row by row: C_00 ..
+ * C_05, C_11 .. C_15, ..., C_55; C positive definite).  Validated on the
+ * device (synchronises); derived per-face impedances of the neighbours are
+ * computed on the device.  Must precede dg_step/dg_rhs.  Errors: DG_E_ARG
+ * (null, a value that is not positive and finite, or an anisotropic
+ * stiffness that is not finite and positive definite in double precision:
+ * the solver then has no coefficients until the next successful call),
+ * DG_E_HIP.                                                                 */
 dg_status dg_set_coefficients(dg_solver* s, const float* coef);
 
 /* Kind of each unpaired face, host int32 [K][4]: DG_BC_REFLECT (the default
@@ -413,7 +434,7 @@ typedef struct dg_misfit dg_misfit;
  * solver must outlive the misfit; the misfit uses its own state buffers (the
  * solver's fields are not touched).  Errors: DG_E_ARG (bad sizes, a point
  * outside the mesh, bad workspace), DG_E_SHAPE (workspace too small),
- * DG_E_HIP.                                                                 */
+ * DG_E_UNSUPPORTED (an anisotropic solver), DG_E_HIP.                       */
 dg_status dg_misfit_create(dg_solver* s, int64_t nsteps, double dt, int checkpoint_every, int nsrc,
                            const double* src_xyz, const double* wavelet, int nrec, const double* rec_xyz,
                            void* workspace, size_t workspace_bytes, dg_misfit** out);

@@ -29,6 +29,13 @@ Walls (unpaired faces; the paper is silent): mirror ghost state with the
 element's own coefficients -- acoustic p^+ = p^-, v_n^+ = -v_n^- (rigid wall);
 elastic v^+ = v^-, (s n)^+ = -(s n)^- (traction-free).
 
+Anisotropic elastic system (Sec. 5 names anisotropic media as future work;
+the reading is ours), the elastic fields with a general symmetric positive
+definite Voigt stiffness C per element: volume terms as above with C e(v) in
+place of lambda div v I + 2 mu sym(grad v), and the Riemann solution of a
+medium whose waves all travel with one impedance Z = sqrt(rho max_a C_aa)
+per side (see AnisotropicElasticOracle).
+
 Absorbing faces (an optional subset of the unpaired faces; Sec. 5 names
 artificial boundary conditions as future work, so the reading is ours): the
 exterior state is zero, with the element's own coefficients.  The upwind

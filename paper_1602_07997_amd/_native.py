@@ -23,6 +23,7 @@ DG_E_UNSUPPORTED = -6
 DG_E_UNSTABLE = -7
 DG_ACOUSTIC = 0
 DG_ELASTIC = 1
+DG_ANISOTROPIC = 2
 DG_VARIANT_VALU = 0
 DG_VARIANT_MFMA = 1
 DG_VARIANT_MFMA_BF16 = 2

@@ -53,6 +53,17 @@ struct HostTables {
 HostTables make_tables(int physics, const dgw::RefElement* ref) {
   HostTables t;
   const int order = ref->N, Np = ref->Np, Nfp = ref->Nfp;
+  t.DT.resize(3 * static_cast<size_t>(Np) * Np);
+  t.LT.resize(static_cast<size_t>(4) * Nfp * Np);
+  for (int j = 0; j < 3; ++j)
+    for (int n = 0; n < Np; ++n)
+      for (int mm = 0; mm < Np; ++mm)
+        t.DT[(static_cast<size_t>(j) * Np + mm) * Np + n] =
+            static_cast<float>(ref->D[(static_cast<size_t>(j) * Np + n) * Np + mm]);
+  for (int n = 0; n < Np; ++n)
+    for (int fm = 0; fm < 4 * Nfp; ++fm)
+      t.LT[static_cast<size_t>(fm) * Np + n] = static_cast<float>(ref->lift[static_cast<size_t>(n) * 4 * Nfp + fm]);
+  if (physics == DG_ANISOTROPIC) return t;  // node-per-thread kernel only: no MFMA layouts
   const dgw::MfmaPacking p32 = dgw::mfma_packing(physics, order, dgw::kVariantMfma);
   const dgw::ColMap c32 = dgw::face_block_columns(Nfp, p32.KF);
   for (int j = 0; j < 3; ++j)
@@ -69,16 +80,6 @@ HostTables make_tables(int physics, const dgw::RefElement* ref) {
     dgw::pack_split16(ref->lift.data(), Np, 4 * Nfp, p16.MB, p16.KL, kw, v == 0, t.L16[v][0], t.L16[v][1],
                       p16.KF > 0 ? &c16 : nullptr);
   }
-  t.DT.resize(3 * static_cast<size_t>(Np) * Np);
-  t.LT.resize(static_cast<size_t>(4) * Nfp * Np);
-  for (int j = 0; j < 3; ++j)
-    for (int n = 0; n < Np; ++n)
-      for (int mm = 0; mm < Np; ++mm)
-        t.DT[(static_cast<size_t>(j) * Np + mm) * Np + n] =
-            static_cast<float>(ref->D[(static_cast<size_t>(j) * Np + n) * Np + mm]);
-  for (int n = 0; n < Np; ++n)
-    for (int fm = 0; fm < 4 * Nfp; ++fm)
-      t.LT[static_cast<size_t>(fm) * Np + n] = static_cast<float>(ref->lift[static_cast<size_t>(n) * 4 * Nfp + fm]);
   return t;
 }
 
@@ -91,7 +92,7 @@ void set_sizes(dg_solver* s, int physics, int order, int64_t K, const dgw::RefEl
   s->NF = dg_num_fields(physics);
   s->NT = dgw::num_traces(physics);
   s->CB = dgw::coef_block(physics);
-  s->ncoef = physics == DG_ACOUSTIC ? 2 : 3;
+  s->ncoef = dgw::num_coefficients(physics);
   s->K = K;
 }
 
@@ -129,7 +130,7 @@ void layout(dg_solver* s, const HostTables& t, const dgw::RefElement* ref, dgw::
 }
 
 dg_status check_create_args(int physics, int order, int64_t K, const dgw::RefElement** ref) {
-  if (physics != DG_ACOUSTIC && physics != DG_ELASTIC) {
+  if (physics != DG_ACOUSTIC && physics != DG_ELASTIC && physics != DG_ANISOTROPIC) {
     set_error("unknown physics");
     return DG_E_ARG;
   }
@@ -199,7 +200,7 @@ const char* dg_last_error(void) { return dgw::last_error(); }
 
 int dg_num_fields(int physics) {
   if (physics == DG_ACOUSTIC) return 4;
-  if (physics == DG_ELASTIC) return 9;
+  if (physics == DG_ELASTIC || physics == DG_ANISOTROPIC) return 9;
   return -1;
 }
 
@@ -506,12 +507,18 @@ dg_status dg_set_coefficients(dg_solver* s, const float* coef) {
                         s->stream));
   // validated on the device (set-up call: one synchronisation, one int back)
   int bad = -1;
-  DG_HIP(dgw::launch_first_nonpositive(n, s->coef, s->flag, s->stream));
+  if (s->physics == DG_ANISOTROPIC)
+    DG_HIP(dgw::launch_first_bad_stiffness(s->K, s->coef, s->flag, s->stream));
+  else
+    DG_HIP(dgw::launch_first_nonpositive(n, s->coef, s->flag, s->stream));
   DG_HIP(hipMemcpyAsync(&bad, s->flag, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   DG_HIP(hipStreamSynchronize(s->stream));
   if (bad >= 0) {
     std::ostringstream os;
-    os << "coefficient " << bad % s->ncoef << " of element " << bad / s->ncoef << " is not positive and finite";
+    if (s->physics == DG_ANISOTROPIC)
+      os << "element " << bad << ": density not positive and finite, or stiffness not finite and positive definite";
+    else
+      os << "coefficient " << bad % s->ncoef << " of element " << bad / s->ncoef << " is not positive and finite";
     set_error(os.str());
     s->have_coef = false;
     return DG_E_ARG;

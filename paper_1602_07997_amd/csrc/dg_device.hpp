@@ -24,6 +24,14 @@ template <>
 struct Phys<1> {  // elastic: v1, v2, v3, s11, s22, s33, s23, s13, s12
   static constexpr int NF = 9, NT = 6, NAUX = 9, CB = 16;
 };
+template <>
+struct Phys<2> {  // anisotropic elastic: the elastic fields, a general stiffness per element
+  static constexpr int NF = 9, NT = 6, NAUX = 9, CB = 32;
+};
+
+// Offset of the Voigt stiffness entry C_ab (a <= b) among the 21 entries of
+// the upper triangle stored row by row.
+__host__ __device__ __forceinline__ constexpr int upper6(int a, int b) { return a * 6 - a * (a - 1) / 2 + (b - a); }
 
 constexpr int kThreads = 256;
 
@@ -58,6 +66,11 @@ __device__ __forceinline__ void face_normal(const float* G, int f, float n[3], f
 //             alpha = [[p]] - Z+ [[v.n]],  Pp = fp * alpha,  Pv = fv * alpha,
 //             fp = Fscale rho c^2 k_c, fv = -Fscale c k_c, k_c = 2/(Z- + Z+)
 //   elastic:  n0 n1 n2 Zp+ Zs+ Fscale k_p k_s wall 0 0 0
+//   anisotropic: n0 n1 n2 at av bt bv wall   with S = Z- + Z+ and, at a face
+//             node with full jumps [v] = v+ - v-, [t] = t+ - t-,
+//             velocity lift  at [t] + av [v],  at = Fscale Z-/(S rho),
+//             av = Fscale Z- Z+/(S rho);  strain lift  bt [t] + bv [v],
+//             bt = Fscale/S,  bv = Fscale Z+/S
 // (wall = 1 for an unpaired face: the mirror ghost state applies there).
 template <int PHYS>
 struct FaceRec;
@@ -68,6 +81,10 @@ struct FaceRec<0> {
 template <>
 struct FaceRec<1> {
   static constexpr int W = 12, WALL = 8;
+};
+template <>
+struct FaceRec<2> {
+  static constexpr int W = 8, WALL = 7;
 };
 
 template <int PHYS>
@@ -88,6 +105,16 @@ __device__ __forceinline__ void face_record(const float* __restrict__ G, const f
     out[5] = -fs * cf[3] * kc;
     out[6] = wall ? 1.0f : 0.0f;
     out[7] = 0.0f;
+  } else if constexpr (PHYS == 2) {
+    const float ZM = cf[22];
+    const float ZP = wall ? ZM : cf[24 + f];
+    const float iS = __builtin_amdgcn_rcpf(ZM + ZP);
+    const float irho = cf[21];
+    out[3] = fs * ZM * iS * irho;
+    out[4] = fs * ZM * ZP * iS * irho;
+    out[5] = fs * iS;
+    out[6] = fs * ZP * iS;
+    out[7] = wall ? 1.0f : 0.0f;
   } else {
     const float ZpM = cf[3], ZsM = cf[4];
     const float ZpP = wall ? ZpM : cf[8 + f];

@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "dg_device.hpp"
 #include "kernels.hpp"
@@ -44,14 +45,15 @@ struct Tile {
   static constexpr int NP = Deg<N>::NP;
   static constexpr int raw = 256 / NP;
   static constexpr int KT =
-      (N == 8 && PHYS == 0) ? 3 : (PHYS == 1 && N <= 2 ? (N == 1 ? 32 : 16) : (raw < 1 ? 1 : raw));
+      (N == 8 && PHYS == 0) ? 3 : (PHYS != 0 && N <= 2 ? (N == 1 ? 32 : 16) : (raw < 1 ? 1 : raw));
 };
 
 // Number of lifted scalars per face node: acoustic (Fscale*penalty for p,
 // scalar velocity penalty along n), elastic (k_p a_p, k_s a_s, vector a_s),
-// each times Fscale.  The normal and the per-face constants are applied after
-// the lift, so the merged LIFT product runs on 2 (acoustic) / 5 (elastic)
-// columns per element instead of 4 / 9.
+// anisotropic (the velocity correction vector, and the vector w whose strain
+// n (x) w the stiffness takes), each times Fscale.  The normal and the
+// per-face / per-element constants are applied after the lift, so the merged
+// LIFT product runs on 2 / 5 / 6 columns per element instead of 4 / 9 / 9.
 template <int PHYS>
 struct LiftCols;
 template <>
@@ -61,6 +63,10 @@ struct LiftCols<0> {
 template <>
 struct LiftCols<1> {
   static constexpr int NL = 5;
+};
+template <>
+struct LiftCols<2> {
+  static constexpr int NL = 6;
 };
 
 template <int N, int PHYS>
@@ -313,19 +319,30 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
         vP[ii] = wall ? gw * vM[ii] : nbt[t][ii];
         tP[ii] = wall ? -gw * tM[ii] : -nbt[t][3 + ii];  // neighbour stored s n with its own normal
       }
-      const float ZpP = rec[3], ZsP = rec[4], fs = rec[5];
-      float jv[3], jt[3];
+      if constexpr (PHYS == 2) {
+        // one-impedance Riemann solution per side: the velocity correction
+        // (t* - t-)/rho and the vector v* - v-, both times Fscale
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        jv[ii] = 0.5f * (vP[ii] - vM[ii]);
-        jt[ii] = 0.5f * (tP[ii] - tM[ii]);
+        for (int ii = 0; ii < 3; ++ii) {
+          const float jv = vP[ii] - vM[ii], jt = tP[ii] - tM[ii];
+          lf[ii * NFN] = rec[3] * jt + rec[4] * jv;
+          lf[(3 + ii) * NFN] = rec[5] * jt + rec[6] * jv;
+        }
+      } else {
+        const float ZpP = rec[3], ZsP = rec[4], fs = rec[5];
+        float jv[3], jt[3];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          jv[ii] = 0.5f * (vP[ii] - vM[ii]);
+          jt[ii] = 0.5f * (tP[ii] - tM[ii]);
+        }
+        const float jvn = jv[0] * nrm[0] + jv[1] * nrm[1] + jv[2] * nrm[2];
+        const float jsnn = jt[0] * nrm[0] + jt[1] * nrm[1] + jt[2] * nrm[2];
+        lf[0] = fs * rec[6] * (jsnn + ZpP * jvn);    // k_p alpha_p
+        lf[NFN] = fs * rec[7] * (jsnn + ZsP * jvn);  // k_s alpha_s
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) lf[(2 + ii) * NFN] = fs * (jt[ii] + ZsP * jv[ii]);  // vector alpha_s
       }
-      const float jvn = jv[0] * nrm[0] + jv[1] * nrm[1] + jv[2] * nrm[2];
-      const float jsnn = jt[0] * nrm[0] + jt[1] * nrm[1] + jt[2] * nrm[2];
-      lf[0] = fs * rec[6] * (jsnn + ZpP * jvn);    // k_p alpha_p
-      lf[NFN] = fs * rec[7] * (jsnn + ZsP * jvn);  // k_s alpha_s
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) lf[(2 + ii) * NFN] = fs * (jt[ii] + ZsP * jv[ii]);  // vector alpha_s
     }
   }
   __syncthreads();
@@ -400,48 +417,76 @@ __device__ __forceinline__ void step_valu_tile(const StepArgs& a, int64_t tile) 
           }
         }
       }
-      const float lam = cf[0], mu = cf[1], irho = cf[2], cp = cf[5], cs = cf[6];
       float gv[3][3];  // d v_i / d x_j = sum_l g_jl D_l v_i
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj)
           gv[ii][jj] = G[3 * jj + 0] * Dv[ii][0] + G[3 * jj + 1] * Dv[ii][1] + G[3 * jj + 2] * Dv[ii][2];
-      const float divv = gv[0][0] + gv[1][1] + gv[2][2];
-      // surface: velocity  sum_f [n (cp L1 - cs L2) + ks cs L3]
-      //          stress    sum_f [lam L1 I + 2 mu n n^T (L1 - L2) + mu ks (n L3^T + L3 n^T)]
-      float sv[3] = {0.f, 0.f, 0.f};
-      float ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      float l1sum = 0.f;
+      if constexpr (PHYS == 2) {
+        // velocity: (1/rho) div s + the lifted corrections (already over rho);
+        // stress: C times the engineering strain of grad v plus, per face,
+        // that of n (x) w for the lifted vector w
+        const float irho = cf[21];
+        float ev[6] = {gv[0][0], gv[1][1], gv[2][2], gv[1][2] + gv[2][1], gv[0][2] + gv[2][0], gv[0][1] + gv[1][0]};
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const float ks = fr[f * FW + 7];
-        const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
-        const float nf[3] = {n0, n1, n2};
-        const float a1 = cp * L[f][0] - cs * L[f][1];
-        const float b2 = 2.0f * mu * (L[f][0] - L[f][1]);
-        const float c3 = mu * ks;
-        l1sum += L[f][0];
+        for (int ii = 0; ii < 3; ++ii) r[ii] = irho * dS[ii] + (L[0][ii] + L[1][ii] + L[2][ii] + L[3][ii]);
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) sv[ii] += nf[ii] * a1 + ks * cs * L[f][2 + ii];
+        for (int f = 0; f < 4; ++f) {
+          const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
+          const float w0 = L[f][3], w1 = L[f][4], w2 = L[f][5];
+          ev[0] += n0 * w0;
+          ev[1] += n1 * w1;
+          ev[2] += n2 * w2;
+          ev[3] += n1 * w2 + n2 * w1;
+          ev[4] += n0 * w2 + n2 * w0;
+          ev[5] += n0 * w1 + n1 * w0;
+        }
+#pragma unroll
+        for (int va = 0; va < 6; ++va) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int vb = 0; vb < 6; ++vb) acc += cf[va <= vb ? upper6(va, vb) : upper6(vb, va)] * ev[vb];
+          r[3 + va] = acc;
+        }
+      } else {
+        const float lam = cf[0], mu = cf[1], irho = cf[2], cp = cf[5], cs = cf[6];
+        const float divv = gv[0][0] + gv[1][1] + gv[2][2];
+        // surface: velocity  sum_f [n (cp L1 - cs L2) + ks cs L3]
+        //          stress    sum_f [lam L1 I + 2 mu n n^T (L1 - L2) + mu ks (n L3^T + L3 n^T)]
+        float sv[3] = {0.f, 0.f, 0.f};
+        float ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float l1sum = 0.f;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const float ks = fr[f * FW + 7];
+          const float n0 = fr[f * FW + 0], n1 = fr[f * FW + 1], n2 = fr[f * FW + 2];
+          const float nf[3] = {n0, n1, n2};
+          const float a1 = cp * L[f][0] - cs * L[f][1];
+          const float b2 = 2.0f * mu * (L[f][0] - L[f][1]);
+          const float c3 = mu * ks;
+          l1sum += L[f][0];
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) sv[ii] += nf[ii] * a1 + ks * cs * L[f][2 + ii];
+          const int vi[6] = {0, 1, 2, 1, 0, 0};
+          const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+          for (int v = 0; v < 6; ++v) {
+            const int ii = vi[v], jj = vj[v];
+            ss[v] += b2 * nf[ii] * nf[jj] + c3 * (nf[ii] * L[f][2 + jj] + L[f][2 + ii] * nf[jj]);
+          }
+        }
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) r[ii] = irho * dS[ii] + sv[ii];
         const int vi[6] = {0, 1, 2, 1, 0, 0};
         const int vj[6] = {0, 1, 2, 2, 2, 1};
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
           const int ii = vi[v], jj = vj[v];
-          ss[v] += b2 * nf[ii] * nf[jj] + c3 * (nf[ii] * L[f][2 + jj] + L[f][2 + ii] * nf[jj]);
+          float val = mu * (gv[ii][jj] + gv[jj][ii]) + ss[v];
+          if (ii == jj) val += lam * (divv + l1sum);
+          r[3 + v] = val;
         }
-      }
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) r[ii] = irho * dS[ii] + sv[ii];
-      const int vi[6] = {0, 1, 2, 1, 0, 0};
-      const int vj[6] = {0, 1, 2, 2, 2, 1};
-#pragma unroll
-      for (int v = 0; v < 6; ++v) {
-        const int ii = vi[v], jj = vj[v];
-        float val = mu * (gv[ii][jj] + gv[jj][ii]) + ss[v];
-        if (ii == jj) val += lam * (divv + l1sum);
-        r[3 + v] = val;
       }
     }
     const int64_t base = (e0 + e) * NF * NP + n;
@@ -578,10 +623,21 @@ dg_trace_comb_kernel(int64_t nlist, const int32_t* __restrict__ list, const floa
   }
 }
 
+// Impedance of an anisotropic element (rho, then the 21 upper-triangle
+// stiffness entries): sqrt(rho * the largest diagonal stiffness), the P
+// impedance when the stiffness is isotropic.
+__device__ __forceinline__ float aniso_impedance(const float* __restrict__ c) {
+  float m = c[1 + upper6(0, 0)];
+#pragma unroll
+  for (int d = 1; d < 6; ++d) m = fmaxf(m, c[1 + upper6(d, d)]);
+  return sqrtf(c[0] * m);
+}
+
 // Derived coefficients per element, including the neighbours' impedances on
 // each face (own values on walls).
-//   acoustic cf = [rho c^2, 1/rho, Z, c, Z+_0..3]
-//   elastic  cf = [lambda, mu, 1/rho, Zp, Zs, cp, cs, 0, Zp+_0..3, Zs+_0..3]
+//   acoustic    cf = [rho c^2, 1/rho, Z, c, Z+_0..3]
+//   elastic     cf = [lambda, mu, 1/rho, Zp, Zs, cp, cs, 0, Zp+_0..3, Zs+_0..3]
+//   anisotropic cf = [C (21 upper-triangle entries), 1/rho, Z, 0, Z+_0..3, 0 0 0 0]
 template <int PHYS>
 __global__ void __launch_bounds__(kThreads)
 dg_coef_kernel(int64_t K, const float* __restrict__ coef, const int32_t* __restrict__ conn,
@@ -600,6 +656,19 @@ dg_coef_kernel(int64_t K, const float* __restrict__ coef, const int32_t* __restr
       int64_t kn = ((w & 7) == 7) ? k : static_cast<int64_t>(w >> 5);
       o[4 + f] = coef[2 * kn] * coef[2 * kn + 1];
     }
+  } else if constexpr (PHYS == 2) {
+    const float* c = coef + 22 * k;
+    float* o = cf + 32 * k;
+    for (int i = 0; i < 21; ++i) o[i] = c[1 + i];
+    o[21] = 1.0f / c[0];
+    o[22] = aniso_impedance(c);
+    o[23] = 0.0f;
+    for (int f = 0; f < 4; ++f) {
+      const int w = conn[4 * k + f];
+      const int64_t kn = ((w & 7) == 7) ? k : static_cast<int64_t>(w >> 5);
+      o[24 + f] = aniso_impedance(coef + 22 * kn);
+    }
+    for (int i = 28; i < 32; ++i) o[i] = 0.0f;
   } else {
     const float rho = coef[3 * k], lam = coef[3 * k + 1], mu = coef[3 * k + 2];
     const float cp = sqrtf((lam + 2.0f * mu) / rho), cs = sqrtf(mu / rho);
@@ -637,6 +706,40 @@ dg_first_nonpositive_kernel(int64_t n, const float* __restrict__ x, int* flag) {
     const float v = x[i];
     if (!(v > 0.0f) || !(v <= 3.402823466e38f)) atomicMin(flag, static_cast<int>(i));
   }
+}
+
+// Cholesky factor of the symmetric 6x6 stiffness given by its 21 upper-
+// triangle entries, in double (lower triangle of Lc, row-major); false when a
+// pivot is not positive (the matrix is not positive definite) or not finite.
+__device__ __forceinline__ bool stiffness_cholesky(const float* __restrict__ c21, double Lc[6][6]) {
+  bool ok = true;
+  for (int i = 0; i < 6; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double v = static_cast<double>(c21[upper6(j, i)]);
+      for (int p = 0; p < j; ++p) v -= Lc[i][p] * Lc[j][p];
+      if (i == j) {
+        ok = ok && (v > 0.0) && (v <= 1.0e300);
+        Lc[i][i] = sqrt(v > 0.0 ? v : 1.0);
+      } else {
+        Lc[i][j] = v / Lc[j][j];
+      }
+    }
+  }
+  return ok;
+}
+
+// Anisotropic coefficients: the smallest element index whose density is not
+// positive and finite or whose stiffness is not finite and positive definite.
+__global__ void __launch_bounds__(kThreads)
+dg_first_bad_stiffness_kernel(int64_t K, const float* __restrict__ coef, int* flag) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (k >= K) return;
+  const float* c = coef + 22 * k;
+  bool ok = (c[0] > 0.0f) && (c[0] <= 3.402823466e38f);
+  for (int i = 1; i < 22; ++i) ok = ok && (fabsf(c[i]) <= 3.402823466e38f);
+  double Lc[6][6];
+  ok = ok && stiffness_cholesky(c + 1, Lc);
+  if (!ok) atomicMin(flag, static_cast<int>(k));
 }
 
 __global__ void dg_flag_none_kernel(int* flag) {
@@ -719,6 +822,29 @@ dg_energy_kernel(int64_t K, const float* __restrict__ q, const float* __restrict
         en = Mq[e][0] * qe[n] / (rho * c * c);
 #pragma unroll
         for (int ii = 1; ii < 4; ++ii) en += rho * Mq[e][ii] * qe[ii * NP + n];
+      } else if constexpr (PHYS == 2) {
+        // rho |v|^2 + s . C^-1 s, C^-1 s from the Cholesky factor
+        const float* c = coef + 22 * k;
+        double Lc[6][6];
+        stiffness_cholesky(c + 1, Lc);
+        double y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          double v = qe[(3 + i) * NP + n];
+          for (int p = 0; p < i; ++p) v -= Lc[i][p] * y[p];
+          y[i] = v / Lc[i][i];
+        }
+        for (int i = 5; i >= 0; --i) {
+          double v = y[i];
+          for (int p = i + 1; p < 6; ++p) v -= Lc[p][i] * y[p];
+          y[i] = v / Lc[i][i];
+        }
+        double kin = 0.0, ss = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) kin += Mq[e][ii] * qe[ii * NP + n];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) ss += Mq[e][3 + v] * y[v];
+        en = static_cast<double>(c[0]) * kin + ss;
       } else {
         const double rho = coef[3 * k], lam = coef[3 * k + 1], mu = coef[3 * k + 2];
         double kin = 0.0, ss = 0.0;
@@ -814,33 +940,51 @@ hipError_t energy_impl(int64_t K, const float* q, const float* coef, const doubl
   return hipGetLastError();
 }
 
-template <int PHYS>
-int64_t energy_blocks_impl(int N, int64_t K) {
-  int KT = 1;
+// Calls f(integral_constant<N>, integral_constant<PHYS>) for a runtime
+// (physics, degree); `bad` when either is out of range.
+template <int P, class R, class F>
+R with_degree(int N, R bad, F&& f) {
+  using P_ = std::integral_constant<int, P>;
   switch (N) {
-    case 1: KT = ETile<1, PHYS>::KT; break;
-    case 2: KT = ETile<2, PHYS>::KT; break;
-    case 3: KT = ETile<3, PHYS>::KT; break;
-    case 4: KT = ETile<4, PHYS>::KT; break;
-    case 5: KT = ETile<5, PHYS>::KT; break;
-    case 6: KT = ETile<6, PHYS>::KT; break;
-    case 7: KT = ETile<7, PHYS>::KT; break;
-    case 8: KT = ETile<8, PHYS>::KT; break;
-    default: return -1;
+    case 1: return f(std::integral_constant<int, 1>{}, P_{});
+    case 2: return f(std::integral_constant<int, 2>{}, P_{});
+    case 3: return f(std::integral_constant<int, 3>{}, P_{});
+    case 4: return f(std::integral_constant<int, 4>{}, P_{});
+    case 5: return f(std::integral_constant<int, 5>{}, P_{});
+    case 6: return f(std::integral_constant<int, 6>{}, P_{});
+    case 7: return f(std::integral_constant<int, 7>{}, P_{});
+    case 8: return f(std::integral_constant<int, 8>{}, P_{});
   }
-  return (K + KT - 1) / KT;
+  return bad;
 }
+
+template <class R, class F>
+R with_physics_degree(int physics, int N, R bad, F&& f) {
+  switch (physics) {
+    case 0: return with_degree<0>(N, bad, f);
+    case 1: return with_degree<1>(N, bad, f);
+    case 2: return with_degree<2>(N, bad, f);
+  }
+  return bad;
+}
+
+#define DGW_NP(n, p) decltype(n)::value, decltype(p)::value
 
 }  // namespace
 
-int coef_block(int physics) { return physics == 0 ? Phys<0>::CB : Phys<1>::CB; }
-int num_traces(int physics) { return physics == 0 ? Phys<0>::NT : Phys<1>::NT; }
+int coef_block(int physics) {
+  return physics == 0 ? Phys<0>::CB : (physics == 1 ? Phys<1>::CB : Phys<2>::CB);
+}
+int num_traces(int physics) {
+  return physics == 0 ? Phys<0>::NT : (physics == 1 ? Phys<1>::NT : Phys<2>::NT);
+}
 
 static bool is_mfma(int variant) { return mfma_precision(variant) >= 0; }
 
 bool variant_supported(int physics, int N, int variant) {
-  if (N < 1 || N > 8 || (physics != 0 && physics != 1)) return false;
+  if (N < 1 || N > 8 || physics < 0 || physics > 2) return false;
   if (variant == kVariantValu) return true;
+  if (physics == 2) return false;  // anisotropic: node-per-thread kernel only
   if (variant == kVariantMfmaWide) return physics == 0;  // acoustic tile shapes only
   if (is_mfma(variant)) return true;
   if (variant == kVariantElem) return elem_supported(physics, N);
@@ -848,36 +992,12 @@ bool variant_supported(int physics, int N, int variant) {
 }
 
 hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
+  if (!variant_supported(physics, N, variant)) return hipErrorInvalidValue;
   if (is_mfma(variant))
     return physics == 1 ? launch_step_mfma_elastic(N, variant, a, s) : launch_step_mfma(physics, N, variant, a, s);
   if (variant == kVariantElem) return launch_step_elem(physics, N, a, s);
-  if (variant != kVariantValu) return hipErrorInvalidValue;
-#define CALL(n, p) step_impl<n, p>(a, s)
-  if (physics == 0) {
-    switch (N) {
-      case 1: return CALL(1, 0);
-      case 2: return CALL(2, 0);
-      case 3: return CALL(3, 0);
-      case 4: return CALL(4, 0);
-      case 5: return CALL(5, 0);
-      case 6: return CALL(6, 0);
-      case 7: return CALL(7, 0);
-      case 8: return CALL(8, 0);
-    }
-  } else {
-    switch (N) {
-      case 1: return CALL(1, 1);
-      case 2: return CALL(2, 1);
-      case 3: return CALL(3, 1);
-      case 4: return CALL(4, 1);
-      case 5: return CALL(5, 1);
-      case 6: return CALL(6, 1);
-      case 7: return CALL(7, 1);
-      case 8: return CALL(8, 1);
-    }
-  }
-#undef CALL
-  return hipErrorInvalidValue;
+  return with_physics_degree(physics, N, hipErrorInvalidValue,
+                             [&](auto n, auto p) { return step_impl<DGW_NP(n, p)>(a, s); });
 }
 
 int64_t tiles_for(int physics, int N, int variant, int64_t K) {
@@ -889,74 +1009,25 @@ int tile_elements(int physics, int N, int variant) {
   if (!variant_supported(physics, N, variant)) return -1;
   if (is_mfma(variant)) return mfma_packing(physics, N, variant).E;
   if (variant == kVariantElem) return elem_tile_elements();
-#define TE(n, p) Tile<n, p>::KT
-  if (physics == 0) {
-    switch (N) {
-      case 1: return TE(1, 0); case 2: return TE(2, 0); case 3: return TE(3, 0); case 4: return TE(4, 0);
-      case 5: return TE(5, 0); case 6: return TE(6, 0); case 7: return TE(7, 0); case 8: return TE(8, 0);
-    }
-  } else {
-    switch (N) {
-      case 1: return TE(1, 1); case 2: return TE(2, 1); case 3: return TE(3, 1); case 4: return TE(4, 1);
-      case 5: return TE(5, 1); case 6: return TE(6, 1); case 7: return TE(7, 1); case 8: return TE(8, 1);
-    }
-  }
-#undef TE
-  return -1;
+  return with_physics_degree(physics, N, -1, [&](auto n, auto p) { return Tile<DGW_NP(n, p)>::KT; });
 }
-
 
 hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* args, const int2* work,
                              int64_t ntiles, int phase, hipStream_t s) {
+  if (!variant_supported(physics, N, variant)) return hipErrorInvalidValue;
   if (is_mfma(variant))
     return physics == 1 ? launch_step_batch_mfma_elastic(N, variant, args, work, ntiles, phase, s)
                         : launch_step_batch_mfma(physics, N, variant, args, work, ntiles, phase, s);
   if (variant == kVariantElem) return launch_step_batch_elem(physics, N, args, work, ntiles, phase, s);
-  if (variant != kVariantValu) return hipErrorInvalidValue;
-#define CALL(n, p) step_batch_impl<n, p>(args, work, ntiles, phase, s)
-  if (physics == 0) {
-    switch (N) {
-      case 1: return CALL(1, 0); case 2: return CALL(2, 0); case 3: return CALL(3, 0); case 4: return CALL(4, 0);
-      case 5: return CALL(5, 0); case 6: return CALL(6, 0); case 7: return CALL(7, 0); case 8: return CALL(8, 0);
-    }
-  } else {
-    switch (N) {
-      case 1: return CALL(1, 1); case 2: return CALL(2, 1); case 3: return CALL(3, 1); case 4: return CALL(4, 1);
-      case 5: return CALL(5, 1); case 6: return CALL(6, 1); case 7: return CALL(7, 1); case 8: return CALL(8, 1);
-    }
-  }
-#undef CALL
-  return hipErrorInvalidValue;
+  return with_physics_degree(physics, N, hipErrorInvalidValue, [&](auto n, auto p) {
+    return step_batch_impl<DGW_NP(n, p)>(args, work, ntiles, phase, s);
+  });
 }
 
 hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const float* geo,
                          const int32_t* fmask, float* qf, hipStream_t s) {
-#define CALL(n, p) trace_impl<n, p>(K, q, geo, fmask, qf, s)
-  if (physics == 0) {
-    switch (N) {
-      case 1: return CALL(1, 0);
-      case 2: return CALL(2, 0);
-      case 3: return CALL(3, 0);
-      case 4: return CALL(4, 0);
-      case 5: return CALL(5, 0);
-      case 6: return CALL(6, 0);
-      case 7: return CALL(7, 0);
-      case 8: return CALL(8, 0);
-    }
-  } else {
-    switch (N) {
-      case 1: return CALL(1, 1);
-      case 2: return CALL(2, 1);
-      case 3: return CALL(3, 1);
-      case 4: return CALL(4, 1);
-      case 5: return CALL(5, 1);
-      case 6: return CALL(6, 1);
-      case 7: return CALL(7, 1);
-      case 8: return CALL(8, 1);
-    }
-  }
-#undef CALL
-  return hipErrorInvalidValue;
+  return with_physics_degree(physics, N, hipErrorInvalidValue,
+                             [&](auto n, auto p) { return trace_impl<DGW_NP(n, p)>(K, q, geo, fmask, qf, s); });
 }
 
 hipError_t launch_first_nonpositive(int64_t n, const float* x, int* flag, hipStream_t s) {
@@ -969,15 +1040,25 @@ hipError_t launch_first_nonpositive(int64_t n, const float* x, int* flag, hipStr
   return hipGetLastError();
 }
 
+hipError_t launch_first_bad_stiffness(int64_t K, const float* coef, int* flag, hipStream_t s) {
+  if (K < 0 || K > kNoIndex) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dg_flag_set_kernel, dim3(1), dim3(64), 0, s, flag, kNoIndex);
+  if (K > 0)
+    hipLaunchKernelGGL(dg_first_bad_stiffness_kernel, dim3(static_cast<unsigned>((K + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, K, coef, flag);
+  hipLaunchKernelGGL(dg_flag_none_kernel, dim3(1), dim3(64), 0, s, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_coef_prep(int physics, int64_t K, const float* coef, const int32_t* conn, float* cf,
                             hipStream_t s) {
-  const int64_t blocks = (K + kThreads - 1) / kThreads;
-  if (physics == 0)
-    hipLaunchKernelGGL(dg_coef_kernel<0>, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, K,
-                       coef, conn, cf);
-  else
-    hipLaunchKernelGGL(dg_coef_kernel<1>, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0, s, K,
-                       coef, conn, cf);
+  const dim3 grid(static_cast<unsigned>((K + kThreads - 1) / kThreads)), block(kThreads);
+  switch (physics) {
+    case 0: hipLaunchKernelGGL(dg_coef_kernel<0>, grid, block, 0, s, K, coef, conn, cf); break;
+    case 1: hipLaunchKernelGGL(dg_coef_kernel<1>, grid, block, 0, s, K, coef, conn, cf); break;
+    case 2: hipLaunchKernelGGL(dg_coef_kernel<2>, grid, block, 0, s, K, coef, conn, cf); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1012,66 +1093,25 @@ hipError_t static_energy_partials(int device, double** ptr) {
 hipError_t launch_trace_comb(int physics, int N, int64_t nlist, const int32_t* list, const float* q,
                              const float* r0, const float* r1, const float* r2, float c0, float c1, float c2,
                              const float* geo, const int32_t* fmask, float* qf, hipStream_t s) {
-#define CALL(n, p) trace_comb_impl<n, p>(nlist, list, q, r0, r1, r2, c0, c1, c2, geo, fmask, qf, s)
-  if (physics == 0) {
-    switch (N) {
-      case 1: return CALL(1, 0);
-      case 2: return CALL(2, 0);
-      case 3: return CALL(3, 0);
-      case 4: return CALL(4, 0);
-      case 5: return CALL(5, 0);
-      case 6: return CALL(6, 0);
-      case 7: return CALL(7, 0);
-      case 8: return CALL(8, 0);
-    }
-  } else {
-    switch (N) {
-      case 1: return CALL(1, 1);
-      case 2: return CALL(2, 1);
-      case 3: return CALL(3, 1);
-      case 4: return CALL(4, 1);
-      case 5: return CALL(5, 1);
-      case 6: return CALL(6, 1);
-      case 7: return CALL(7, 1);
-      case 8: return CALL(8, 1);
-    }
-  }
-#undef CALL
-  return hipErrorInvalidValue;
+  return with_physics_degree(physics, N, hipErrorInvalidValue, [&](auto n, auto p) {
+    return trace_comb_impl<DGW_NP(n, p)>(nlist, list, q, r0, r1, r2, c0, c1, c2, geo, fmask, qf, s);
+  });
 }
 
 int64_t energy_blocks(int physics, int N, int64_t K) {
-  return physics == 0 ? energy_blocks_impl<0>(N, K) : energy_blocks_impl<1>(N, K);
+  return with_physics_degree(physics, N, int64_t(-1), [&](auto n, auto p) {
+    constexpr int KT = ETile<DGW_NP(n, p)>::KT;
+    return (K + KT - 1) / KT;
+  });
 }
 
 hipError_t launch_energy(int physics, int N, int64_t K, const float* q, const float* coef, const double* J,
                          const double* mass, double* partial, double* out, hipStream_t s) {
-#define CALL(n, p) energy_impl<n, p>(K, q, coef, J, mass, partial, out, s)
-  if (physics == 0) {
-    switch (N) {
-      case 1: return CALL(1, 0);
-      case 2: return CALL(2, 0);
-      case 3: return CALL(3, 0);
-      case 4: return CALL(4, 0);
-      case 5: return CALL(5, 0);
-      case 6: return CALL(6, 0);
-      case 7: return CALL(7, 0);
-      case 8: return CALL(8, 0);
-    }
-  } else {
-    switch (N) {
-      case 1: return CALL(1, 1);
-      case 2: return CALL(2, 1);
-      case 3: return CALL(3, 1);
-      case 4: return CALL(4, 1);
-      case 5: return CALL(5, 1);
-      case 6: return CALL(6, 1);
-      case 7: return CALL(7, 1);
-      case 8: return CALL(8, 1);
-    }
-  }
-#undef CALL
-  return hipErrorInvalidValue;
+  return with_physics_degree(physics, N, hipErrorInvalidValue, [&](auto n, auto p) {
+    return energy_impl<DGW_NP(n, p)>(K, q, coef, J, mass, partial, out, s);
+  });
 }
+
+#undef DGW_NP
 
 }  // namespace dgw

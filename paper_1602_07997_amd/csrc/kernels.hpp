@@ -42,7 +42,10 @@ constexpr int kRhsMode = 1;
 
 // Number of coefficient words per element in `cf`.
 int coef_block(int physics);
-// Number of traces per face node (2 acoustic, 6 elastic).
+// Number of caller coefficients per element (2 acoustic, 3 elastic, 22
+// anisotropic).
+inline int num_coefficients(int physics) { return physics == 0 ? 2 : (physics == 1 ? 3 : 22); }
+// Number of traces per face node (2 acoustic, 6 elastic and anisotropic).
 int num_traces(int physics);
 
 // Kernel variants of the step.
@@ -139,6 +142,10 @@ hipError_t launch_grad_finalize(int physics, int64_t K, const double* gacc, cons
 hipError_t launch_fill_zero_f64(int64_t n, double* p, hipStream_t s);
 // flag[0] = smallest i < n with x[i] not positive and finite, or -1.
 hipError_t launch_first_nonpositive(int64_t n, const float* x, int* flag, hipStream_t s);
+// Anisotropic coefficients [K][22]: flag[0] = smallest element whose density
+// is not positive and finite or whose stiffness is not finite and positive
+// definite, or -1.
+hipError_t launch_first_bad_stiffness(int64_t K, const float* coef, int* flag, hipStream_t s);
 hipError_t launch_fill_zero_f32(int64_t n, float* p, hipStream_t s);
 
 hipError_t launch_traces(int physics, int N, int64_t K, const float* q, const float* geo,

@@ -518,6 +518,10 @@ dg_status misfit_build(dg_solver* s, int64_t nsteps, double dt, int checkpoint_e
     set_error("dg_misfit_create: bad arguments");
     return DG_E_ARG;
   }
+  if (s->physics == DG_ANISOTROPIC) {
+    set_error("dg_misfit_create: the adjoint gradient is built for the acoustic and elastic physics only");
+    return DG_E_UNSUPPORTED;
+  }
   std::unique_ptr<dg_misfit> f(new dg_misfit);
   f->s = s;
   f->M = nsteps;

@@ -15,7 +15,8 @@ import numpy as np
 from . import _native as nat
 from ._native import check, lib
 
-PHYSICS = {"acoustic": nat.DG_ACOUSTIC, "elastic": nat.DG_ELASTIC}
+PHYSICS = {"acoustic": nat.DG_ACOUSTIC, "elastic": nat.DG_ELASTIC, "anisotropic": nat.DG_ANISOTROPIC}
+NCOEF = {"acoustic": 2, "elastic": 3, "anisotropic": 22}  # rho, c | rho, lambda, mu | rho, 21 stiffness entries
 
 
 def ref_sizes(order: int):
@@ -97,7 +98,7 @@ class DGSolver:
         self.K = int(self.xyz.shape[0])
         self.Np, self.Nfp = ref_sizes(order)
         self.nfields = lib.dg_num_fields(PHYSICS[physics])
-        self.ncoef = 2 if physics == "acoustic" else 3
+        self.ncoef = NCOEF[physics]
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream

@@ -30,6 +30,11 @@ def coefficients(physics: str, mesh, kind: str, seed: int = 1) -> np.ndarray:
             c = di.acoustic_two_layer(mesh)
         else:
             c = di.acoustic_loguniform(mesh, seed)
+    elif physics == "anisotropic":
+        if kind == "constant":
+            c = di.anisotropic_from_isotropic(di.elastic_constant(mesh))
+        else:
+            c = di.anisotropic_random(mesh, seed)
     else:
         if kind == "constant":
             c = di.elastic_constant(mesh)

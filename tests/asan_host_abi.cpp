@@ -64,7 +64,7 @@ int main() {
     expect(dg_reference_operators(N, nodes.data(), D.data(), mass.data(), lift.data(), fmask.data()) == DG_OK,
            "reference operators");
     expect(dg_face_permutations(N, perm.data()) == DG_OK, "face permutations");
-    for (int physics = 0; physics < 2; ++physics) {
+    for (int physics = 0; physics < 3; ++physics) {
       size_t bytes = 0;
       expect(dg_workspace_bytes(physics, N, 1000, &bytes) == DG_OK && bytes > 0, "workspace bytes");
     }
@@ -90,7 +90,7 @@ int main() {
   // dg_create up to the workspace check: host geometry, connectivity,
   // operator packing and layout run; the stand-in buffer is never touched
   void* fake = reinterpret_cast<void*>(uintptr_t(1) << 20);
-  for (int physics = 0; physics < 2; ++physics)
+  for (int physics = 0; physics < 3; ++physics)
     for (int N = 1; N <= 8; ++N) {
       size_t need = 0;
       dg_workspace_bytes(physics, N, K, &need);

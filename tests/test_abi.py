@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported_and_bound():
         assert name in nat.SIGNATURES, name
     assert set(nat.SIGNATURES) == set(names)
     assert nat.lib.dg_abi_version() == 2
-    assert nat.lib.dg_num_fields(0) == 4 and nat.lib.dg_num_fields(1) == 9
+    assert nat.lib.dg_num_fields(0) == 4 and nat.lib.dg_num_fields(1) == 9 and nat.lib.dg_num_fields(2) == 9
     assert nat.lib.dg_num_fields(7) == -1
 
 
@@ -136,7 +136,7 @@ def _ws_bytes(physics, order, K):
     return st, n.value
 
 
-@pytest.mark.parametrize("physics", [0, 1])
+@pytest.mark.parametrize("physics", [0, 1, 2])
 @pytest.mark.parametrize("N", [1, 4, 8])
 def test_workspace_bytes_cover_every_array(physics, N):
     """The workspace holds q, the three-slot AB3 ring, three trace buffers and
@@ -152,12 +152,14 @@ def test_workspace_bytes_cover_every_array(physics, N):
     # the operator tables do not grow with K; per element: q and three ring
     # slots, three trace buffers, G, derived and raw coefficients, four face
     # words, J and at most one energy partial sum
-    CB, ncoef = (8, 2) if physics == 0 else (16, 3)
+    CB, ncoef = {0: (8, 2), 1: (16, 3), 2: (32, 22)}[physics]
     per_elem = 4 * (4 * NF * Np + 3 * 4 * NT * Nfp + 9 + CB + ncoef + 4) + 8
     _, n1 = _ws_bytes(physics, N, 1000)
     _, n2 = _ws_bytes(physics, N, 2000)
     delta = (n2 - n1) - 1000 * per_elem
     assert -32 * 256 <= delta <= 1000 * 8 + 32 * 256  # alignment of each array, energy partial sums
+    if physics == 2:  # the anisotropic physics has the node-per-thread kernel only: no MFMA tables
+        assert _ws_bytes(2, N, 1)[1] < _ws_bytes(1, N, 1)[1]
 
 
 def test_workspace_bytes_argument_errors():
