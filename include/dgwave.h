@@ -90,7 +90,8 @@ typedef int dg_status;
  * (the P impedance for an isotropic C), applied to every traction and
  * velocity component; it dissipates (Z- Z+/(Z- + Z+)) |[v]|^2 + |[t]|^2 /
  * (Z- + Z+) per unit face area.  Walls and absorbing faces as DG_ELASTIC.
- * Only DG_VARIANT_VALU is built for it; misfits are not.                    */
+ * DG_VARIANT_VALU and DG_VARIANT_MFMA (FP32 matrix cores) are built for it;
+ * the split 16-bit and element variants, and misfits, are not.             */
 #define DG_ANISOTROPIC 2
 
 typedef struct dg_solver dg_solver;
@@ -195,7 +196,8 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
  *                         dg_autotune (the paper tunes its elements per
  *                         block per degree, Sec. 3.2 and Table 5).
  * The VALU and MFMA variants are built for the acoustic and elastic physics
- * and N = 1..8; the anisotropic physics has DG_VARIANT_VALU only.
+ * and N = 1..8; the anisotropic physics has DG_VARIANT_VALU and
+ * DG_VARIANT_MFMA.
  * Fields, r and the update stay FP32 in every variant.  Returns
  * DG_E_UNSUPPORTED for a combination that is not built.                    */
 #define DG_VARIANT_VALU 0

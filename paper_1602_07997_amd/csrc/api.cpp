@@ -63,7 +63,6 @@ HostTables make_tables(int physics, const dgw::RefElement* ref) {
   for (int n = 0; n < Np; ++n)
     for (int fm = 0; fm < 4 * Nfp; ++fm)
       t.LT[static_cast<size_t>(fm) * Np + n] = static_cast<float>(ref->lift[static_cast<size_t>(n) * 4 * Nfp + fm]);
-  if (physics == DG_ANISOTROPIC) return t;  // node-per-thread kernel only: no MFMA layouts
   const dgw::MfmaPacking p32 = dgw::mfma_packing(physics, order, dgw::kVariantMfma);
   const dgw::ColMap c32 = dgw::face_block_columns(Nfp, p32.KF);
   for (int j = 0; j < 3; ++j)

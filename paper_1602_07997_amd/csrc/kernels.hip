@@ -984,7 +984,7 @@ static bool is_mfma(int variant) { return mfma_precision(variant) >= 0; }
 bool variant_supported(int physics, int N, int variant) {
   if (N < 1 || N > 8 || physics < 0 || physics > 2) return false;
   if (variant == kVariantValu) return true;
-  if (physics == 2) return false;  // anisotropic: node-per-thread kernel only
+  if (physics == 2) return variant == kVariantMfma;  // anisotropic: node per thread and FP32 MFMA
   if (variant == kVariantMfmaWide) return physics == 0;  // acoustic tile shapes only
   if (is_mfma(variant)) return true;
   if (variant == kVariantElem) return elem_supported(physics, N);
@@ -994,7 +994,7 @@ bool variant_supported(int physics, int N, int variant) {
 hipError_t launch_step(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
   if (!variant_supported(physics, N, variant)) return hipErrorInvalidValue;
   if (is_mfma(variant))
-    return physics == 1 ? launch_step_mfma_elastic(N, variant, a, s) : launch_step_mfma(physics, N, variant, a, s);
+    return physics != 0 ? launch_step_mfma_elastic(physics, N, variant, a, s) : launch_step_mfma(physics, N, variant, a, s);
   if (variant == kVariantElem) return launch_step_elem(physics, N, a, s);
   return with_physics_degree(physics, N, hipErrorInvalidValue,
                              [&](auto n, auto p) { return step_impl<DGW_NP(n, p)>(a, s); });
@@ -1016,7 +1016,7 @@ hipError_t launch_step_batch(int physics, int N, int variant, const StepArgs* ar
                              int64_t ntiles, int phase, hipStream_t s) {
   if (!variant_supported(physics, N, variant)) return hipErrorInvalidValue;
   if (is_mfma(variant))
-    return physics == 1 ? launch_step_batch_mfma_elastic(N, variant, args, work, ntiles, phase, s)
+    return physics != 0 ? launch_step_batch_mfma_elastic(physics, N, variant, args, work, ntiles, phase, s)
                         : launch_step_batch_mfma(physics, N, variant, args, work, ntiles, phase, s);
   if (variant == kVariantElem) return launch_step_batch_elem(physics, N, args, work, ntiles, phase, s);
   return with_physics_degree(physics, N, hipErrorInvalidValue, [&](auto n, auto p) {

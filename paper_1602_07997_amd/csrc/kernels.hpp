@@ -75,11 +75,12 @@ int elem_tile_elements();
 hipError_t launch_step_elem(int physics, int N, const StepArgs& a, hipStream_t s);
 hipError_t launch_step_batch_elem(int physics, int N, const StepArgs* args, const int2* work, int64_t ntiles,
                                   int phase, hipStream_t s);
-// Elastic MFMA kernels (512-thread workgroups).
+// Elastic MFMA kernels (512-thread workgroups); physics 1 isotropic (every
+// precision), 2 anisotropic (FP32 products only).
 int mfma_elastic_tile_elements(int N, int variant);
-hipError_t launch_step_mfma_elastic(int N, int variant, const StepArgs& a, hipStream_t s);
-hipError_t launch_step_batch_mfma_elastic(int N, int variant, const StepArgs* args, const int2* work, int64_t ntiles,
-                                          int phase, hipStream_t s);
+hipError_t launch_step_mfma_elastic(int physics, int N, int variant, const StepArgs& a, hipStream_t s);
+hipError_t launch_step_batch_mfma_elastic(int physics, int N, int variant, const StepArgs* args, const int2* work,
+                                          int64_t ntiles, int phase, hipStream_t s);
 hipError_t launch_step_batch_mfma(int physics, int N, int variant, const StepArgs* args, const int2* work,
                                   int64_t ntiles, int phase, hipStream_t s);
 

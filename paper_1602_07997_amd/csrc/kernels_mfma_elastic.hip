@@ -65,7 +65,7 @@ constexpr int elastic_min_waves() {
   return (N == 5 && PREC == 0) ? 3 : (elastic_threads<N, PREC>() + 255) / 256;
 }
 
-template <int N, int PREC>
+template <int N, int PREC, int PHYS = 1>
 struct EShape {
   static constexpr int NP = Deg<N>::NP, NFP = Deg<N>::NFP;
   static constexpr int KS = PREC == 0 ? 4 : 16;
@@ -78,7 +78,9 @@ struct EShape {
   static constexpr int E = 16 * NBLK;
   static constexpr int PAIRS = MB * NBLK;
   static constexpr int NSV = 9;  // volume operand sets (the fields)
-  static constexpr int NSL = 5;  // LIFT operand sets (the lifted penalty scalars)
+  // LIFT operand sets (the lifted penalty scalars): five for the isotropic
+  // flux, six for the anisotropic one (velocity correction, strain vector)
+  static constexpr int NSL = PHYS == 1 ? 5 : 6;
   static constexpr int THREADS = elastic_threads<N, PREC>();
   // 4-byte words: the LIFT sets, then (reused) the volume sets
   static constexpr int REGION = (NSV * KP > NSL * KL ? NSV * KP : NSL * KL) * E;
@@ -91,9 +93,9 @@ struct EShape {
 //     else:    word s*STRIDE*E + ((k/4)*E + e)*4 + k%4   (4 consecutive k contiguous)
 //   16-bit split sets (LIFT operands of PREC 1, 2): hi at unit
 //     s*STRIDE*E + ((k/4)*E + e)*4 + k%4, lo REGION units later.
-template <int N, int PREC, int STRIDE>
+template <int N, int PREC, int STRIDE, int PHYS = 1>
 struct ERegion {
-  using S = EShape<N, PREC>;
+  using S = EShape<N, PREC, PHYS>;
   float* w;
   __device__ __forceinline__ int f32_word(int s, int k, int e) const {
     if constexpr (PREC == 0)
@@ -129,12 +131,14 @@ __device__ __forceinline__ Frag16 split4(const float4& x) {
   return f;
 }
 
-template <int N, int PREC>
+template <int N, int PREC, int PHYS>
 __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_t tile) {
-  using S = EShape<N, PREC>;
+  static_assert(PHYS == 1 || (PHYS == 2 && PREC == 0), "anisotropic: FP32 products only");
+  using S = EShape<N, PREC, PHYS>;
   constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
-  constexpr int NF = 9, NT = 6, CB = 16;
-  constexpr int FW = FaceRec<1>::W;
+  constexpr int NF = 9, NT = 6, CB = Phys<PHYS>::CB;
+  constexpr int NSL = S::NSL;
+  constexpr int FW = FaceRec<PHYS>::W;
   constexpr int TH = S::THREADS;
   constexpr int NW = TH / 64;
   constexpr int NIT = (E * KP + TH - 1) / TH;
@@ -155,8 +159,8 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   const int lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, nl = lane & 15;
   const bool step = (a.mode == kStepMode);
-  const ERegion<N, PREC, KL> lreg{s_B};  // LIFT operands
-  const ERegion<N, PREC, KP> vreg{s_B};  // fields (after the LIFT products)
+  const ERegion<N, PREC, KL, PHYS> lreg{s_B};  // LIFT operands
+  const ERegion<N, PREC, KP, PHYS> vreg{s_B};  // fields (after the LIFT products)
 
   // ---- A1: every global read indexed by the tile alone, issued together ----
   // Loads are unconditional at clamped (in-range) addresses and unused values
@@ -239,7 +243,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 #pragma unroll
     for (int c = 0; c < NT; ++c) nt[t][c] = tr[c * NFP];
   }
-  if (rec_e < ne) face_record<1>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
+  if (rec_e < ne) face_record<PHYS>(s_g + 9 * rec_e, s_cf + CB * rec_e, rec_f, rec_word, s_face + tid * FW);
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < FIT; ++t) {
@@ -250,9 +254,9 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     // A1 = Fs k_p (s_nn + Zp+ v_n), A2 = Fs k_s (s_nn + Zs+ v_n),
     // A3 = Fs (s n + Zs+ v); the normal and the coefficients are applied
     // after the per-face LIFT products
-    float b[5];
+    float b[NSL];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) b[c] = 0.0f;
+    for (int c = 0; c < NSL; ++c) b[c] = 0.0f;
     const int f = slot / KF;
     if (e < ne && slot - f * KF < NFP) {
       const float* rec = s_face + (e * 4 + f) * FW;
@@ -269,22 +273,33 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
         vP[ii] = wall ? gw * vM[ii] : nt[t][ii];
         tP[ii] = wall ? -gw * tM[ii] : -nt[t][3 + ii];
       }
-      float jv[3], jt[3];
+      if constexpr (PHYS == 2) {
+        // one-impedance Riemann solution per side: the velocity correction
+        // (t* - t-)/rho and the vector v* - v-, both times Fscale (full jumps)
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        jv[ii] = 0.5f * (vP[ii] - vM[ii]);
-        jt[ii] = 0.5f * (tP[ii] - tM[ii]);
+        for (int ii = 0; ii < 3; ++ii) {
+          const float jv = vP[ii] - vM[ii], jt = tP[ii] - tM[ii];
+          b[ii] = rec[3] * jt + rec[4] * jv;
+          b[3 + ii] = rec[5] * jt + rec[6] * jv;
+        }
+      } else {
+        float jv[3], jt[3];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          jv[ii] = 0.5f * (vP[ii] - vM[ii]);
+          jt[ii] = 0.5f * (tP[ii] - tM[ii]);
+        }
+        const float jvn = jv[0] * n0 + jv[1] * n1 + jv[2] * n2;
+        const float jsnn = jt[0] * n0 + jt[1] * n1 + jt[2] * n2;
+        const float ZpP = rec[3], ZsP = rec[4], fs = rec[5], kp = rec[6], ks = rec[7];
+        b[0] = fs * kp * (jsnn + ZpP * jvn);
+        b[1] = fs * ks * (jsnn + ZsP * jvn);
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) b[2 + ii] = fs * (jt[ii] + ZsP * jv[ii]);
       }
-      const float jvn = jv[0] * n0 + jv[1] * n1 + jv[2] * n2;
-      const float jsnn = jt[0] * n0 + jt[1] * n1 + jt[2] * n2;
-      const float ZpP = rec[3], ZsP = rec[4], fs = rec[5], kp = rec[6], ks = rec[7];
-      b[0] = fs * kp * (jsnn + ZpP * jvn);
-      b[1] = fs * ks * (jsnn + ZsP * jvn);
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) b[2 + ii] = fs * (jt[ii] + ZsP * jv[ii]);
     }
 #pragma unroll
-    for (int c = 0; c < 5; ++c) lreg.put_split(c, slot, e, b[c]);
+    for (int c = 0; c < NSL; ++c) lreg.put_split(c, slot, e, b[c]);
   }
   __syncthreads();
 
@@ -304,35 +319,54 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + nl;
     const int ecol = col < ne ? col : 0;
-    floatx4 LA[5];
+    floatx4 LA[NSL];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) LA[c] = floatx4{0, 0, 0, 0};
+    for (int c = 0; c < NSL; ++c) LA[c] = floatx4{0, 0, 0, 0};
     auto combine = [&](int f) {
       const float* rec = s_face + (ecol * 4 + f) * FW;
-      const float* cf = s_cf + ecol * CB;
-      const float nn[3] = {rec[0], rec[1], rec[2]};
-      const float ks = rec[7];
-      const float lam = cf[0], mu = cf[1], cp = cf[5], cs = cf[6];
-      const int vi[6] = {0, 1, 2, 1, 0, 0};
-      const int vj[6] = {0, 1, 2, 2, 2, 1};
+      if constexpr (PHYS == 2) {
+        // velocity: the lifted corrections as they are; rows 3..8 collect
+        // the engineering strain of n (x) w, to which the stiffness is
+        // applied once, with the volume strain, before the update
+        const float n0 = rec[0], n1 = rec[1], n2 = rec[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float a1 = LA[0][r], a2 = LA[1][r];
-        const float a3[3] = {LA[2][r], LA[3][r], LA[4][r]};
-        const float t = cp * a1 - cs * a2;
+        for (int r = 0; r < 4; ++r) {
+          const float w0 = LA[3][r], w1 = LA[4][r], w2 = LA[5][r];
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) LL[q][ii][r] += nn[ii] * t + ks * cs * a3[ii];
-        const float b2 = 2.0f * mu * (a1 - a2), c3 = mu * ks;
+          for (int ii = 0; ii < 3; ++ii) LL[q][ii][r] += LA[ii][r];
+          LL[q][3][r] += n0 * w0;
+          LL[q][4][r] += n1 * w1;
+          LL[q][5][r] += n2 * w2;
+          LL[q][6][r] += n1 * w2 + n2 * w1;
+          LL[q][7][r] += n0 * w2 + n2 * w0;
+          LL[q][8][r] += n0 * w1 + n1 * w0;
+        }
+      } else {
+        const float* cf = s_cf + ecol * CB;
+        const float nn[3] = {rec[0], rec[1], rec[2]};
+        const float ks = rec[7];
+        const float lam = cf[0], mu = cf[1], cp = cf[5], cs = cf[6];
+        const int vi[6] = {0, 1, 2, 1, 0, 0};
+        const int vj[6] = {0, 1, 2, 2, 2, 1};
 #pragma unroll
-        for (int v = 0; v < 6; ++v) {
-          const int ii = vi[v], jj = vj[v];
-          float x = b2 * nn[ii] * nn[jj] + c3 * (nn[ii] * a3[jj] + a3[ii] * nn[jj]);
-          if (ii == jj) x += lam * a1;
-          LL[q][3 + v][r] += x;
+        for (int r = 0; r < 4; ++r) {
+          const float a1 = LA[0][r], a2 = LA[1][r];
+          const float a3[3] = {LA[2][r], LA[3][r], LA[4][r]};
+          const float t = cp * a1 - cs * a2;
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) LL[q][ii][r] += nn[ii] * t + ks * cs * a3[ii];
+          const float b2 = 2.0f * mu * (a1 - a2), c3 = mu * ks;
+#pragma unroll
+          for (int v = 0; v < 6; ++v) {
+            const int ii = vi[v], jj = vj[v];
+            float x = b2 * nn[ii] * nn[jj] + c3 * (nn[ii] * a3[jj] + a3[ii] * nn[jj]);
+            if (ii == jj) x += lam * a1;
+            LL[q][3 + v][r] += x;
+          }
         }
       }
 #pragma unroll
-      for (int c = 0; c < 5; ++c) LA[c] = floatx4{0, 0, 0, 0};
+      for (int c = 0; c < NSL; ++c) LA[c] = floatx4{0, 0, 0, 0};
     };
     // operator fragments stream through two register sets (pipelined, fully
     // unrolled so that each k-step's face is known at compile time)
@@ -351,7 +385,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
           const int kk = g * PD + i;
           const int k = kk * 4 + kq;
 #pragma unroll
-          for (int c = 0; c < 5; ++c) LA[c] = mfma_f32(r.v[i][0], s_B[lreg.f32_word(c, k, col)], LA[c]);
+          for (int c = 0; c < NSL; ++c) LA[c] = mfma_f32(r.v[i][0], s_B[lreg.f32_word(c, k, col)], LA[c]);
           if (kk % NKF == NKF - 1) combine(kk / NKF);
         }
       };
@@ -512,7 +546,6 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
     }
     // right-hand sides in the accumulator layout (rows 4 kq + r, column nl)
     const float* cf = s_cf + ec * CB;
-    const float lam = cf[0], mu = cf[1], irho = cf[2];
     float rr[9][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -522,17 +555,35 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj)
           gv[ii][jj] = G[3 * jj + 0] * Dv[ii][0][r] + G[3 * jj + 1] * Dv[ii][1][r] + G[3 * jj + 2] * Dv[ii][2][r];
-      const float divv = gv[0][0] + gv[1][1] + gv[2][2];
+      if constexpr (PHYS == 2) {
+        // stiffness times the volume strain plus the faces' strain
+        const float irho = cf[21];
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) rr[ii][r] = irho * dS[ii][r] + LL[q][ii][r];
-      const int vi[6] = {0, 1, 2, 1, 0, 0};
-      const int vj[6] = {0, 1, 2, 2, 2, 1};
+        for (int ii = 0; ii < 3; ++ii) rr[ii][r] = irho * dS[ii][r] + LL[q][ii][r];
+        const float ev[6] = {gv[0][0] + LL[q][3][r], gv[1][1] + LL[q][4][r], gv[2][2] + LL[q][5][r],
+                             gv[1][2] + gv[2][1] + LL[q][6][r], gv[0][2] + gv[2][0] + LL[q][7][r],
+                             gv[0][1] + gv[1][0] + LL[q][8][r]};
 #pragma unroll
-      for (int v = 0; v < 6; ++v) {
-        const int ii = vi[v], jj = vj[v];
-        float x = mu * (gv[ii][jj] + gv[jj][ii]) + LL[q][3 + v][r];
-        if (ii == jj) x += lam * divv;
-        rr[3 + v][r] = x;
+        for (int va = 0; va < 6; ++va) {
+          float x = 0.0f;
+#pragma unroll
+          for (int vb = 0; vb < 6; ++vb) x += cf[va <= vb ? upper6(va, vb) : upper6(vb, va)] * ev[vb];
+          rr[3 + va][r] = x;
+        }
+      } else {
+        const float lam = cf[0], mu = cf[1], irho = cf[2];
+        const float divv = gv[0][0] + gv[1][1] + gv[2][2];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) rr[ii][r] = irho * dS[ii][r] + LL[q][ii][r];
+        const int vi[6] = {0, 1, 2, 1, 0, 0};
+        const int vj[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+          const int ii = vi[v], jj = vj[v];
+          float x = mu * (gv[ii][jj] + gv[jj][ii]) + LL[q][3 + v][r];
+          if (ii == jj) x += lam * divv;
+          rr[3 + v][r] = x;
+        }
       }
     }
     // transpose, update and write field by field; lane -> (node mb*16 + nl,
@@ -613,37 +664,39 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
   }
 }
 
-template <int N, int PREC>
+// PHYS = 1: isotropic elasticity; PHYS = 2: anisotropic (FP32 products only)
+template <int N, int PREC, int PHYS>
 __global__ void __launch_bounds__((elastic_threads<N, PREC>()), (elastic_min_waves<N, PREC>()))
 dg_step_mfma_elastic(StepArgs a) {
-  step_mfma_elastic_tile<N, PREC>(a, tile_of_block(a.xcd_remap));
+  step_mfma_elastic_tile<N, PREC, PHYS>(a, tile_of_block(a.xcd_remap));
 }
 
-template <int N, int PREC>
+template <int N, int PREC, int PHYS>
 __global__ void __launch_bounds__((elastic_threads<N, PREC>()), (elastic_min_waves<N, PREC>()))
 dg_step_mfma_elastic_batch(const StepArgs* __restrict__ args, const int2* __restrict__ work, int phase) {
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
   const StepArgs a = args[w.x * kBatchPhases + phase];
-  step_mfma_elastic_tile<N, PREC>(a, w.y);
+  step_mfma_elastic_tile<N, PREC, PHYS>(a, w.y);
 }
 
-template <int N, int PREC>
+template <int N, int PREC, int PHYS = 1>
 hipError_t emfma_impl(const StepArgs& a, hipStream_t s) {
-  constexpr int E = EShape<N, PREC>::E;
+  constexpr int E = EShape<N, PREC, PHYS>::E;
   int64_t tiles = (a.K - a.e_begin + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC>), dim3(static_cast<unsigned>(tiles)), dim3(elastic_threads<N, PREC>()), 0, s, a);
+  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC, PHYS>), dim3(static_cast<unsigned>(tiles)),
+                     dim3(elastic_threads<N, PREC>()), 0, s, a);
   return hipGetLastError();
 }
 
-template <int N, int PREC>
+template <int N, int PREC, int PHYS = 1>
 hipError_t emfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntiles, int phase, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_elastic_batch<N, PREC>), dim3(static_cast<unsigned>(ntiles)), dim3(elastic_threads<N, PREC>()), 0,
-                     s, args, work, phase);
+  hipLaunchKernelGGL((dg_step_mfma_elastic_batch<N, PREC, PHYS>), dim3(static_cast<unsigned>(ntiles)),
+                     dim3(elastic_threads<N, PREC>()), 0, s, args, work, phase);
   return hipGetLastError();
 }
 
@@ -688,20 +741,44 @@ MfmaPacking mfma_elastic_packing(int N, int variant) {
   return MfmaPacking{};
 }
 
-hipError_t launch_step_mfma_elastic(int N, int variant, const StepArgs& a, hipStream_t s) {
+// the anisotropic kernels: FP32 products only
+#define DGW_AMFMA_DISPATCH(CALL)                                                          \
+  if (mfma_precision(variant) == 0) {                                                      \
+    switch (N) {                                                                           \
+      case 1: return CALL(1, 0); case 2: return CALL(2, 0); case 3: return CALL(3, 0);     \
+      case 4: return CALL(4, 0); case 5: return CALL(5, 0); case 6: return CALL(6, 0);     \
+      case 7: return CALL(7, 0); case 8: return CALL(8, 0);                                \
+    }                                                                                      \
+  }
+
+hipError_t launch_step_mfma_elastic(int physics, int N, int variant, const StepArgs& a, hipStream_t s) {
+  if (physics == 2) {
+#define CALL(n, p) emfma_impl<n, p, 2>(a, s)
+    DGW_AMFMA_DISPATCH(CALL)
+#undef CALL
+    return hipErrorInvalidValue;
+  }
 #define CALL(n, p) emfma_impl<n, p>(a, s)
   DGW_EMFMA_DISPATCH(CALL)
 #undef CALL
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_batch_mfma_elastic(int N, int variant, const StepArgs* args, const int2* work, int64_t ntiles,
-                                          int phase, hipStream_t s) {
+hipError_t launch_step_batch_mfma_elastic(int physics, int N, int variant, const StepArgs* args, const int2* work,
+                                          int64_t ntiles, int phase, hipStream_t s) {
+  if (physics == 2) {
+#define CALL(n, p) emfma_batch_impl<n, p, 2>(args, work, ntiles, phase, s)
+    DGW_AMFMA_DISPATCH(CALL)
+#undef CALL
+    return hipErrorInvalidValue;
+  }
 #define CALL(n, p) emfma_batch_impl<n, p>(args, work, ntiles, phase, s)
   DGW_EMFMA_DISPATCH(CALL)
 #undef CALL
   return hipErrorInvalidValue;
 }
+
+#undef DGW_AMFMA_DISPATCH
 
 #undef DGW_EMFMA_DISPATCH
 

@@ -30,31 +30,37 @@ def _mesh_n(N):
     return 3 if N <= 4 else 2
 
 
+@pytest.mark.parametrize("variant", ["valu", "mfma"])
 @pytest.mark.parametrize("N", DEGREES)
-def test_rhs_parity(N):
-    log(f"anisotropic rhs parity N={N}")
+def test_rhs_parity(N, variant):
+    log(f"anisotropic rhs parity N={N} {variant}")
     c = Case("anisotropic", N, _mesh_n(N), jitter=0.1, seed=N, coef_kind="random", init="smooth")
+    c.solver.variant = variant
     r = c.solver.rhs(c.to_gpu(c.q0_gpu))
     torch.cuda.synchronize()
     c.check(c.to_host(r), c.oracle.rhs(c.q0), 2e-6, "rhs")
 
 
+@pytest.mark.parametrize("variant", ["valu", "mfma"])
 @pytest.mark.parametrize("N", [2, 5])
-def test_rhs_parity_absorbing_faces(N):
-    log(f"anisotropic rhs parity, half the walls absorbing, N={N}")
+def test_rhs_parity_absorbing_faces(N, variant):
+    log(f"anisotropic rhs parity, half the walls absorbing, N={N} {variant}")
     c = Case("anisotropic", N, 2, jitter=0.1, seed=50 + N, coef_kind="random", init="smooth", absorbing="half")
+    c.solver.variant = variant
     r = c.solver.rhs(c.to_gpu(c.q0_gpu))
     torch.cuda.synchronize()
     c.check(c.to_host(r), c.oracle.rhs(c.q0), 2e-6, "rhs absorbing")
 
 
-@pytest.mark.parametrize("N,periodic", [(1, True), (3, False), (4, True)])
-def test_all_face_orientations_parity(N, periodic):
+@pytest.mark.parametrize("variant,N,periodic", [("valu", 1, True), ("valu", 3, False), ("valu", 4, True),
+                                               ("mfma", 2, True), ("mfma", 6, False), ("mfma", 8, False)])
+def test_all_face_orientations_parity(variant, N, periodic):
     """Vertices listed in random even orders, so that shared faces meet under
     all six relative orientations: one right-hand side and 20 AB3 steps."""
-    log(f"anisotropic all orientations N={N} periodic={periodic}")
+    log(f"anisotropic all orientations {variant} N={N} periodic={periodic}")
     mesh = di.relabel_vertices(di.kuhn_box(3, 2, 3, jitter=0.1, seed=60 + N, periodic=periodic), seed=70 + N)
     c = Case("anisotropic", N, 0, coef_kind="random", init="smooth", mesh=mesh, seed=60 + N)
+    c.solver.variant = variant
     r = c.solver.rhs(c.to_gpu(c.q0_gpu))
     torch.cuda.synchronize()
     c.check(c.to_host(r), c.oracle.rhs(c.q0), 2e-6, "rhs")
@@ -63,10 +69,12 @@ def test_all_face_orientations_parity(N, periodic):
     c.check(c.to_host(c.solver.get_fields()), AB3Stepper(c.oracle, c.q0).step(20, c.dt), 1e-5, "20 steps")
 
 
+@pytest.mark.parametrize("variant", ["valu", "mfma"])
 @pytest.mark.parametrize("N", DEGREES)
-def test_steps_parity(N):
-    log(f"anisotropic 20-step parity N={N}")
+def test_steps_parity(N, variant):
+    log(f"anisotropic 20-step parity N={N} {variant}")
     c = Case("anisotropic", N, _mesh_n(N), jitter=0.1, seed=10 + N, coef_kind="random", init="gaussian")
+    c.solver.variant = variant
     c.solver.set_fields(c.to_gpu(c.q0_gpu))
     c.solver.step(20, c.dt)
     q = c.to_host(c.solver.get_fields())
@@ -137,12 +145,15 @@ def test_two_rate_parity():
 def test_batch_member_matches_alone():
     from paper_1602_07997_amd import DGBatch, DGSolver
 
+    specs = ((2, (3, 2, 2), "valu"), (3, (2, 3, 2), "valu"), (5, (2, 2, 2), "mfma"))
     cases = [Case("anisotropic", N, None, jitter=0.1, seed=80 + N, coef_kind="random", init="gaussian", dims=d)
-             for N, d in ((2, (3, 2, 2)), (3, (2, 3, 2)))]
+             for N, d, _ in specs]
     twins = []
-    for c in cases:
+    for c, (_, _, v) in zip(cases, specs):
+        c.solver.variant = v
         c.solver.set_fields(c.to_gpu(c.q0_gpu))
         t = DGSolver("anisotropic", c.N, c.mesh.elem_xyz, c.mesh.elem_topo)
+        t.variant = v
         t.set_coefficients(torch.tensor(c.coef, dtype=torch.float32, device="cuda"))
         t.set_fields(c.to_gpu(c.q0_gpu))
         twins.append(t)
@@ -184,15 +195,17 @@ def test_invalid_stiffness_is_refused():
     c.solver.step(1, c.dt)
 
 
-def test_only_the_valu_variant_and_no_misfit_are_built():
+def test_only_valu_and_fp32_mfma_and_no_misfit_are_built():
     from paper_1602_07997_amd import DGMisfit
 
     c = Case("anisotropic", 3, 2, jitter=0.1, seed=91, coef_kind="random", init="gaussian")
-    for v in ("mfma", "mfma_bf16", "mfma_f16", "elem", "mfma_wide"):
+    for v in ("mfma_bf16", "mfma_f16", "elem", "mfma_wide"):
         with pytest.raises(nat.DGError) as ei:
             c.solver.variant = v
         assert ei.value.status == nat.DG_E_UNSUPPORTED
     assert c.solver.variant == "valu"
+    c.solver.variant = "mfma"
+    assert c.solver.variant == "mfma"
     with pytest.raises(nat.DGError) as ei:
         DGMisfit(c.solver, 10, c.dt, [[0.5, 0.5, 0.5]], np.zeros(11), [[0.3, 0.4, 0.5]])
     assert ei.value.status == nat.DG_E_UNSUPPORTED
