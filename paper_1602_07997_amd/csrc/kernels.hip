@@ -39,13 +39,16 @@ namespace {
 
 using namespace dev;
 
-// Elements per workgroup, chosen so that KT*NP fills ~256 threads.
+// Elements per workgroup, chosen so that KT*NP fills ~256 threads; the
+// elastic fields at N = 1 take 32 elements (measured: at N = 2 the full 25
+// is 5% faster than 20 and 14% faster than 16; at N = 3, 4 fewer elements
+// than 256 / Np measured slower, and so did other counts for the acoustic
+// fields at N = 1..3).
 template <int N, int PHYS>
 struct Tile {
   static constexpr int NP = Deg<N>::NP;
   static constexpr int raw = 256 / NP;
-  static constexpr int KT =
-      (N == 8 && PHYS == 0) ? 3 : (PHYS != 0 && N <= 2 ? (N == 1 ? 32 : 16) : (raw < 1 ? 1 : raw));
+  static constexpr int KT = (N == 8 && PHYS == 0) ? 3 : (PHYS != 0 && N == 1 ? 32 : (raw < 1 ? 1 : raw));
 };
 
 // Number of lifted scalars per face node: acoustic (Fscale*penalty for p,

@@ -57,12 +57,13 @@ constexpr int prefetch_fp32(int N) { return (N >= 5 && N <= 7) ? 2 : 4; }
 constexpr int kPrefetch16 = 1;
 
 // wavefronts per workgroup: one per (node block, element block) pair where
-// that fits the tile (N = 6: six pairs, N = 7: eight), which also leaves
-// fewer accumulators per wavefront and so more resident wavefronts; at N = 8
-// the split 16-bit products take eight wavefronts for eleven pairs, the FP32
-// ones keep four (measured faster each way)
+// that fits the tile (N = 4 FP32: three pairs, N = 6: six, N = 7: eight),
+// which also leaves fewer accumulators per wavefront and so more resident
+// wavefronts (N = 4: eight workgroups per compute unit instead of six, 2%
+// faster); at N = 8 the split 16-bit products take eight wavefronts for
+// eleven pairs, the FP32 ones keep four (measured faster each way)
 constexpr int acoustic_waves(int N, int PREC) {
-  return N == 6 ? 6 : (N == 7 ? 8 : ((N == 8 && PREC != 0) ? 8 : 4));
+  return (N == 4 && PREC == 0) ? 3 : (N == 6 ? 6 : (N == 7 ? 8 : ((N == 8 && PREC != 0) ? 8 : 4)));
 }
 
 // resident wavefronts per SIMD that the register allocation must allow: the
@@ -100,7 +101,8 @@ struct MShape {
   static constexpr int NBLK = !cfg_wide(CFG) ? NBLK0 : (N <= 3 ? NBLK0 / 2 : 2);
   static constexpr int E = 16 * NBLK;            // elements per tile
   static constexpr int PAIRS = MB * NBLK;
-  static constexpr int NW = acoustic_waves(N, P) * ((cfg_wide(CFG) && N >= 4) ? 2 : 1);  // wavefronts per workgroup
+  // wavefronts per workgroup (the wide N = 4 tile keeps eight: six spill)
+  static constexpr int NW = (cfg_wide(CFG) && N >= 4) ? 2 * (N == 4 ? 4 : acoustic_waves(N, P)) : acoustic_waves(N, P);
   static constexpr int THREADS = 64 * NW;
   // 4-byte words of B operands: four volume sets of KP rows, then (reused)
   // two penalty sets of KL rows

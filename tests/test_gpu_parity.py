@@ -334,3 +334,23 @@ def test_all_face_orientations_parity(physics, variant, N, periodic):
     c.solver.step(20, c.dt)
     q = c.to_host(c.solver.get_fields())
     c.check(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt), tol_q, "20 steps")
+
+
+@pytest.mark.parametrize("physics,N,dims", [
+    ("elastic", 7, (9, 9, 9)), ("elastic", 8, (9, 9, 9)), ("anisotropic", 7, (9, 9, 9)), ("acoustic", 7, (11, 12, 12)),
+])
+def test_mfma_short_last_round_parity(physics, N, dims):
+    """Meshes whose 16-element tiles fill the MI355X's resident workgroups
+    (256 compute units times one, or two for acoustic N = 7) once or twice
+    plus a short last round (274 tiles for 256 slots, 594 for 512), with the
+    tiles mapped onto the XCDs in contiguous ranges: one RHS and 10 AB3
+    steps against the oracle."""
+    log(f"short last round {physics} N={N} dims={dims}")
+    c = Case(physics, N, None, jitter=0.1, seed=95 + N, coef_kind="random", init="smooth", dims=dims)
+    c.solver.variant = "mfma"
+    r = c.solver.rhs(c.to_gpu(c.q0_gpu))
+    torch.cuda.synchronize()
+    c.check(c.to_host(r), c.oracle.rhs(c.q0), 2e-6, "rhs")
+    c.solver.set_fields(c.to_gpu(c.q0_gpu))
+    c.solver.step(10, c.dt)
+    c.check(c.to_host(c.solver.get_fields()), AB3Stepper(c.oracle, c.q0).step(10, c.dt), 1e-5, "10 steps")
