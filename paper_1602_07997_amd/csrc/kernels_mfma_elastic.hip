@@ -587,8 +587,10 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
       }
     }
     // transpose, update and write field by field; lane -> (node mb*16 + nl,
-    // element nb*16 + kq + 4 it); the fields and history are read three
-    // fields at a time, each batch issued together at clamped addresses
+    // element nb*16 + kq + 4 it); the fields q^m come from the operand region
+    // (the FP32 volume sets are exact copies, still in place), the history
+    // is read three fields at a time, each batch issued together at clamped
+    // addresses
     const int n = mb * 16 + nl;
     const int ncl = n < NP ? n : NP - 1;
     int nfs[3] = {-1, -1, -1};
@@ -610,7 +612,7 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
           const int64_t base = (e0 + (e < ne ? e : ne - 1)) * NF * NP + ncl;
 #pragma unroll
           for (int u = 0; u < 3; ++u) {
-            qo[u][it] = a.q_in[base + (c0 + u) * NP];
+            qo[u][it] = s_B[vreg.f32_word(c0 + u, ncl, e < ne ? e : ne - 1)];
             h1[u][it] = p1[base + (c0 + u) * NP];
             h2[u][it] = p2[base + (c0 + u) * NP];
           }
