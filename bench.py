@@ -696,7 +696,7 @@ def main_adjoint(args, log):
     s = DGSolver("elastic", N, mesh.elem_xyz, mesh.elem_topo)
     s.set_coefficients(torch.tensor(coef * blob[:, None].astype(np.float32), device="cuda"))
     s.set_fields(torch.zeros(s.field_shape, device="cuda"))
-    chosen = s.autotune(2, dt, None if args.variant == "auto-mixed" else FP32_VARIANTS)
+    chosen = s.autotune(2, dt, FP32_VARIANTS + ("mfma_f16",) if args.variant == "auto-mixed" else FP32_VARIANTS)
     f = DGMisfit(s, steps, dt, [0.5, 0.5, 0.5], wav, rec, checkpoint_every=20)
     data, _ = f.forward()
     s.set_coefficients(torch.tensor(coef, device="cuda"))
@@ -745,7 +745,10 @@ def dtype_of(variants) -> str:
 
 
 def main_batched(args, log):
-    cands = None if args.variant == "auto-mixed" else FP32_VARIANTS
+    # auto-mixed: the FP16 split variant joins the FP32 candidates; the BF16
+    # split misses the 1e-4 accuracy target from N = 4 on the paper-scale
+    # meshes (its dropped lo*lo term is 2^-16 relative), so it stays out
+    cands = FP32_VARIANTS + ("mfma_f16",) if args.variant == "auto-mixed" else FP32_VARIANTS
     r = run_batched(args.steps, args.warmup, log, candidates=cands)
     step_s = r["t_batch"] / r["steps"]
     plain_s = r["t_plain"] / r["plain_steps"]
@@ -799,7 +802,8 @@ def main(argv=None):
     ap.add_argument(
         "--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "elem", "auto", "auto-mixed"], default="auto",
         help="kernel variant for every degree; 'auto' lets the autotuner pick among the FP32 variants per "
-        "degree, 'auto-mixed' also among the BF16/FP16 split-product variants",
+        "degree, 'auto-mixed' also among the split-product variants (the sweep admits those within 1e-4 of the "
+        "FP64 oracle on its meshes; the batched and adjoint workloads admit FP16 only)",
     )
     ap.add_argument(
         "--variant-map", type=str, default="",
