@@ -9,9 +9,9 @@
   same kernels on the same inputs: identical results);
 * at the paper-scale adjoint workload (elastic N=4, 14,196 tetrahedra, 200
   steps, checkpoints every 20) central differences of the FP32 GPU misfit
-  agree with the gradient to 5e-3 on 8 coefficients drawn at random among
-  the sensitive ones (the FP32 rounding of J over the 0.2% step bounds the
-  differences; exactness is the complex-step comparison above).
+  agree with the gradient to 5e-3 on the 8 most sensitive coefficients (the
+  FP32 rounding of J over the 0.2% step bounds the differences; exactness is
+  the complex-step comparison above).
 """
 
 import numpy as np
@@ -178,10 +178,11 @@ def test_paper_scale_adjoint_finite_differences():
     """Elastic N=4 on the 13x13x14 Kuhn box (14,196 tetrahedra), 200 steps,
     checkpoints every 20, Ricker source (peak frequency 5) at the box centre,
     64 receivers uniform in [0.1, 0.9]^3 (seed 4), data from coefficients
-    with a +5% Gaussian blob; central differences of the GPU misfit on 8
-    coefficients drawn at random (seed 6) from those whose sensitivity
-    |g c| is at least a quarter of the largest (below that the FP32
-    rounding of J swamps a 0.2% central difference).  200 CFL-limited
+    with a +5% Gaussian blob; central differences of the GPU misfit on the
+    8 coefficients of largest sensitivity |g c| (the sensitivity falls off
+    steeply away from the source and receivers: only 3 coefficients reach a
+    quarter of the largest, and below that the FP32 rounding of J swamps a
+    0.2% central difference).  200 CFL-limited
     steps span a small part of one period of the wavelet, so its peak is
     placed in the middle of the window (t0 = 100 dt)."""
     from paper_1602_07997_amd import DGMisfit, DGSolver
@@ -210,10 +211,7 @@ def test_paper_scale_adjoint_finite_differences():
     log(f"  J = {J:.6e}, |g| max {np.abs(g).max():.3e}")
     assert J > 0.0
     sens = np.abs(g * coef).ravel()
-    cands = np.flatnonzero(sens >= 0.25 * sens.max())
-    assert cands.size >= 8, cands.size
-    flat = np.random.default_rng(6).choice(cands, 8, replace=False)
-    log(f"  {cands.size} coefficients with at least a quarter of the largest sensitivity")
+    flat = np.argsort(sens)[::-1][:8]
     results = []
     for idx in flat:
         k, p = np.unravel_index(idx, g.shape)
