@@ -696,7 +696,10 @@ def main_adjoint(args, log):
     s = DGSolver("elastic", N, mesh.elem_xyz, mesh.elem_topo)
     s.set_coefficients(torch.tensor(coef * blob[:, None].astype(np.float32), device="cuda"))
     s.set_fields(torch.zeros(s.field_shape, device="cuda"))
-    chosen = s.autotune(2, dt, FP32_VARIANTS + ("mfma_f16",) if args.variant == "auto-mixed" else FP32_VARIANTS)
+    # misfits refuse the FP16 split (the projected point source exceeds its
+    # range) and the BF16 split misses the 1e-4 target here, so the FP32
+    # variants compete in either mode
+    chosen = s.autotune(2, dt, FP32_VARIANTS)
     f = DGMisfit(s, steps, dt, [0.5, 0.5, 0.5], wav, rec, checkpoint_every=20)
     data, _ = f.forward()
     s.set_coefficients(torch.tensor(coef, device="cuda"))
@@ -803,7 +806,7 @@ def main(argv=None):
         "--variant", choices=["valu", "mfma", "mfma_bf16", "mfma_f16", "elem", "auto", "auto-mixed"], default="auto",
         help="kernel variant for every degree; 'auto' lets the autotuner pick among the FP32 variants per "
         "degree, 'auto-mixed' also among the split-product variants (the sweep admits those within 1e-4 of the "
-        "FP64 oracle on its meshes; the batched and adjoint workloads admit FP16 only)",
+        "FP64 oracle on its meshes; the batched workload admits FP16 only, the adjoint workload none)",
     )
     ap.add_argument(
         "--variant-map", type=str, default="",

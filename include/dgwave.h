@@ -186,7 +186,13 @@ dg_status dg_set_stream(dg_solver* s, void* stream);
  *   DG_VARIANT_MFMA_BF16  BF16 matrix cores with FP32 accumulation, both
  *                         operands split x = x_hi + x_lo and the products
  *                         D_hi x_hi + D_hi x_lo + D_lo x_hi;
- *   DG_VARIANT_MFMA_F16   the same with FP16 halves;
+ *   DG_VARIANT_MFMA_F16   the same with FP16 halves, which need field and
+ *                         face-penalty values well inside FP16's range: a
+ *                         value beyond 65504 overflows (the results turn
+ *                         non-finite and dg_energy reports DG_E_UNSTABLE),
+ *                         and below about 1e-3 the lo half is subnormal and
+ *                         the products lose accuracy (O(1) amplitudes give
+ *                         the 1e-5 relative accuracy of the other variants);
  *   DG_VARIANT_ELEM       one element per thread, all in registers
  *                         (acoustic N = 1, 2; elastic N = 1);
  *   DG_VARIANT_MFMA_WIDE  FP32 matrix cores with the other acoustic tile
@@ -352,7 +358,9 @@ dg_status dg_debug_buffer(dg_solver* s, const char* name, void* dst, size_t* byt
  * microseconds per step of each variant, -1 where not built or not a
  * candidate.  The choice of
  * kernel per degree and mesh follows the observation of Sec. 4 that the best
- * implementation strategy depends on the degree.  Errors: DG_E_STATE (no
+ * implementation strategy depends on the degree.  The autotuner compares
+ * speed only: leave the split 16-bit variants out of `candidates` unless the
+ * fields suit them (see dg_set_variant).  Errors: DG_E_STATE (no
  * coefficients or fields), DG_E_ARG, DG_E_HIP.                              */
 #define DG_NUM_VARIANTS 6
 dg_status dg_autotune(dg_solver* s, int steps, double dt, unsigned candidates, void* scratch,
@@ -456,7 +464,10 @@ int64_t dg_misfit_channels(dg_misfit* f);
  * float32 [nsteps+1][channels], may be NULL) is copied; traces (device
  * float32 [nsteps+1][channels], may be NULL) receives the receiver values;
  * *J (host, may be NULL) the misfit against data (0 without data; the call
- * then synchronises).  Errors: DG_E_STATE (no coefficients), DG_E_HIP.      */
+ * then synchronises).  Errors: DG_E_STATE (no coefficients),
+ * DG_E_UNSUPPORTED (the solver's variant is DG_VARIANT_MFMA_F16, whose FP16
+ * operands cannot hold the projected point source), DG_E_UNSTABLE (J not
+ * finite), DG_E_HIP.                                                        */
 dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, double* J);
 
 /* Gradient of J with respect to the per-element coefficients (acoustic
@@ -468,7 +479,7 @@ dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, doub
  * the upwind penalty are accumulated per element in float64.  Needs a
  * preceding dg_misfit_forward with data; DG_E_STATE if there was none or if
  * dg_set_coefficients was called on the solver after it.  Errors:
- * DG_E_STATE, DG_E_HIP.                                                     */
+ * DG_E_STATE, DG_E_UNSUPPORTED (as dg_misfit_forward), DG_E_HIP.           */
 dg_status dg_misfit_gradient(dg_misfit* f, float* grad);
 
 #ifdef __cplusplus

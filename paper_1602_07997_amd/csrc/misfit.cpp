@@ -351,6 +351,18 @@ void dg_misfit_destroy(dg_misfit* f) {
 
 int64_t dg_misfit_channels(dg_misfit* f) { return f ? f->R : -1; }
 
+// The projected point source b = (1/J_k) M^-1 l(x_s) grows with the mesh's
+// resolution far beyond FP16's range, so the FP16 split products, whose
+// operands must stay below 65504, are refused for misfits.
+static dg_status check_misfit_variant(const dg_solver* s) {
+  if (s->variant == dgw::kVariantMfmaF16) {
+    set_error("misfits need a variant with the FP32 exponent range (the FP16 split products overflow on the "
+              "projected point source): use DG_VARIANT_VALU, _MFMA, _MFMA_BF16 or _ELEM");
+    return DG_E_UNSUPPORTED;
+  }
+  return DG_OK;
+}
+
 dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, double* J) {
   if (!f) {
     set_error("null misfit");
@@ -361,6 +373,7 @@ dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, doub
     set_error("set coefficients before the misfit");
     return DG_E_STATE;
   }
+  if (dg_status st = check_misfit_variant(s)) return st;
   const size_t ntrace = static_cast<size_t>(f->M + 1) * f->R;
   // zero state, zero history, zero traces
   DG_HIP(dgw::launch_fill_zero_f32(static_cast<int64_t>(f->nq), seg_q(f, 0), s->stream));
@@ -402,6 +415,10 @@ dg_status dg_misfit_forward(dg_misfit* f, const float* data, float* traces, doub
         acc += r * r;
       }
       *J = 0.5 * f->dt * acc;
+      if (!std::isfinite(*J)) {
+        set_error("dg_misfit_forward: the misfit is not finite");
+        return DG_E_UNSTABLE;
+      }
     }
   } else if (J) {
     *J = 0.0;
@@ -419,6 +436,7 @@ dg_status dg_misfit_gradient(dg_misfit* f, float* grad) {
     return DG_E_STATE;
   }
   dg_solver* s = f->s;
+  if (dg_status st = check_misfit_variant(s)) return st;
   if (s->coef_gen != f->fwd_coef_gen) {
     set_error("dg_misfit_gradient: the coefficients changed after the last dg_misfit_forward");
     return DG_E_STATE;

@@ -76,6 +76,29 @@ def test_misfit_forward_matches_oracle(physics, N):
     assert J == pytest.approx(J_ref, rel=1e-3)
 
 
+def test_misfit_refuses_the_fp16_split_variant():
+    """The projected point source exceeds FP16's range, so a solver on the
+    FP16 split products gets DG_E_UNSUPPORTED from the misfit calls (the
+    BF16 split, with FP32's exponent range, runs)."""
+    from paper_1602_07997_amd import _native as nat
+
+    _, coef, pr, data, s, f = _setup("acoustic", 2, steps=10)
+    d = torch.tensor(data[: 11], dtype=torch.float32, device="cuda")
+    s.variant = "mfma_f16"
+    with pytest.raises(nat.DGError) as ei:
+        f.forward(d)
+    assert ei.value.status == nat.DG_E_UNSUPPORTED
+    s.variant = "mfma_bf16"
+    _, J = f.forward(d)
+    assert np.isfinite(J) and J > 0.0
+    s.variant = "mfma_f16"
+    with pytest.raises(nat.DGError) as ei:
+        f.gradient()
+    assert ei.value.status == nat.DG_E_UNSUPPORTED
+    s.variant = "valu"
+    assert np.all(np.isfinite(f.gradient().cpu().numpy()))
+
+
 @pytest.mark.parametrize("physics,N", [("acoustic", 2), ("acoustic", 3), ("elastic", 2), ("elastic", 3)])
 def test_gradient_matches_complex_step(physics, N):
     log(f"adjoint gradient {physics} N={N}")
