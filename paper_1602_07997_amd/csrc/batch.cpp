@@ -29,7 +29,7 @@ struct dg_batch_group {
   dgw::StepArgs* args = nullptr;      // device [members][kBatchPhases], in the workspace
   int2* work = nullptr;               // device [nwork] (member slot, tile), in the workspace
   int64_t tiles = 0;                  // real work items
-  int64_t nwork = 0;                  // launched workgroups (padded to 8)
+  int64_t nwork = 0;                  // launched workgroups (one per work item)
 };
 
 struct dg_batch {
@@ -72,8 +72,8 @@ int64_t max_member_tiles(int physics, const dg_solver* s) {
 }
 
 // Workspace bytes that cover every grouping of the members: at most one group
-// per member, each group's work list padded to a multiple of 8 workgroups,
-// plus the alignment of every array.
+// per member, each group's work list (rounded up to 8 entries), plus the
+// alignment of every array.
 size_t batch_bytes(int physics, dg_solver* const* members, int count) {
   size_t bytes = 0;
   for (int i = 0; i < count; ++i) {
@@ -90,20 +90,6 @@ void drop_graph(dg_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-}
-
-// Workgroup b of a launch of n tiles runs work item xcd_order(b): the
-// hardware deals workgroups round-robin to the 8 XCDs, so giving XCD x the
-// items [x*per, (x+1)*per) keeps an element's neighbours in one L2.
-std::vector<int2> xcd_order(const std::vector<int2>& items) {
-  const int64_t n = static_cast<int64_t>(items.size());
-  const int64_t per = (n + 7) / 8;
-  std::vector<int2> out(static_cast<size_t>(per * 8), int2{-1, 0});
-  for (int64_t w = 0; w < per * 8; ++w) {
-    const int64_t item = (w % 8) * per + w / 8;
-    if (item < n) out[static_cast<size_t>(w)] = items[static_cast<size_t>(item)];
-  }
-  return out;
 }
 
 dg_status build_groups(dg_batch* b) {
@@ -145,7 +131,10 @@ dg_status build_groups(dg_batch* b) {
       }
     }
     g.tiles = static_cast<int64_t>(items.size());
-    const std::vector<int2> work = xcd_order(items);
+    // launch order = (member, tile) order: the tiles in flight stay one
+    // contiguous window of each member's arrays (a per-XCD split of the list
+    // measured 1.5 % slower)
+    const std::vector<int2>& work = items;
     g.nwork = static_cast<int64_t>(work.size());
     if (g.nwork > 0x7fffffff) {
       set_error("batch launch too large");

@@ -34,7 +34,7 @@ struct StepArgs {
   const uint16_t* L16l;
   float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
   int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))
-  int xcd_remap;         // map consecutive tiles onto one XCD
+  int xcd_remap;         // 1: give each XCD a contiguous range of tiles (0: launch order)
 };
 
 constexpr int kStepMode = 0;

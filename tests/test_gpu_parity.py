@@ -336,16 +336,19 @@ def test_all_face_orientations_parity(physics, variant, N, periodic):
     c.check(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt), tol_q, "20 steps")
 
 
-@pytest.mark.parametrize("physics,N,dims", [
-    ("elastic", 7, (9, 9, 9)), ("elastic", 8, (9, 9, 9)), ("anisotropic", 7, (9, 9, 9)), ("acoustic", 7, (11, 12, 12)),
+@pytest.mark.parametrize("physics,N,dims,remap", [
+    ("elastic", 7, (9, 9, 9), "0"), ("elastic", 8, (9, 9, 9), "1"), ("anisotropic", 7, (9, 9, 9), "1"),
+    ("acoustic", 7, (11, 12, 12), "0"), ("acoustic", 7, (11, 12, 12), "1"),
 ])
-def test_mfma_short_last_round_parity(physics, N, dims):
+def test_mfma_short_last_round_parity(physics, N, dims, remap, monkeypatch):
     """Meshes whose 16-element tiles fill the MI355X's resident workgroups
     (256 compute units times one, or two for acoustic N = 7) once or twice
     plus a short last round (274 tiles for 256 slots, 594 for 512), with the
-    tiles mapped onto the XCDs in contiguous ranges: one RHS and 10 AB3
+    tiles in launch order or (DGWAVE_XCD_REMAP=1, read when the solver is
+    created) each XCD given a contiguous range of tiles: one RHS and 10 AB3
     steps against the oracle."""
-    log(f"short last round {physics} N={N} dims={dims}")
+    log(f"short last round {physics} N={N} dims={dims} remap={remap}")
+    monkeypatch.setenv("DGWAVE_XCD_REMAP", remap)
     c = Case(physics, N, None, jitter=0.1, seed=95 + N, coef_kind="random", init="smooth", dims=dims)
     c.solver.variant = "mfma"
     r = c.solver.rhs(c.to_gpu(c.q0_gpu))
