@@ -168,6 +168,7 @@ StepArgs base_args(const dg_solver* s) {
   a.L16h = s->L16[p16][0];
   a.L16l = s->L16[p16][1];
   a.xcd_remap = s->xcd_remap;
+  a.tail_split = s->tail_split;
   return a;
 }
 
@@ -377,6 +378,7 @@ dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz, c
   s->conn_h = conn;
   (void)hipGetDevice(&s->device);
   if (const char* env = std::getenv("DGWAVE_XCD_REMAP")) s->xcd_remap = (std::atoi(env) != 0);
+  if (const char* env = std::getenv("DGWAVE_TAIL_SPLIT")) s->tail_split = (std::atoi(env) != 0);
   dgw::Arena arena(workspace, workspace_bytes);
   layout(s, t, ref, arena);
   if (!arena.fits()) {

@@ -336,19 +336,24 @@ def test_all_face_orientations_parity(physics, variant, N, periodic):
     c.check(q, AB3Stepper(c.oracle, c.q0).step(20, c.dt), tol_q, "20 steps")
 
 
-@pytest.mark.parametrize("physics,N,dims,remap", [
-    ("elastic", 7, (9, 9, 9), "0"), ("elastic", 8, (9, 9, 9), "1"), ("anisotropic", 7, (9, 9, 9), "1"),
-    ("acoustic", 7, (11, 12, 12), "0"), ("acoustic", 7, (11, 12, 12), "1"),
+@pytest.mark.parametrize("physics,N,dims,remap,split", [
+    ("elastic", 7, (9, 9, 9), "0", "1"), ("elastic", 7, (9, 9, 9), "0", "0"), ("elastic", 8, (9, 9, 9), "1", "1"),
+    ("elastic", 8, (9, 9, 9), "0", "1"), ("anisotropic", 7, (9, 9, 9), "1", "1"),
+    ("anisotropic", 8, (9, 9, 9), "0", "1"),
+    ("acoustic", 7, (11, 12, 12), "0", "1"), ("acoustic", 7, (11, 12, 12), "1", "1"),
 ])
-def test_mfma_short_last_round_parity(physics, N, dims, remap, monkeypatch):
+def test_mfma_short_last_round_parity(physics, N, dims, remap, split, monkeypatch):
     """Meshes whose 16-element tiles fill the MI355X's resident workgroups
     (256 compute units times one, or two for acoustic N = 7) once or twice
     plus a short last round (274 tiles for 256 slots, 594 for 512), with the
     tiles in launch order or (DGWAVE_XCD_REMAP=1, read when the solver is
-    created) each XCD given a contiguous range of tiles: one RHS and 10 AB3
-    steps against the oracle."""
-    log(f"short last round {physics} N={N} dims={dims} remap={remap}")
+    created) each XCD given a contiguous range of tiles, and the elastic
+    kernels' last-round tiles split over two or three workgroups (launch
+    order; DGWAVE_TAIL_SPLIT=0 keeps them whole): one RHS and 10 AB3 steps
+    against the oracle."""
+    log(f"short last round {physics} N={N} dims={dims} remap={remap} split={split}")
     monkeypatch.setenv("DGWAVE_XCD_REMAP", remap)
+    monkeypatch.setenv("DGWAVE_TAIL_SPLIT", split)
     c = Case(physics, N, None, jitter=0.1, seed=95 + N, coef_kind="random", init="smooth", dims=dims)
     c.solver.variant = "mfma"
     r = c.solver.rhs(c.to_gpu(c.q0_gpu))
@@ -357,3 +362,27 @@ def test_mfma_short_last_round_parity(physics, N, dims, remap, monkeypatch):
     c.solver.set_fields(c.to_gpu(c.q0_gpu))
     c.solver.step(10, c.dt)
     c.check(c.to_host(c.solver.get_fields()), AB3Stepper(c.oracle, c.q0).step(10, c.dt), 1e-5, "10 steps")
+
+
+@pytest.mark.parametrize("physics,N,variant,dims", [
+    ("elastic", 6, "mfma", (4, 4, 4)), ("elastic", 7, "mfma", (4, 4, 4)), ("elastic", 8, "mfma", (3, 4, 4)),
+    ("elastic", 8, "mfma_f16", (3, 4, 4)), ("anisotropic", 8, "mfma", (3, 3, 4)),
+])
+def test_tail_split_matches_whole_tiles(physics, N, variant, dims, monkeypatch):
+    """A mesh smaller than one round of workgroups: every tile of the elastic
+    MFMA kernels shared by two or three workgroups, each taking a range of
+    the tile's (node block, element block) pairs (default), or kept whole
+    (DGWAVE_TAIL_SPLIT=0).  Each pair's arithmetic is the same either way, so
+    the fields after 10 AB3 steps are identical; both against the oracle."""
+    log(f"tail split {physics} N={N} {variant} dims={dims}")
+    out = []
+    for split in ("1", "0"):
+        monkeypatch.setenv("DGWAVE_TAIL_SPLIT", split)
+        c = Case(physics, N, None, jitter=0.1, seed=97 + N, coef_kind="random", init="smooth", dims=dims)
+        c.solver.variant = variant
+        c.solver.set_fields(c.to_gpu(c.q0_gpu))
+        c.solver.step(10, c.dt)
+        out.append(c.solver.get_fields().clone())
+    assert torch.equal(out[0], out[1])
+    tol = 1e-5 if variant == "mfma" else 1e-4
+    c.check(c.to_host(out[0]), AB3Stepper(c.oracle, c.q0).step(10, c.dt), tol, "10 steps")
