@@ -35,8 +35,8 @@ struct StepArgs {
   float c0, c1, c2;      // dt*a1, dt*a2, dt*a3
   int mode;              // 0: AB3 step, 1: right-hand side only (r_out = r(q_in))
   int xcd_remap;         // 1: give each XCD a contiguous range of tiles (0: launch order)
-  int tail_split;        // 1: the elastic MFMA launcher may split a last, partial round of tiles
-  // set by that launcher: from tile split_from on, each tile is shared by
+  int tail_split;        // 1: the MFMA launchers may split a last, partial round of tiles
+  // set by those launchers: from tile split_from on, each tile is shared by
   // split_parts workgroups, each taking a contiguous range of the tile's
   // (node block, element block) pairs (split_parts <= 1: no split)
   int split_parts;

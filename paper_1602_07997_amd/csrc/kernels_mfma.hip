@@ -131,8 +131,11 @@ struct BRegion {
   }
 };
 
+// Pairs [p0, p1) of the tile's (node block, element block) pairs: all of
+// them, or a part of a tile split over several workgroups (every workgroup
+// of a split tile stages the whole tile and writes only its pairs' nodes)
 template <int N, int CFG>
-__device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) {
+__device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile, int p0, int p1) {
   using S = MShape<N, CFG>;
   constexpr int PREC = S::P;
   constexpr int NP = S::NP, NFP = S::NFP, MB = S::MB, KP = S::KP, KL = S::KL, KF = S::KF, E = S::E;
@@ -343,9 +346,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   floatx4 T0[PPW], T1[PPW], T2[PPW], DV[PPW];
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
-    const int p = wave + NW * q;
+    const int p = p0 + wave + NW * q;
     T0[q] = T1[q] = T2[q] = DV[q] = floatx4{0, 0, 0, 0};
-    if (p >= S::PAIRS) continue;
+    if (p >= p1) continue;
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + (lane & 15);
     if constexpr (PREC == 0) {
@@ -453,8 +456,8 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
   const int nl = lane & 15, eg = lane >> 4;
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
-    const int p = wave + NW * q;
-    if (p >= S::PAIRS) continue;
+    const int p = p0 + wave + NW * q;
+    if (p >= p1) continue;
     const int mb = p % MB, nb = p / MB;
     const int col = nb * 16 + nl;
     // per-face LIFT of the two penalty scalars; k-steps never straddle a
@@ -611,7 +614,9 @@ __device__ __forceinline__ void step_mfma_tile(const StepArgs& a, int64_t tile) 
 template <int N, int CFG>
 __global__ void __launch_bounds__((MShape<N, CFG>::THREADS), (acoustic_min_waves(N, cfg_prec(CFG))))
 dg_step_mfma_acoustic(StepArgs a) {
-  step_mfma_tile<N, CFG>(a, tile_of_block(a.xcd_remap));
+  int p0, p1;
+  const int64_t tile = split_tile(tile_of_block(a.xcd_remap), a.split_from, a.split_parts, MShape<N, CFG>::PAIRS, p0, p1);
+  step_mfma_tile<N, CFG>(a, tile, p0, p1);
 }
 
 template <int N, int CFG>
@@ -620,7 +625,7 @@ dg_step_mfma_acoustic_batch(const StepArgs* __restrict__ args, const int2* __res
   const int2 w = work[blockIdx.x];
   if (w.x < 0) return;  // padding entry of the work list
   const StepArgs a = args[w.x * kBatchPhases + phase];
-  step_mfma_tile<N, CFG>(a, w.y);
+  step_mfma_tile<N, CFG>(a, w.y, 0, MShape<N, CFG>::PAIRS);
 }
 
 template <int N, int CFG>
@@ -632,13 +637,26 @@ hipError_t mfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntile
   return hipGetLastError();
 }
 
+// A short last round of tiles is split over up to ceil(pairs / wavefronts)
+// workgroups per tile, so that each wavefront of a part runs at most one
+// pair (tiles in launch order only).
 template <int N, int CFG>
 hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
-  constexpr int E = MShape<N, CFG>::E;
-  int64_t tiles = (a.K - a.e_begin + E - 1) / E;
+  using S = MShape<N, CFG>;
+  int64_t tiles = (a.K - a.e_begin + S::E - 1) / S::E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
-  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, CFG>), dim3(static_cast<unsigned>(tiles)), dim3(MShape<N, CFG>::THREADS), 0, s, a);
+  StepArgs b = a;
+  TailSplit plan{tiles, tiles, 1};
+  if (a.tail_split && !a.xcd_remap) {
+    static std::atomic<int> slots_cache[16];
+    const int slots =
+        resident_workgroups(reinterpret_cast<const void*>(&dg_step_mfma_acoustic<N, CFG>), S::THREADS, slots_cache);
+    plan = plan_tail_split(tiles, slots, (S::PAIRS + S::NW - 1) / S::NW);
+  }
+  b.split_from = plan.from;
+  b.split_parts = plan.parts;
+  if (plan.grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_step_mfma_acoustic<N, CFG>), dim3(static_cast<unsigned>(plan.grid)), dim3(S::THREADS), 0, s, b);
   return hipGetLastError();
 }
 

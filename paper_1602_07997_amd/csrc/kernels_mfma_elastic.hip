@@ -31,7 +31,6 @@
 //       scratch, AB3 update, q / r writes, own traces), pair by pair.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <cstdint>
 
 #include "dg_device.hpp"
@@ -692,20 +691,9 @@ __device__ __forceinline__ void step_mfma_elastic_tile(const StepArgs& a, int64_
 template <int N, int PREC, int PHYS>
 __global__ void __launch_bounds__((elastic_threads<N, PREC>()), (elastic_min_waves<N, PREC>()))
 dg_step_mfma_elastic(StepArgs a) {
-  constexpr int P = EShape<N, PREC, PHYS>::PAIRS;
-  int64_t tile;
-  int p0 = 0, p1 = P;
-  const int64_t b = blockIdx.x;
-  if (a.split_parts > 1 && b >= a.split_from) {
-    // the last round's tiles, split_parts workgroups each
-    const int64_t t = b - a.split_from;
-    const int j = static_cast<int>(t % a.split_parts);
-    tile = a.split_from + t / a.split_parts;
-    p0 = j * P / a.split_parts;
-    p1 = (j + 1) * P / a.split_parts;
-  } else {
-    tile = tile_of_block(a.xcd_remap);
-  }
+  int p0, p1;
+  const int64_t tile = split_tile(tile_of_block(a.xcd_remap), a.split_from, a.split_parts,
+                                  EShape<N, PREC, PHYS>::PAIRS, p0, p1);
   step_mfma_elastic_tile<N, PREC, PHYS>(a, tile, p0, p1);
 }
 
@@ -718,63 +706,26 @@ dg_step_mfma_elastic_batch(const StepArgs* __restrict__ args, const int2* __rest
   step_mfma_elastic_tile<N, PREC, PHYS>(a, w.y, 0, EShape<N, PREC, PHYS>::PAIRS);
 }
 
-// Workgroups of the kernel resident on the current device at once (its
-// occupancy times the compute units), cached per device; 0 when unknown.
-template <int N, int PREC, int PHYS>
-int resident_workgroups() {
-  constexpr int kDevices = 16;
-  static std::atomic<int> cache[kDevices];
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  if (dev >= 0 && dev < kDevices) {
-    const int c = cache[dev].load(std::memory_order_relaxed);
-    if (c > 0) return c;
-  }
-  int occ = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(&dg_step_mfma_elastic<N, PREC, PHYS>),
-                                                   elastic_threads<N, PREC>(), 0) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  const int slots = occ > 0 && cus > 0 ? occ * cus : 0;
-  if (slots > 0 && dev >= 0 && dev < kDevices) cache[dev].store(slots, std::memory_order_relaxed);
-  return slots;
-}
-
-// The tiles of a last, partial round of workgroups (all tiles when they do
-// not fill one round) are split over up to ceil(pairs / 4) workgroups, so
-// that each part runs at most one pair's products per SIMD, as far as the
-// free slots of that round allow.  Tiles in launch order only.
+// A short last round of tiles is split over up to ceil(pairs / 4)
+// workgroups per tile, so that each part runs at most one pair's products
+// per SIMD (tiles in launch order only).
 template <int N, int PREC, int PHYS = 1>
 hipError_t emfma_impl(const StepArgs& a, hipStream_t s) {
   constexpr int E = EShape<N, PREC, PHYS>::E, P = EShape<N, PREC, PHYS>::PAIRS;
   int64_t tiles = (a.K - a.e_begin + E - 1) / E;
   if (a.xcd_remap) tiles = ((tiles + 7) / 8) * 8;
   StepArgs b = a;
-  b.split_parts = 1;
-  b.split_from = tiles;
-  int64_t grid = tiles;
-  constexpr int kMaxParts = (P + 3) / 4;
-  if (kMaxParts > 1 && a.tail_split && !a.xcd_remap && tiles > 0) {
-    const int slots = resident_workgroups<N, PREC, PHYS>();
-    if (slots > 0) {
-      const int64_t full = ((tiles - 1) / slots) * slots;
-      const int64_t tail = tiles - full;
-      const int64_t fit = slots / tail;
-      const int parts = static_cast<int>(fit < kMaxParts ? fit : kMaxParts);
-      if (parts > 1) {
-        b.split_parts = parts;
-        b.split_from = full;
-        grid = full + tail * parts;
-      }
-    }
+  TailSplit plan{tiles, tiles, 1};
+  if (a.tail_split && !a.xcd_remap) {
+    static std::atomic<int> slots_cache[16];
+    const int slots = resident_workgroups(reinterpret_cast<const void*>(&dg_step_mfma_elastic<N, PREC, PHYS>),
+                                          elastic_threads<N, PREC>(), slots_cache);
+    plan = plan_tail_split(tiles, slots, (P + 3) / 4);
   }
-  if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC, PHYS>), dim3(static_cast<unsigned>(grid)),
+  b.split_from = plan.from;
+  b.split_parts = plan.parts;
+  if (plan.grid > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dg_step_mfma_elastic<N, PREC, PHYS>), dim3(static_cast<unsigned>(plan.grid)),
                      dim3(elastic_threads<N, PREC>()), 0, s, b);
   return hipGetLastError();
 }

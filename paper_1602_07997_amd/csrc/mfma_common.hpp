@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 namespace dgw {
@@ -17,6 +18,70 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+// ---- host side: splitting a short last round of workgroups ----------------
+
+// Workgroups of `kernel` (launched with `threads` threads) resident on the
+// current device at once: its occupancy times the compute units, cached per
+// device in `cache` (one array per kernel); 0 when unknown.
+template <int kDevices>
+inline int resident_workgroups(const void* kernel, int threads, std::atomic<int> (&cache)[kDevices]) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (dev >= 0 && dev < kDevices) {
+    const int c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int occ = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int slots = occ > 0 && cus > 0 ? occ * cus : 0;
+  if (slots > 0 && dev >= 0 && dev < kDevices) cache[dev].store(slots, std::memory_order_relaxed);
+  return slots;
+}
+
+// Launch plan of `tiles` tiles on `slots` resident workgroups: the tiles of
+// the last, partial round (all tiles when they do not fill one round) are
+// each shared by `parts` workgroups, as many as the free slots of that round
+// allow, up to max_parts; the workgroup for part j of such a tile takes its
+// pairs [j P / parts, (j + 1) P / parts).  parts = 1: one workgroup per tile.
+struct TailSplit {
+  int64_t grid;  // workgroups to launch
+  int64_t from;  // first split tile (= tiles when none is split)
+  int parts;
+};
+
+inline TailSplit plan_tail_split(int64_t tiles, int slots, int max_parts) {
+  TailSplit t{tiles, tiles, 1};
+  if (max_parts <= 1 || slots <= 0 || tiles <= 0) return t;
+  const int64_t full = ((tiles - 1) / slots) * slots;
+  const int64_t tail = tiles - full;
+  const int64_t fit = slots / tail;
+  const int parts = static_cast<int>(fit < max_parts ? fit : max_parts);
+  if (parts > 1) t = TailSplit{full + tail * parts, full, parts};
+  return t;
+}
+
+// Device side: the tile and pair range [p0, p1) of workgroup blockIdx.x of a
+// launch planned by plan_tail_split (split_parts <= 1: whole tiles).
+__device__ __forceinline__ int64_t split_tile(int64_t whole_tile, int64_t split_from, int split_parts, int pairs,
+                                              int& p0, int& p1) {
+  const int64_t b = blockIdx.x;
+  p0 = 0;
+  p1 = pairs;
+  if (split_parts <= 1 || b < split_from) return whole_tile;
+  const int64_t t = b - split_from;
+  const int j = static_cast<int>(t % split_parts);
+  p0 = j * pairs / split_parts;
+  p1 = (j + 1) * pairs / split_parts;
+  return split_from + t / split_parts;
+}
 
 // Column swizzle of the FP32 [row][E] operand arrays: a bijection on [0, E)
 // per row that keeps the fragment reads conflict-free and spreads the

@@ -64,7 +64,7 @@ struct dg_solver {
   // (1, environment DGWAVE_XCD_REMAP=1): launch order measured 1-5 % faster
   // on the ~2M-node meshes at every degree
   int xcd_remap = 0;
-  // a last, partial round of elastic MFMA workgroups split by tile pairs
+  // a last, partial round of MFMA workgroups split by tile pairs
   // over more compute units (1; environment DGWAVE_TAIL_SPLIT=0 turns it off)
   int tail_split = 1;
   int variant = 0;
