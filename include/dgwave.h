@@ -164,9 +164,14 @@ dg_status dg_workspace_bytes(int physics, int order, int64_t K, size_t* bytes);
  * the caller, outliving the solver).  `stream` is a hipStream_t (NULL =
  * default stream) used by every later call; the call synchronises it.  K must
  * lie in [1, 2^26) (the per-face connectivity word packs the neighbour index
- * in 26 bits).  Errors: DG_E_ARG (K out of range, null or misaligned arrays),
- * DG_E_SHAPE (workspace too small), DG_E_UNSUPPORTED, DG_E_MESH (J <= 0,
- * inconsistent face pairing), DG_E_HIP.                                     */
+ * in 26 bits).  Two launch options are read from the environment here,
+ * neither of which changes any result: DGWAVE_XCD_REMAP=1 gives each XCD a
+ * contiguous range of tiles (default: launch order), DGWAVE_TAIL_SPLIT=0
+ * keeps the tiles of a short last round of MFMA workgroups whole (default:
+ * shared by two or three workgroups where a tile has more (node block,
+ * element block) pairs than wavefronts).  Errors: DG_E_ARG (K out of range,
+ * null or misaligned arrays), DG_E_SHAPE (workspace too small),
+ * DG_E_UNSUPPORTED, DG_E_MESH (J <= 0, inconsistent face pairing), DG_E_HIP. */
 dg_status dg_create(int physics, int order, int64_t K, const double* elem_xyz,
                     const int64_t* elem_topo, void* workspace, size_t workspace_bytes, void* stream,
                     dg_solver** out);
