@@ -138,7 +138,7 @@ struct GradArgs {
   const int32_t* conn;
   const int32_t* fmask;
   const int32_t* perm;
-  const float* mass;      // [Np][Np]
+  const float* mass_pack; // M as 16x4 FP32 fragments [MB][KP/4][64] (MB = ceil(Np/16), KP = Np rounded up to 4)
   const float* face_mass; // [Nfp][Nfp]
   const double* J;        // [K]
   double* gacc;           // [K][kGradAccStride]

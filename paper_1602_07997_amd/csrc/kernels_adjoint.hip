@@ -30,6 +30,7 @@
 
 #include "dg_device.hpp"
 #include "kernels.hpp"
+#include "mfma_common.hpp"
 
 namespace dgw {
 
@@ -38,12 +39,6 @@ namespace {
 using namespace dev;
 
 constexpr int kWave = 64;
-
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // Own traces of element k of field array q (the step kernel's convention).
 template <int N, int PHYS>
@@ -117,8 +112,11 @@ dg_record_kernel(int nch, const float* __restrict__ q, const int64_t* __restrict
 
 // One wavefront per element.  Every global load is issued up front (the
 // element's accumulators, chi from the three adjoint states, r, the own and
-// neighbour traces of all four faces); the mass products read r from LDS and
-// the faces are processed together, one face node per lane.
+// neighbour traces of all four faces); the mass products M r run on the
+// matrix cores (M in 16x4 FP32 fragments, r from LDS, one column per field
+// and, elastic, one for r_s11 + r_s22 + r_s33), the faces are processed
+// together, one face node per lane, and the per-lane partial sums are added
+// up through LDS.
 template <int N, int PHYS>
 __global__ void __launch_bounds__(kWave)
 dg_grad_accum_kernel(const GradArgs a) {
@@ -128,8 +126,14 @@ dg_grad_accum_kernel(const GradArgs a) {
   constexpr int NACC = (PHYS == 0) ? 10 : 19;  // accumulators used
   constexpr int NQ = (PHYS == 0) ? 2 : 4;      // face quantities: gm (P, S), gp (P, S)
   constexpr int FIT = (4 * NFP + kWave - 1) / kWave;
+  constexpr int MB = (NP + 15) / 16, KP = (NP + 3) / 4 * 4;  // fragments of M
+  constexpr int NCOL = PHYS == 0 ? NF : NF + 1;               // columns of M r
+  constexpr int NRED = PHYS == 0 ? 2 : 3;                     // volume sums before the face sums
+  // r (NCOL columns, then zeros up to the last fragment's k), later the
+  // per-lane partial sums [NACC][kWave + 1]
+  constexpr int SR = NCOL * NP + 4, SRED = NACC * (kWave + 1);
   __shared__ float s_chi[NF * NP];
-  __shared__ float s_r[NF * NP];
+  __shared__ float s_r[SR > SRED ? SR : SRED];
   __shared__ float s_jump[4 * NJ * NFP];
   __shared__ double s_out[kGradAccStride];
   const int64_t k = blockIdx.x;
@@ -225,30 +229,51 @@ dg_grad_accum_kernel(const GradArgs a) {
       }
     }
   }
+  if (lane < 4) s_r[NCOL * NP + lane] = 0.0f;
   __syncthreads();
+  if constexpr (PHYS == 1) {
+    for (int m = lane; m < NP; m += kWave) s_r[NF * NP + m] = s_r[3 * NP + m] + s_r[4 * NP + m] + s_r[5 * NP + m];
+    __syncthreads();
+  }
 
   // ---- mass-weighted products of chi and r = A q ---------------------------
+  // y = M [r_0 .. r_(NF-1) (, r_3 + r_4 + r_5)] node block by node block:
+  // lane (kq, col) holds y[mb*16 + 4 kq + i][col], i < 4, and weighs it with
+  // chi of the same node and field: acoustic p -> t0, v -> t1; elastic v ->
+  // t0, s -> t1 (shear entries twice), the trace column -> t2
   float t0 = 0.f, t1 = 0.f, t2 = 0.f;
-  for (int n = lane; n < NP; n += kWave) {
-    float mr[NF];
+  {
+    using mfma::floatx4;
+    const int col = lane & 15, kq = lane >> 4;
+    const int bcol = col < NCOL ? col : 0;
+    const float bsel = col < NCOL ? 1.0f : 0.0f;
+    const float* Mp = a.mass_pack + lane;
+#pragma unroll 1
+    for (int mb = 0; mb < MB; ++mb) {
+      floatx4 y = floatx4{0, 0, 0, 0};
 #pragma unroll
-    for (int c = 0; c < NF; ++c) mr[c] = 0.f;
-    // M is symmetric: column n of M, contiguous across the lanes
-#pragma unroll 8
-    for (int m = 0; m < NP; ++m) {
-      const float w = a.mass[m * NP + n];
+      for (int kk = 0; kk < KP / 4; ++kk)
+        y = mfma::mfma_f32(Mp[(mb * (KP / 4) + kk) * 64], bsel * s_r[bcol * NP + 4 * kk + kq], y);
 #pragma unroll
-      for (int c = 0; c < NF; ++c) mr[c] += w * s_r[c * NP + m];
-    }
-    if constexpr (PHYS == 0) {
-      t0 += s_chi[n] * mr[0];
-      t1 += s_chi[NP + n] * mr[1] + s_chi[2 * NP + n] * mr[2] + s_chi[3 * NP + n] * mr[3];
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) t0 += s_chi[c * NP + n] * mr[c];
-#pragma unroll
-      for (int c = 3; c < 9; ++c) t1 += (c < 6 ? 1.0f : 2.0f) * s_chi[c * NP + n] * mr[c];
-      t2 += (s_chi[3 * NP + n] + s_chi[4 * NP + n] + s_chi[5 * NP + n]) * (mr[3] + mr[4] + mr[5]);
+      for (int i = 0; i < 4; ++i) {
+        const int n = mb * 16 + 4 * kq + i;
+        if (n >= NP || col >= NCOL) continue;
+        if constexpr (PHYS == 0) {
+          const float v = s_chi[col * NP + n] * y[i];
+          if (col == 0)
+            t0 += v;
+          else
+            t1 += v;
+        } else {
+          if (col < 3) {
+            t0 += s_chi[col * NP + n] * y[i];
+          } else if (col < 9) {
+            t1 += (col < 6 ? 1.0f : 2.0f) * s_chi[col * NP + n] * y[i];
+          } else {
+            t2 += (s_chi[3 * NP + n] + s_chi[4 * NP + n] + s_chi[5 * NP + n]) * y[i];
+          }
+        }
+      }
     }
   }
 
@@ -335,30 +360,32 @@ dg_grad_accum_kernel(const GradArgs a) {
     }
   }
   // ---- reductions and the accumulator update ---------------------------------
-  t0 = wave_sum(t0);
-  t1 = wave_sum(t1);
-  if constexpr (PHYS == 1) t2 = wave_sum(t2);
+  // the partial sums of all lanes into LDS (the r region is free now), then
+  // lane i < NACC adds up sum i: the volume sums, then face f's quantity c at
+  // NRED + f NQ + c, stored to accumulator NRED + 4 c + f
+  float* s_red = s_r;
+  __syncthreads();
+  s_red[0 * (kWave + 1) + lane] = t0;
+  s_red[1 * (kWave + 1) + lane] = t1;
+  if constexpr (PHYS == 1) s_red[2 * (kWave + 1) + lane] = t2;
 #pragma unroll
   for (int f = 0; f < 4; ++f)
 #pragma unroll
-    for (int c = 0; c < NQ; ++c) part[f][c] = wave_sum(part[f][c]);
-  if (lane == 0) {
+    for (int c = 0; c < NQ; ++c) s_red[(NRED + f * NQ + c) * (kWave + 1) + lane] = part[f][c];
+  __syncthreads();
+  if (lane < NACC) {
+    float v = 0.f;
+#pragma unroll 8
+    for (int i = 0; i < kWave; ++i) v += s_red[lane * (kWave + 1) + i];
     const double Jk = a.J[k];
-    s_out[0] = Jk * t0;
-    s_out[1] = Jk * t1;
-    if constexpr (PHYS == 1) s_out[2] = Jk * t2;
+    if (lane < NRED) {
+      s_out[lane] = Jk * v;
+    } else {
+      const int f = (lane - NRED) / NQ, c = (lane - NRED) - f * NQ;
+      float fs = 0.f;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const double sJ = Jk * static_cast<double>(fsc[f]);
-      if constexpr (PHYS == 0) {
-        s_out[2 + f] = sJ * part[f][0];
-        s_out[6 + f] = sJ * part[f][1];
-      } else {
-        s_out[3 + f] = sJ * part[f][0];
-        s_out[7 + f] = sJ * part[f][1];
-        s_out[11 + f] = sJ * part[f][2];
-        s_out[15 + f] = sJ * part[f][3];
-      }
+      for (int ff = 0; ff < 4; ++ff) fs += (f == ff) ? fsc[ff] : 0.0f;
+      s_out[NRED + 4 * c + f] = Jk * static_cast<double>(fs) * v;
     }
   }
   __syncthreads();

@@ -16,6 +16,7 @@
 #include "dg_internal.hpp"
 #include "dgwave.h"
 #include "kernels.hpp"
+#include "mfma_pack.hpp"
 #include "solver_state.hpp"
 #include "workspace.hpp"
 
@@ -170,7 +171,7 @@ struct dg_misfit {
   // adjoint
   DevBuf<float> phi, aring, atr;
   DevBuf<double> gacc;
-  DevBuf<float> mass_f, face_mass_f;
+  DevBuf<float> mass_pack_f, face_mass_f;
   size_t nq = 0, ntr = 0;
 };
 
@@ -491,7 +492,7 @@ dg_status dg_misfit_gradient(dg_misfit* f, float* grad) {
       g.conn = s->conn;
       g.fmask = s->fmask;
       g.perm = s->perm;
-      g.mass = f->mass_f.p;
+      g.mass_pack = f->mass_pack_f.p;
       g.face_mass = f->face_mass_f.p;
       g.J = s->J;
       g.gacc = f->gacc.p;
@@ -600,7 +601,9 @@ dg_status misfit_build(dg_solver* s, int64_t nsteps, double dt, int checkpoint_e
   // the adjoint source list has the receivers' shape; its values follow the
   // coefficients and are written by each gradient call
   const HostInject adj_h = adjoint_entries(f.get(), std::vector<float>(static_cast<size_t>(s->K) * s->ncoef, 1.0f));
-  std::vector<float> mf(ref->mass.begin(), ref->mass.end()), fmf(ref->face_mass.begin(), ref->face_mass.end());
+  // the mass matrix in the fragment order of the gradient kernel's products
+  std::vector<float> mf, fmf(ref->face_mass.begin(), ref->face_mass.end());
+  dgw::pack_fp32(ref->mass.data(), s->Np, s->Np, (s->Np + 15) / 16, (s->Np + 3) / 4 * 4, mf);
 
   // ---- layout in the workspace ----
   dgw::Arena arena(workspace, ws_bytes);
@@ -619,7 +622,7 @@ dg_status misfit_build(dg_solver* s, int64_t nsteps, double dt, int checkpoint_e
   f->aring.carve(arena, 3 * f->nq);
   f->atr.carve(arena, 2 * f->ntr);
   f->gacc.carve(arena, static_cast<size_t>(s->K) * dgw::kGradAccStride);
-  f->mass_f.carve(arena, mf.size());
+  f->mass_pack_f.carve(arena, mf.size());
   f->face_mass_f.carve(arena, fmf.size());
   if (need) *need = arena.used();
   if (!workspace) return DG_OK;
@@ -634,7 +637,7 @@ dg_status misfit_build(dg_solver* s, int64_t nsteps, double dt, int checkpoint_e
   if (err == hipSuccess) err = f->ch_elem.upload(che, s->stream);
   if (err == hipSuccess) err = f->ch_field.upload(chf, s->stream);
   if (err == hipSuccess) err = f->ch_w.upload(chw, s->stream);
-  if (err == hipSuccess) err = f->mass_f.upload(mf, s->stream);
+  if (err == hipSuccess) err = f->mass_pack_f.upload(mf, s->stream);
   if (err == hipSuccess) err = f->face_mass_f.upload(fmf, s->stream);
   if (err == hipSuccess) err = hipStreamSynchronize(s->stream);  // the host arrays die here
   if (err != hipSuccess) {
