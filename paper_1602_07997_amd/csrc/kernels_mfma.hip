@@ -637,9 +637,9 @@ hipError_t mfma_batch_impl(const StepArgs* args, const int2* work, int64_t ntile
   return hipGetLastError();
 }
 
-// A short last round of tiles is split over up to ceil(pairs / wavefronts)
-// workgroups per tile, so that each wavefront of a part runs at most one
-// pair (tiles in launch order only).
+// A short last round of tiles is split over up to ceil(pairs / 4)
+// workgroups per tile, so that each part runs at most one pair's products
+// per SIMD (tiles in launch order only).
 template <int N, int CFG>
 hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
   using S = MShape<N, CFG>;
@@ -651,7 +651,7 @@ hipError_t mfma_impl(const StepArgs& a, hipStream_t s) {
     static std::atomic<int> slots_cache[16];
     const int slots =
         resident_workgroups(reinterpret_cast<const void*>(&dg_step_mfma_acoustic<N, CFG>), S::THREADS, slots_cache);
-    plan = plan_tail_split(tiles, slots, (S::PAIRS + S::NW - 1) / S::NW);
+    plan = plan_tail_split(tiles, slots, (S::PAIRS + 3) / 4);
   }
   b.split_from = plan.from;
   b.split_parts = plan.parts;

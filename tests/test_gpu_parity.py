@@ -368,11 +368,12 @@ def test_mfma_short_last_round_parity(physics, N, dims, remap, split, monkeypatc
     ("elastic", 6, "mfma", (4, 4, 4)), ("elastic", 7, "mfma", (4, 4, 4)), ("elastic", 8, "mfma", (3, 4, 4)),
     ("elastic", 8, "mfma_f16", (3, 4, 4)), ("anisotropic", 8, "mfma", (3, 3, 4)),
     ("acoustic", 8, "mfma", (3, 4, 4)), ("acoustic", 8, "mfma_f16", (3, 4, 4)),
+    ("acoustic", 7, "mfma", (3, 4, 4)), ("acoustic", 6, "mfma_wide", (4, 4, 4)),
 ])
 def test_tail_split_matches_whole_tiles(physics, N, variant, dims, monkeypatch):
     """A mesh smaller than one round of workgroups: every tile of the MFMA
-    kernels with more pairs than wavefronts (elastic N = 6..8, acoustic
-    N = 8) shared by two or three workgroups, each taking a range of
+    kernels with more than four pairs (elastic N = 6..8, acoustic N = 6..8)
+    shared by two or three workgroups, each taking a range of
     the tile's (node block, element block) pairs (default), or kept whole
     (DGWAVE_TAIL_SPLIT=0).  Each pair's arithmetic is the same either way, so
     the fields after 10 AB3 steps are identical; both against the oracle."""
