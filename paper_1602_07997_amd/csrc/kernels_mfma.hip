@@ -51,10 +51,9 @@ using namespace mfma;
 
 // k-steps of operator prefetch in the FP32 products (the LIFT stream takes
 // twice as many) and in the 16-bit ones; the shallower FP32 depth at
-// N = 5..8 leaves registers for more resident wavefronts (measured 1-4%
-// faster at N = 5..7; at N = 8 it is slower with two resident workgroups
-// and, with the three that the register bound below holds, 3% faster)
-constexpr int prefetch_fp32(int N) { return (N >= 5 && N <= 8) ? 2 : 4; }
+// N = 5..7 leaves registers for more resident wavefronts (measured 1-4%
+// faster there, 3% slower at N = 8)
+constexpr int prefetch_fp32(int N) { return (N >= 5 && N <= 7) ? 2 : 4; }
 constexpr int kPrefetch16 = 1;
 
 // wavefronts per workgroup: one per (node block, element block) pair where
@@ -73,16 +72,12 @@ constexpr int acoustic_waves(int N, int PREC) {
 // per compute unit instead of four: 2-8% faster); the FP16 split products
 // would spill, so they keep the default.  FP32 at N = 6 (six wavefronts per
 // workgroup) and the split products at N = 3 sit just above the 80 / 168
-// register edges of 6 / 3 waves and are held below them, without spilling.
-// FP32 at N = 8 is held at three (three workgroups per compute unit, 88
-// bytes of spills): its 824 paper-scale tiles then take one round of 768
-// and a short split one, instead of 512 + 312 (3% faster)
+// register edges of 6 / 3 waves and are held below them, without spilling
 constexpr int acoustic_min_waves(int N, int PREC) {
   return (N == 4 && PREC == 0) ? 6
          : ((N == 4 || N == 5) && PREC != 2) ? 5
          : (N == 6 && PREC == 0) ? 6
          : (N == 3 && PREC != 0) ? 3
-         : (N == 8 && PREC == 0) ? 3
          : 1;
 }
 
