@@ -341,6 +341,9 @@ def test_all_face_orientations_parity(physics, variant, N, periodic):
     ("elastic", 8, (9, 9, 9), "0", "1"), ("anisotropic", 7, (9, 9, 9), "1", "1"),
     ("anisotropic", 8, (9, 9, 9), "0", "1"),
     ("acoustic", 7, (11, 12, 12), "0", "1"), ("acoustic", 7, (11, 12, 12), "1", "1"),
+    # ragged last tile inside a split last round: 258 tiles (the last with 4
+    # elements) on 256 slots, and 515 tiles (the last with 8) on 512
+    ("elastic", 8, (7, 7, 14), "0", "1"), ("acoustic", 7, (7, 7, 28), "0", "1"),
 ])
 def test_mfma_short_last_round_parity(physics, N, dims, remap, split, monkeypatch):
     """Meshes whose 16-element tiles fill the MI355X's resident workgroups
